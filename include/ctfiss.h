@@ -1,0 +1,153 @@
+/*
+ * ctfiss.h -- C ABI of the MI355X (gfx950) CTF-MNMF-ISS separation library.
+ *
+ * Blind source separation by convolutive-transfer-function multichannel NMF
+ * (Xie et al., APSIPA ASC 2025).  Given the STFT of an M-channel mixture, the
+ * library minimises the negative log-likelihood of Eq. (5) over the
+ * per-bin extended demixing matrices W_f and the NMF source model
+ * lambda_{n,f,t} = sum_k b_{n,f,k} v_{n,k,t} (Sec. II, problem statement
+ * Eq. (6)), and returns the separated source images of Sec. III-B.
+ *
+ * Shapes and layouts (all device buffers are dense, row-major, caller-owned):
+ *   X  [M][F][T]       observed STFT, complex, interleaved (re, im)
+ *   W  [F][Mbar][Mbar] extended demixing matrices; row r of W_f holds w_r^H
+ *                      (Sec. II, demixing Eq. (4)), Mbar = M * D
+ *   B  [N][F][K]       NMF bases b_{n,f,k} (real)
+ *   V  [N][K][T]       NMF activations v_{n,k,t} (real)
+ *   C  [N][M][F][T]    source images (complex)
+ * Scalar type: precision CTFISS_FP32 uses complex64 / float32 for every
+ * buffer above, CTFISS_FP64 uses complex128 / float64.
+ *
+ * Rows of W: r = L_0 + ... + L_{n-1} + l is tap l of source n (source-major,
+ * tap-minor, the flattened index of Sec. III-A-1).  The observation may stack
+ * D delayed frames, xbar_{f,t}[d*M + m] = x_{m,f,t-d} (zero before the first
+ * frame); D = 1 is the paper's square model with sum_n L_n = M.
+ *
+ * Ownership: the caller allocates X, W, B, V, C and one device workspace of
+ * ctfiss_workspace_size() bytes (256-byte aligned).  The library allocates and
+ * frees no device memory; a context holds host metadata and pointers only.
+ * X must stay alive and unchanged while a context may read it.
+ *
+ * Errors and ordering: argument and shape errors are returned synchronously,
+ * before any HIP call.  Every other call enqueues work on the context's stream
+ * (hipStream_t passed as void*, NULL = the null stream) and returns without
+ * waiting, except where stated.  Numeric faults found on the device (a
+ * non-positive or non-finite ISS denominator, a singular IP system, a singular
+ * W_f in the output stage, a non-finite multiplicative update) are latched in
+ * a device status word and reported by ctfiss_sync_status().  No exceptions
+ * cross this interface.  One context per stream; calls on one context must
+ * not overlap from several host threads.
+ */
+#ifndef CTFISS_H
+#define CTFISS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes: 0 on success, negative on error. */
+#define CTFISS_OK 0
+#define CTFISS_E_ARG (-1)          /* null pointer, bad enum, negative count        */
+#define CTFISS_E_SHAPE (-2)        /* inconsistent shape, e.g. sum(taps) != M*D    */
+#define CTFISS_E_UNSUPPORTED (-3)  /* valid shape beyond this build's kernel limits */
+#define CTFISS_E_WORKSPACE (-4)    /* workspace too small or not 256-byte aligned  */
+#define CTFISS_E_ORDER (-5)        /* input or state not set before use            */
+#define CTFISS_E_HIP (-6)          /* a HIP runtime call failed                    */
+#define CTFISS_E_NUMERIC (-7)      /* a device numeric fault was latched           */
+
+/* Limits of this build (CTFISS_E_UNSUPPORTED beyond them). */
+#define CTFISS_MAX_ROWS 64         /* Mbar = M * D                                  */
+#define CTFISS_MAX_SOURCES 8       /* N                                             */
+#define CTFISS_MAX_BASES 64        /* K                                             */
+
+typedef enum { CTFISS_FP32 = 0, CTFISS_FP64 = 1 } ctfiss_precision;
+
+/* Demixing-matrix update: ISS rank-1 steering, Eqs. (11) and (16), or the
+ * iterative-projection baseline, Eqs. (9) and (10). */
+typedef enum { CTFISS_RULE_ISS = 0, CTFISS_RULE_IP = 1 } ctfiss_rule;
+
+/* Activation update: ALL_TAPS sums every tap of a source (the exact
+ * majorise-minimise step of Eq. (5)); PAPER_TAP0 is Eq. (18) as printed,
+ * tap 0 only.  Bases always follow Eq. (17). */
+typedef enum { CTFISS_VRULE_ALL_TAPS = 0, CTFISS_VRULE_PAPER_TAP0 = 1 } ctfiss_vrule;
+
+typedef struct {
+  int32_t F;            /* frequency bins                                */
+  int32_t T;            /* frames                                        */
+  int32_t M;            /* microphones                                   */
+  int32_t D;            /* stacked delayed frames (1 = paper's model)    */
+  int32_t N;            /* sources                                       */
+  int32_t K;            /* NMF bases per source                          */
+  const int32_t* taps;  /* host pointer, N entries L_n >= 1, sum = M * D */
+} ctfiss_shape;
+
+typedef struct ctfiss_ctx ctfiss_ctx;
+
+/* Bytes of device workspace a context of this shape and precision needs. */
+int ctfiss_workspace_size(const ctfiss_shape* shape, int precision, size_t* bytes);
+
+/* Create a context.  rule: ctfiss_rule; vrule: ctfiss_vrule; floor >= 0 is
+ * the lower clamp applied to b and v after every multiplicative update
+ * (0 = the printed update; 1e-8 is the recommended value).  workspace must
+ * hold ctfiss_workspace_size() bytes, 256-byte aligned; it belongs to the
+ * context until ctfiss_destroy().  stream: hipStream_t or NULL. */
+int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule, double floor,
+                  void* workspace, size_t workspace_bytes, void* stream, ctfiss_ctx** out);
+
+/* Bind the observation X [M][F][T] (device, complex of the context's precision). */
+int ctfiss_set_input(ctfiss_ctx* ctx, const void* X);
+
+/* Copy an initial state into the context (device-to-device on its stream).
+ * W [F][Mbar][Mbar] may be NULL for identity matrices (the paper's
+ * initialisation, Sec. V-A); B [N][F][K] and V [N][K][T] must be positive.
+ * Clears the device status word. */
+int ctfiss_set_state(ctfiss_ctx* ctx, const void* W, const void* B, const void* V);
+
+/* Enqueue n_iter >= 0 iterations.  One iteration is: W update for every row r
+ * in ascending order (ISS or IP), multiplicative update of b (Eq. (17)), of v
+ * (Eq. (18) or ALL_TAPS), each followed by the floor clamp, and the scale
+ * normalisation of Eqs. (19)-(21).  Requires set_input and set_state. */
+int ctfiss_iterate(ctfiss_ctx* ctx, int32_t n_iter);
+
+/* Copy the current state out (device-to-device on the context's stream).
+ * Any of W, B, V may be NULL to skip it. */
+int ctfiss_get_state(ctfiss_ctx* ctx, void* W, void* B, void* V);
+
+/* Source images C [N][M][F][T] of the current state: multichannel Wiener
+ * filter of Eq. (24), which with H_f = W_f^{-1} square reduces to
+ * c_{n,f,t} = sum_{l < L_n} H_f[:, (n,l)] y_{(n,l),f,t}; the M undelayed rows
+ * are returned.  The inverse and projection run in FP64 for both precisions. */
+int ctfiss_source_images(ctfiss_ctx* ctx, void* C);
+
+/* Negative log-likelihood of Eq. (5) (constant dropped) at the current state,
+ * written to *out.  Computed on the device in FP64; synchronises the stream. */
+int ctfiss_nll(ctfiss_ctx* ctx, double* out);
+
+/* Synchronise the stream and return CTFISS_E_NUMERIC if a device fault was
+ * latched since the last set_state, CTFISS_E_HIP on a HIP error, else 0.
+ * *fault_code (nullable) receives the raw device code (0 = none). */
+int ctfiss_sync_status(ctfiss_ctx* ctx, int32_t* fault_code);
+
+/* Release the context (does not touch the workspace or any device buffer). */
+int ctfiss_destroy(ctfiss_ctx* ctx);
+
+/* Static description of a status code. */
+const char* ctfiss_status_string(int status);
+
+/* Kernel timing: when enabled, ctfiss_iterate and ctfiss_source_images record
+ * HIP events around each kernel launch on the context's stream.
+ * ctfiss_kernel_stats synchronises and returns, for kernel class `which`
+ * (0 = W update [ISS or IP sweep kernel], 1 = activation partial sums,
+ * 2 = activation update and scale, 3 = final rescale, 4 = source images),
+ * the launches and summed milliseconds since profiling was enabled. */
+int ctfiss_set_profiling(ctfiss_ctx* ctx, int enable);
+int ctfiss_kernel_stats(ctfiss_ctx* ctx, int which, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTFISS_H */

@@ -1,0 +1,156 @@
+// Device-side building blocks shared by the CTF-MNMF kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ctfiss {
+
+constexpr int kMaxRows = 64;   // Mbar
+constexpr int kMaxSrc = 8;     // N
+constexpr int kMaxK = 64;      // K
+
+// Device fault codes latched in the status word (first one wins).
+enum Fault : int {
+  kFaultNone = 0,
+  kFaultIssDenominator = 1,  // ISS weighted power d_p not positive / not finite
+  kFaultIpSingular = 2,      // IP system (W Q_r) singular or u^H Q u not positive
+  kFaultMu = 3,              // multiplicative update produced a non-finite factor
+  kFaultOutSingular = 4,     // W_f singular in the source-image stage
+  kFaultScale = 5,           // zero or non-finite row power in the rescale
+};
+
+template <typename R>
+struct Cx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ Cx<R> cadd(Cx<R> a, Cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> csub(Cx<R> a, Cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename R>
+__device__ __forceinline__ Cx<R> cmulc(Cx<R> a, Cx<R> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+// acc + a * b
+template <typename R>
+__device__ __forceinline__ Cx<R> cfma(Cx<R> a, Cx<R> b, Cx<R> acc) {
+  return {acc.x + a.x * b.x - a.y * b.y, acc.y + a.x * b.y + a.y * b.x};
+}
+// acc - a * b
+template <typename R>
+__device__ __forceinline__ Cx<R> cfms(Cx<R> a, Cx<R> b, Cx<R> acc) {
+  return {acc.x - a.x * b.x + a.y * b.y, acc.y - a.x * b.y - a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ R cabs2(Cx<R> a) { return a.x * a.x + a.y * a.y; }
+
+// Row map of the extended demixing matrix: row r is tap tap[r] of source src[r].
+struct RowMap {
+  int Mb, N;
+  int r0[kMaxSrc];   // first row of each source
+  int L[kMaxSrc];    // taps per source
+  uint8_t src[kMaxRows];
+  uint8_t tap[kMaxRows];
+};
+
+// ------------------------------------------------------------------ reductions
+// Sum over aligned groups of G lanes (G = 16, 32 or 64); every lane of the
+// group receives the total.  Within 16 lanes the butterfly uses DPP
+// (quad_perm xor1, quad_perm xor2, row_half_mirror, row_mirror), across rows
+// the LDS crossbar (ds_swizzle / bpermute, no LDS memory traffic).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) { return dpp_f<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) { return dpp_d<CTRL>(v); }
+
+template <typename R>
+__device__ __forceinline__ R xor_lane(R v, int mask) { return __shfl_xor(v, mask, 64); }
+
+template <int G, typename R>
+__device__ __forceinline__ R group_sum(R v) {
+  static_assert(G == 16 || G == 32 || G == 64, "group size");
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  if constexpr (G >= 32) v += xor_lane(v, 16);
+  if constexpr (G >= 64) v += xor_lane(v, 32);
+  return v;
+}
+
+__device__ __forceinline__ void latch(int* status, int code) {
+  if (status) atomicCAS(status, 0, code);
+}
+
+template <typename R>
+__device__ __forceinline__ bool finite_pos(R v) {
+  return v > R(0) && isfinite(v);  // false for NaN, 0, negatives, +inf
+}
+
+// Largest workgroup the W-update kernels are compiled for.  The per-lane
+// footprint (y, phi and the broadcast y_r: 5 reals per frame, plus ~48
+// registers of addressing and scalars) sets the VGPRs a lane needs; a SIMD
+// has 512 per lane, so at most floor(512 / need) waves of the workgroup may
+// share it, i.e. 256 * that many threads (4 SIMDs per CU).
+__host__ __device__ constexpr int iter_max_threads(int rsize, int cpl) {
+  return (512 / (cpl * 5 * rsize / 4 + 48)) * 256 > 1024 ? 1024 : (512 / (cpl * 5 * rsize / 4 + 48)) * 256;
+}
+
+// ------------------------------------------------------------------ LDS layout
+// Per-bin on-chip layout of the W-update kernels.  Region A first holds the
+// observation block and the demixing matrix, and after the sweep the per-row
+// powers |y|^2 (the two uses never overlap in time).
+struct IterLds {
+  size_t x, w, a, lam, p, b, yb, wb, q, aug, u, fac, misc, total;
+};
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+__host__ __device__ inline IterLds iter_lds_layout(int M, int T, int Mb, int N, int K, int rsize, bool ip) {
+  IterLds L{};
+  const size_t cs = 2 * (size_t)rsize;
+  size_t xw = align_up((size_t)M * T * cs, 16) + align_up((size_t)Mb * Mb * cs, 16);
+  size_t aa = align_up((size_t)Mb * T * rsize, 16);
+  size_t off = 0;
+  L.x = off;
+  L.w = off + align_up((size_t)M * T * cs, 16);
+  L.a = off;
+  off += (xw > aa ? xw : aa);
+  L.lam = off; off += align_up((size_t)N * T * rsize, 16);
+  L.p = off; off += align_up((size_t)N * T * rsize, 16);
+  L.b = off; off += align_up((size_t)N * K * rsize, 16);
+  L.yb = off; off += align_up((size_t)2 * T * cs, 16);
+  L.wb = off; off += align_up((size_t)2 * Mb * cs, 16);
+  if (ip) {
+    L.q = off; off += align_up((size_t)Mb * Mb * cs, 16);
+    L.aug = off; off += align_up((size_t)Mb * (Mb + 1) * cs, 16);
+    L.u = off; off += align_up((size_t)Mb * cs, 16);
+    L.fac = off; off += align_up((size_t)(Mb + 1) * cs, 16);
+  } else {
+    L.q = L.aug = L.u = L.fac = 0;
+  }
+  L.misc = off; off += 64;
+  L.total = off;
+  return L;
+}
+
+}  // namespace ctfiss

@@ -1,0 +1,207 @@
+// Typed kernel launchers; included by exactly one translation unit per precision.
+#pragma once
+
+#include "iter_impl.hpp"
+#include "launch.hpp"
+#include "nmf_impl.hpp"
+#include "out_impl.hpp"
+
+namespace ctfiss {
+
+template <typename R>
+using WFn = void (*)(IterArgs<R>, IterLds);
+
+template <typename R, int G, int CPL>
+WFn<R> wfn(int rule) {
+  return rule == 0 ? &k_iss<R, G, CPL> : &k_ip<R, G, CPL>;
+}
+
+template <typename R, int G>
+WFn<R> pick_cpl(int rule, int cpl) {
+  if constexpr (sizeof(R) == 4) {
+    switch (cpl) {
+      case 4: return wfn<R, G, 4>(rule);
+      case 8: return wfn<R, G, 8>(rule);
+      case 12: return wfn<R, G, 12>(rule);
+      case 16: return wfn<R, G, 16>(rule);
+      case 20: return wfn<R, G, 20>(rule);
+      case 24: return wfn<R, G, 24>(rule);
+      case 28: return wfn<R, G, 28>(rule);
+      case 32: return wfn<R, G, 32>(rule);
+      default: return nullptr;
+    }
+  } else {
+    switch (cpl) {
+      case 4: return wfn<R, G, 4>(rule);
+      case 6: return wfn<R, G, 6>(rule);
+      case 8: return wfn<R, G, 8>(rule);
+      case 10: return wfn<R, G, 10>(rule);
+      case 12: return wfn<R, G, 12>(rule);
+      case 16: return wfn<R, G, 16>(rule);
+      default: return nullptr;
+    }
+  }
+}
+
+template <typename R>
+WFn<R> pick(int rule, int G, int cpl) {
+  if constexpr (sizeof(R) == 4) {
+    if (G == 16) return pick_cpl<R, 16>(rule, cpl);
+    if (G == 32) return pick_cpl<R, 32>(rule, cpl);
+  } else {
+    if (G == 16) return pick_cpl<R, 16>(rule, cpl);
+    if (G == 32) return pick_cpl<R, 32>(rule, cpl);
+    if (G == 64) return pick_cpl<R, 64>(rule, cpl);
+  }
+  return nullptr;
+}
+
+template <typename R>
+hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, double floor, bool apply_mu,
+                     hipStream_t s) {
+  WFn<R> fn = pick<R>(rule, p.G, p.CPL);
+  if (!fn) return hipErrorInvalidValue;
+  IterArgs<R> a;
+  a.X = static_cast<const Cx<R>*>(ptr.X);
+  a.W = static_cast<Cx<R>*>(ptr.W);
+  a.B = static_cast<R*>(ptr.B);
+  a.V = static_cast<const R*>(ptr.V);
+  a.P = static_cast<R*>(ptr.P);
+  a.P0 = static_cast<R*>(ptr.P0);
+  a.musq = static_cast<R*>(ptr.musq);
+  a.mu = apply_mu ? static_cast<const R*>(ptr.mu) : nullptr;
+  a.status = ptr.status;
+  a.F = d.F;
+  a.T = d.T;
+  a.M = d.M;
+  a.D = d.D;
+  a.K = d.K;
+  a.floor = (R)floor;
+  a.rm = d.rm;
+  const IterLds L = iter_lds_layout(d.M, d.T, d.Mb, d.N, d.K, (int)sizeof(R), rule != 0);
+  if (L.total > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(d.F), dim3(p.threads), L.total, s, a, L);
+  return hipGetLastError();
+}
+
+template <typename R>
+VArgs<R> make_vargs(const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0) {
+  VArgs<R> a;
+  a.B = static_cast<const R*>(ptr.B);
+  a.V = static_cast<R*>(ptr.V);
+  a.P = static_cast<const R*>(tap0 ? ptr.P0 : ptr.P);
+  a.vnum = static_cast<R*>(ptr.vnum);
+  a.vden = static_cast<R*>(ptr.vden);
+  a.musq = static_cast<const R*>(ptr.musq);
+  a.mu = static_cast<R*>(ptr.mu);
+  a.status = ptr.status;
+  a.F = d.F;
+  a.T = d.T;
+  a.K = d.K;
+  a.nch = vs.nch;
+  a.fchunk = vs.fchunk;
+  a.tap0 = tap0 ? 1 : 0;
+  a.floor = (R)floor;
+  a.rm = d.rm;
+  return a;
+}
+
+template <typename R>
+hipError_t vpart_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, bool tap0, hipStream_t s) {
+  VArgs<R> a = make_vargs<R>(d, vs, ptr, 0.0, tap0);
+  dim3 grid((d.T + kVTile - 1) / kVTile, vs.nch, d.N);
+  hipLaunchKernelGGL(k_vpart<R>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t vfinal_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0, hipStream_t s) {
+  VArgs<R> a = make_vargs<R>(d, vs, ptr, floor, tap0);
+  const int n = d.N * d.K * d.T;
+  dim3 grid((n + 255) / 256 + 1);
+  hipLaunchKernelGGL(k_vfinal<R>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t apply_mu_t(const Dims& d, const Ptrs& ptr, hipStream_t s) {
+  const size_t n = (size_t)d.F * d.Mb * d.Mb + (size_t)d.N * d.F * d.K;
+  hipLaunchKernelGGL(k_apply_mu<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     static_cast<Cx<R>*>(ptr.W), static_cast<R*>(ptr.B), static_cast<const R*>(ptr.mu), d.F, d.K,
+                     d.rm);
+  return hipGetLastError();
+}
+
+template <typename R>
+OutArgs<R> make_oargs(const Dims& d, const Ptrs& ptr, void* C) {
+  OutArgs<R> a;
+  a.X = static_cast<const Cx<R>*>(ptr.X);
+  a.W = static_cast<const Cx<R>*>(ptr.W);
+  a.B = static_cast<const R*>(ptr.B);
+  a.V = static_cast<const R*>(ptr.V);
+  a.C = static_cast<Cx<R>*>(C);
+  a.part = ptr.nllpart;
+  a.status = ptr.status;
+  a.F = d.F;
+  a.T = d.T;
+  a.M = d.M;
+  a.D = d.D;
+  a.K = d.K;
+  a.rm = d.rm;
+  return a;
+}
+
+template <typename R>
+hipError_t images_t(const Dims& d, const Ptrs& ptr, void* C, hipStream_t s) {
+  OutArgs<R> a = make_oargs<R>(d, ptr, C);
+  const size_t lds = out_lds_bytes(d.Mb, d.M, d.N);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_images<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_images<R>, dim3(d.F), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t nll_t(const Dims& d, const Ptrs& ptr, hipStream_t s) {
+  OutArgs<R> a = make_oargs<R>(d, ptr, nullptr);
+  const size_t lds = nll_lds_bytes(d.Mb);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_nll<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_nll<R>, dim3(d.F), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_identity(Cx<R>* W, int F, int Mb) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t n = (size_t)F * Mb * Mb;
+  if (i >= n) return;
+  const int c = (int)(i % Mb), r = (int)((i / Mb) % Mb);
+  W[i] = Cx<R>{R(r == c ? 1 : 0), R(0)};
+}
+
+template <typename R>
+hipError_t identity_t(const Dims& d, void* W, hipStream_t s) {
+  const size_t n = (size_t)d.F * d.Mb * d.Mb;
+  hipLaunchKernelGGL(k_identity<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, static_cast<Cx<R>*>(W), d.F,
+                     d.Mb);
+  return hipGetLastError();
+}
+
+#define CTFISS_INSTANTIATE(R)                                                                                  \
+  template hipError_t wupdate_t<R>(int, const Plan&, const Dims&, const Ptrs&, double, bool, hipStream_t);     \
+  template hipError_t vpart_t<R>(const Dims&, const VSplit&, const Ptrs&, bool, hipStream_t);                 \
+  template hipError_t vfinal_t<R>(const Dims&, const VSplit&, const Ptrs&, double, bool, hipStream_t);        \
+  template hipError_t apply_mu_t<R>(const Dims&, const Ptrs&, hipStream_t);                                  \
+  template hipError_t images_t<R>(const Dims&, const Ptrs&, void*, hipStream_t);                             \
+  template hipError_t nll_t<R>(const Dims&, const Ptrs&, hipStream_t);                                       \
+  template hipError_t identity_t<R>(const Dims&, void*, hipStream_t);
+
+}  // namespace ctfiss

@@ -1,0 +1,96 @@
+"""Tensor-level wrapper over the C ABI: one context, its workspace and bound buffers."""
+from __future__ import annotations
+
+import torch
+
+from . import binding as b
+
+_PREC = {"fp32": b.CTFISS_FP32, "fp64": b.CTFISS_FP64}
+_RULE = {"iss": b.CTFISS_RULE_ISS, "ip": b.CTFISS_RULE_IP}
+_VRULE = {"all_taps": b.CTFISS_VRULE_ALL_TAPS, "paper_tap0": b.CTFISS_VRULE_PAPER_TAP0}
+
+
+class Separator:
+    """CTF-MNMF separation of one mixture on one GPU.
+
+    X [M, F, T] complex (complex64 for fp32, complex128 for fp64) on the device;
+    W [F, Mbar, Mbar] complex, B [N, F, K] and V [N, K, T] real.  All work is
+    enqueued on `stream` (default: torch's current stream when the object is made).
+    """
+
+    def __init__(self, F, T, M, D, N, K, taps, precision="fp32", rule="iss", vrule="all_taps", floor=1e-8,
+                 device="cuda", stream=None):
+        self.F, self.T, self.M, self.D, self.N, self.K = int(F), int(T), int(M), int(D), int(N), int(K)
+        self.taps = tuple(int(x) for x in taps)
+        self.Mbar = self.M * self.D
+        self.precision = precision
+        self.rdtype = torch.float32 if precision == "fp32" else torch.float64
+        self.cdtype = torch.complex64 if precision == "fp32" else torch.complex128
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._shape = b.make_shape(F, T, M, D, N, K, self.taps)
+        nbytes = b.ctfiss_workspace_size(self._shape, _PREC[precision])
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace allocation is not 256-byte aligned")
+        self.ctx = b.ctfiss_create(self._shape, _PREC[precision], _RULE[rule], _VRULE[vrule], floor,
+                                   self.workspace, self.stream)
+        self._X = None
+
+    def _check(self, t, shape, dtype, name):
+        if t.device != self.device or t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)} on {self.device}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
+    def set_input(self, X: torch.Tensor) -> None:
+        self._check(X, (self.M, self.F, self.T), self.cdtype, "X")
+        self._X = X
+        b.ctfiss_set_input(self.ctx, X)
+
+    def set_state(self, B: torch.Tensor, V: torch.Tensor, W: torch.Tensor | None = None) -> None:
+        self._check(B, (self.N, self.F, self.K), self.rdtype, "B")
+        self._check(V, (self.N, self.K, self.T), self.rdtype, "V")
+        if W is not None:
+            self._check(W, (self.F, self.Mbar, self.Mbar), self.cdtype, "W")
+        b.ctfiss_set_state(self.ctx, W, B, V)
+
+    def iterate(self, n_iter: int) -> None:
+        b.ctfiss_iterate(self.ctx, n_iter)
+
+    def state(self):
+        W = torch.empty((self.F, self.Mbar, self.Mbar), dtype=self.cdtype, device=self.device)
+        B = torch.empty((self.N, self.F, self.K), dtype=self.rdtype, device=self.device)
+        V = torch.empty((self.N, self.K, self.T), dtype=self.rdtype, device=self.device)
+        b.ctfiss_get_state(self.ctx, W, B, V)
+        return W, B, V
+
+    def source_images(self) -> torch.Tensor:
+        C = torch.empty((self.N, self.M, self.F, self.T), dtype=self.cdtype, device=self.device)
+        b.ctfiss_source_images(self.ctx, C)
+        return C
+
+    def nll(self) -> float:
+        return b.ctfiss_nll(self.ctx)
+
+    def status(self) -> int:
+        """0 if no device fault was latched, else the device fault code (synchronises)."""
+        return b.ctfiss_sync_status(self.ctx)[1]
+
+    def set_profiling(self, enable: bool) -> None:
+        b.ctfiss_set_profiling(self.ctx, enable)
+
+    def kernel_stats(self, which: int):
+        return b.ctfiss_kernel_stats(self.ctx, which)
+
+    def close(self) -> None:
+        if self.ctx is not None:
+            b.ctfiss_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

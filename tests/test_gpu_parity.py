@@ -1,0 +1,271 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every input is seeded and synthetic; the oracle sees exactly the values the
+GPU sees (the FP32 path's inputs rounded to complex64/float32 first).
+
+Tolerances (relative Frobenius norm per output array):
+  * FP64 path, one iteration: 1e-11; 30 iterations: 1e-9.  Both sides are
+    FP64 and differ only in summation order (~1e-15 per reduction), which the
+    fixed-point dynamics amplify by at most ~10x per 10 iterations.
+  * FP32 path: 1e-4, the accuracy target for separated STFTs of the FP32
+    path.  One iteration accumulates O(Mbar + log T) roundings of 6e-8 each
+    (ISS steps and reductions), i.e. ~1e-6; 100 ISS iterations amplify that by
+    ~10x (a 1e-14 input perturbation of the c1 mixture grows to 2e-13).
+  * IP trajectories amplify rounding far more: the same 1e-14 perturbation
+    grows to 3e-7 after 100 IP iterations (~3e7x), so FP64 IP over 100
+    iterations is held to 1e-5, and FP32 IP is not numerically usable on the
+    stacked-frame workloads (it latches the singular-system fault).
+"""
+import numpy as np
+import pytest
+import torch
+
+from datagen import WORKLOADS, init_nmf, make_mixture, random_problem, rng_for
+from oracle import ctf_iss as o
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (F, T, M, D, taps, K)
+    "d1_tiny": (5, 37, 3, 1, (2, 1), 3),
+    "single_row": (3, 50, 1, 1, (1,), 2),
+    "ragged": (7, 100, 2, 3, (4, 2), 1),
+    "three_src": (4, 150, 4, 2, (3, 3, 2), 4),
+    "short_T": (4, 5, 2, 2, (2, 2), 2),
+    "c0_like": (9, 251, 3, 4, (6, 6), 10),
+    "c1_like": (6, 313, 3, 8, (12, 12), 20),
+    "p8_like": (5, 501, 8, 1, (4, 4), 3),
+    "max_rows": (3, 100, 4, 16, (22, 21, 21), 4),
+}
+
+TOL1 = {"fp32": 1e-4, "fp64": 1e-11}
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def as_device(x, precision):
+    if np.iscomplexobj(x):
+        dt = torch.complex64 if precision == "fp32" else torch.complex128
+    else:
+        dt = torch.float32 if precision == "fp32" else torch.float64
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dt).contiguous()
+
+
+def rounded(x, precision):
+    """The values the device holds, back in float64/complex128."""
+    if precision == "fp64":
+        return np.array(x)
+    return np.array(x).astype(np.complex64 if np.iscomplexobj(x) else np.float32).astype(
+        np.complex128 if np.iscomplexobj(x) else np.float64)
+
+
+def make_case(name, seed=0):
+    F, T, M, D, taps, K = CASES[name]
+    X, B0, V0 = random_problem(F, T, M, len(taps), K, seed, scale_spread=0.5)
+    rng = rng_for(seed + 3)
+    Mb = M * D
+    W0 = np.eye(Mb) + 0.2 * (rng.standard_normal((F, Mb, Mb)) + 1j * rng.standard_normal((F, Mb, Mb)))
+    return X, B0, V0, W0, D, taps
+
+
+def gpu_run(X, D, taps, B0, V0, W0, n_iter, precision, rule="iss", vrule="all_taps", floor=o.FLOOR,
+            images=True, splits=None):
+    from paper_2510_02382_amd import Separator
+    M, F, T = X.shape
+    K = B0.shape[-1]
+    sep = Separator(F, T, M, D, len(taps), K, taps, precision=precision, rule=rule, vrule=vrule, floor=floor)
+    Xd = as_device(X, precision)
+    sep.set_input(Xd)
+    sep.set_state(B=as_device(B0, precision), V=as_device(V0, precision),
+                  W=None if W0 is None else as_device(W0, precision))
+    for n in (splits or [n_iter]):
+        sep.iterate(n)
+    W, B, V = sep.state()
+    C = sep.source_images() if images else None
+    status = sep.status()
+    torch.cuda.synchronize()
+    out = dict(W=W.cpu().numpy(), B=B.cpu().numpy(), V=V.cpu().numpy(), status=status)
+    if images:
+        out["C"] = C.cpu().numpy()
+    sep.close()
+    return out
+
+
+def oracle_run(X, D, taps, B0, V0, W0, n_iter, precision, rule="iss", vrule="all_taps"):
+    Xr, Br, Vr = rounded(X, precision), rounded(B0, precision), rounded(V0, precision)
+    Wr = None if W0 is None else rounded(W0, precision)
+    rule_o = o.ISS if rule == "iss" else o.IP
+    vrule_o = o.ALL_TAPS if vrule == "all_taps" else o.PAPER_TAP0
+    W, B, V = o.run(Xr, D, taps, Br, Vr, n_iter, W0=Wr, rule=rule_o, vrule=vrule_o)
+    return dict(W=W, B=B, V=V, C=o.source_images(W, Xr, D, taps))
+
+
+# ------------------------------------------------------------------ one iteration, every case
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("rule", ["iss", "ip"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_one_iteration_matches_oracle(case, rule, precision):
+    X, B0, V0, W0, D, taps = make_case(case)
+    if case == "max_rows" and rule == "ip" and precision == "fp64":
+        # the per-bin IP working set (W, Q_r, [W Q_r | e_r] in FP64) exceeds one workgroup's LDS
+        from paper_2510_02382_amd import binding as b
+        with pytest.raises(b.CtfissError) as e:
+            gpu_run(X, D, taps, B0, V0, W0, 1, precision, rule)
+        assert e.value.status == b.CTFISS_E_UNSUPPORTED
+        return
+    g = gpu_run(X, D, taps, B0, V0, W0, 1, precision, rule)
+    r = oracle_run(X, D, taps, B0, V0, W0, 1, precision, rule)
+    assert g["status"] == 0
+    for k in ("W", "B", "V", "C"):
+        assert rel(g[k], r[k]) < TOL1[precision], (k, rel(g[k], r[k]))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", ["c0_like", "three_src", "ragged"])
+def test_paper_tap0_rule_matches_oracle(case, precision):
+    X, B0, V0, W0, D, taps = make_case(case, seed=4)
+    g = gpu_run(X, D, taps, B0, V0, W0, 2, precision, "iss", "paper_tap0")
+    r = oracle_run(X, D, taps, B0, V0, W0, 2, precision, "iss", "paper_tap0")
+    for k in ("W", "B", "V"):
+        assert rel(g[k], r[k]) < 10 * TOL1[precision], (k, rel(g[k], r[k]))
+
+
+def test_identity_initialisation_and_zero_iterations():
+    X, B0, V0, _, D, taps = make_case("c0_like", seed=2)
+    g = gpu_run(X, D, taps, B0, V0, None, 0, "fp64")
+    np.testing.assert_array_equal(g["W"], np.tile(np.eye(12), (9, 1, 1)))
+    np.testing.assert_array_equal(g["B"], B0)
+    r = o.source_images(np.tile(np.eye(12, dtype=complex), (9, 1, 1)), X, D, taps)
+    assert rel(g["C"], r) < 1e-13
+    g = gpu_run(X, D, taps, B0, V0, None, 3, "fp64")
+    r = oracle_run(X, D, taps, B0, V0, None, 3, "fp64")
+    for k in ("W", "B", "V", "C"):
+        assert rel(g[k], r[k]) < 1e-10, k
+
+
+# ------------------------------------------------------------------ trajectories on mixtures
+def mixture_slice(name, f0, nf, seed=0):
+    wl = WORKLOADS[name]
+    X = make_mixture(wl, seed).X[:, f0:f0 + nf, :]
+    B0, V0 = init_nmf(wl.N, nf, wl.K, wl.T, seed)
+    return X, B0, V0, wl
+
+
+def test_fp64_trajectory_c0_slice():
+    X, B0, V0, wl = mixture_slice("c0", 120, 16)
+    g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp64")
+    r = oracle_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp64")
+    assert g["status"] == 0
+    for k in ("W", "B", "V", "C"):
+        assert rel(g[k], r[k]) < 1e-9, (k, rel(g[k], r[k]))
+
+
+def test_fp32_iss_trajectory_c1_slice_100_iterations():
+    X, B0, V0, wl = mixture_slice("c1", 300, 12)
+    g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp32", "iss")
+    # the FP32 path is held to the FP64 oracle on the original (unrounded) data
+    W, B, V = o.run(X, wl.D, wl.row_taps, B0, V0, wl.n_iter, rule=o.ISS)
+    C = o.source_images(W, X, wl.D, wl.row_taps)
+    assert g["status"] == 0
+    for n in range(wl.N):
+        assert rel(g["C"][n], C[n]) < 1e-4, (n, rel(g["C"][n], C[n]))
+
+
+def test_fp64_ip_trajectory_c1_slice_100_iterations():
+    X, B0, V0, wl = mixture_slice("c1", 300, 12)
+    g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp64", "ip")
+    r = oracle_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp64", "ip")
+    assert g["status"] == 0
+    for k in ("W", "B", "V", "C"):
+        assert rel(g[k], r[k]) < 1e-5, (k, rel(g[k], r[k]))
+
+
+def test_fp32_ip_instability_is_reported_not_hidden():
+    """FP32 IP on the stacked-frame c1 mixture loses positivity of u^H Q u: the device
+    latches the singular-system fault instead of returning silently wrong filters."""
+    X, B0, V0, wl = mixture_slice("c1", 300, 12)
+    g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp32", "ip", images=False)
+    assert g["status"] == 2
+
+
+# ------------------------------------------------------------------ full size (bench workload)
+@pytest.fixture(scope="module")
+def c1_full():
+    wl = WORKLOADS["c1"]
+    X = make_mixture(wl, 0).X
+    B0, V0 = init_nmf(wl.N, wl.F, wl.K, wl.T, 0)
+    return X, B0, V0, wl
+
+
+def test_full_size_c1_two_iterations(c1_full):
+    X, B0, V0, wl = c1_full
+    g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, 2, "fp32")
+    r = oracle_run(X, wl.D, wl.row_taps, B0, V0, None, 2, "fp32")
+    assert g["status"] == 0
+    for k in ("W", "B", "V", "C"):
+        assert rel(g[k], r[k]) < TOL1["fp32"], (k, rel(g[k], r[k]))
+
+
+def test_full_size_c1_100_iterations_properties(c1_full):
+    """At the full workload the run stays finite and fault-free, every row of the final
+    demixed signals has unit mean power (the rescale), and the images sum to the mixture."""
+    X, B0, V0, wl = c1_full
+    g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp32")
+    assert g["status"] == 0
+    for k in ("W", "B", "V", "C"):
+        assert np.all(np.isfinite(g[k])), k
+    assert g["B"].min() >= np.float32(o.FLOOR) and g["V"].min() >= np.float32(o.FLOOR)
+    Xr = rounded(X, "fp32")
+    Y = o.demix(g["W"].astype(np.complex128), o.stacked_view(Xr, wl.D))
+    np.testing.assert_allclose(np.mean(np.abs(Y) ** 2, axis=(0, 2)), 1.0, rtol=1e-3)
+    assert rel(g["C"].sum(axis=0), Xr) < 1e-5
+
+
+# ------------------------------------------------------------------ objective, determinism, faults
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_nll_matches_oracle(precision):
+    from paper_2510_02382_amd import Separator
+    X, B0, V0, W0, D, taps = make_case("c0_like", seed=6)
+    M, F, T = X.shape
+    sep = Separator(F, T, M, D, len(taps), B0.shape[-1], taps, precision=precision)
+    sep.set_input(as_device(X, precision))
+    sep.set_state(B=as_device(B0, precision), V=as_device(V0, precision), W=as_device(W0, precision))
+    got = sep.nll()
+    ref = o.nll(rounded(W0, precision), o.stacked_view(rounded(X, precision), D), rounded(B0, precision),
+                rounded(V0, precision), taps)
+    assert abs(got - ref) <= (1e-12 if precision == "fp64" else 1e-6) * abs(ref)
+    sep.close()
+
+
+def test_bitwise_determinism_and_split_runs():
+    X, B0, V0, W0, D, taps = make_case("c1_like", seed=8)
+    a = gpu_run(X, D, taps, B0, V0, W0, 5, "fp32", images=False)
+    b = gpu_run(X, D, taps, B0, V0, W0, 5, "fp32", images=False)
+    c = gpu_run(X, D, taps, B0, V0, W0, 5, "fp32", images=False, splits=[3, 2])
+    for k in ("W", "B", "V"):
+        np.testing.assert_array_equal(a[k], b[k])
+        np.testing.assert_array_equal(a[k], c[k])
+
+
+def test_nan_input_latches_fault_status():
+    X, B0, V0, W0, D, taps = make_case("d1_tiny", seed=1)
+    X = X.copy()
+    X[0, 2, 5] = np.nan
+    g = gpu_run(X, D, taps, B0, V0, W0, 1, "fp32", images=False)
+    assert g["status"] != 0
+
+
+def test_call_order_is_checked():
+    from paper_2510_02382_amd import Separator
+    from paper_2510_02382_amd import binding as b
+    sep = Separator(4, 20, 2, 1, 2, 2, (1, 1))
+    with pytest.raises(b.CtfissError) as e:
+        sep.iterate(1)
+    assert e.value.status == b.CTFISS_E_ORDER
+    with pytest.raises(ValueError):
+        sep.set_input(torch.zeros((2, 4, 20), dtype=torch.complex128, device="cuda"))
+    sep.close()
