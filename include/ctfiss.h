@@ -141,8 +141,9 @@ const char* ctfiss_status_string(int status);
  * HIP events around each kernel launch on the context's stream.
  * ctfiss_kernel_stats synchronises and returns, for kernel class `which`
  * (0 = W update [ISS or IP sweep kernel], 1 = activation partial sums,
- * 2 = activation update and scale, 3 = final rescale, 4 = source images),
- * the launches and summed milliseconds since profiling was enabled. */
+ * 2 = activation update and scale, 3 = final rescale, 4 = source images,
+ * 5 = source-variance product lambda = b v, 6 = basis update), the launches
+ * and summed milliseconds since profiling was enabled. */
 int ctfiss_set_profiling(ctfiss_ctx* ctx, int enable);
 int ctfiss_kernel_stats(ctfiss_ctx* ctx, int which, int64_t* launches, double* total_ms);
 

@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -12,30 +14,59 @@
 
 namespace ctfiss {
 
-bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
-  (void)rule;
-  const int* gs = prec == 0 ? kG32 : kG64;
-  const int ng = prec == 0 ? (int)(sizeof(kG32) / sizeof(int)) : (int)(sizeof(kG64) / sizeof(int));
+// Candidate (G, RPL) orders per precision and rule; the first that fits wins.
+// For each, CPL is the smallest instantiated value with G * CPL >= T.
+namespace {
+struct GR {
+  int G, RPL;
+};
+constexpr GR kIss32[] = {{16, 1}, {32, 1}, {16, 2}, {32, 2}};
+constexpr GR kIss64[] = {{32, 1}, {64, 1}, {16, 1}, {16, 2}, {32, 2}};
+constexpr GR kIp32[] = {{16, 1}, {32, 1}};
+constexpr GR kIp64[] = {{32, 1}, {64, 1}, {16, 1}};
+
+bool plan_for(int prec, int rule, const Dims& d, size_t max_lds, int G, int RPL, int cpl_req, Plan* out) {
   const int* cpls = prec == 0 ? kCpl32 : kCpl64;
   const int ncpl = prec == 0 ? (int)(sizeof(kCpl32) / sizeof(int)) : (int)(sizeof(kCpl64) / sizeof(int));
-  const size_t lds = iter_lds_layout(d.M, d.T, d.Mb, d.N, d.K, prec == 0 ? 4 : 8, rule != 0).total;
-  if (lds > max_lds) return false;
-  for (int gi = 0; gi < ng; ++gi) {
-    const int G = gs[gi];
-    const int threads = (d.Mb * G + 63) / 64 * 64;
-    const int need = (d.T + G - 1) / G;
-    for (int ci = 0; ci < ncpl; ++ci) {
-      if (cpls[ci] >= need) {
-        if (threads > iter_max_threads(prec == 0 ? 4 : 8, cpls[ci])) break;
-        out->G = G;
-        out->CPL = cpls[ci];
-        out->threads = threads;
-        out->lds = lds;
-        return true;
-      }
-    }
+  const int rs = prec == 0 ? 4 : 8;
+  const int need = (d.T + G - 1) / G;
+  for (int ci = 0; ci < ncpl; ++ci) {
+    const int cpl = cpls[ci];
+    if (cpl < need || (cpl_req > 0 && cpl != cpl_req)) continue;
+    const int groups = (d.Mb + RPL - 1) / RPL;
+    const int threads = (groups * G + 63) / 64 * 64;
+    if (threads > iter_max_threads(rs, cpl, RPL)) return false;
+    const bool ok = prec == 0 ? have_wkernel<float>(rule, G, cpl, RPL) : have_wkernel<double>(rule, G, cpl, RPL);
+    if (!ok) return false;
+    const size_t lds = iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, G, cpl, rs, rule != 0).total;
+    if (lds > max_lds) return false;
+    *out = Plan{G, cpl, RPL, threads, lds};
+    return true;
   }
   return false;
+}
+}  // namespace
+
+bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
+  const GR* list;
+  int n;
+  if (rule == 0) {
+    list = prec == 0 ? kIss32 : kIss64;
+    n = prec == 0 ? (int)(sizeof(kIss32) / sizeof(GR)) : (int)(sizeof(kIss64) / sizeof(GR));
+  } else {
+    list = prec == 0 ? kIp32 : kIp64;
+    n = prec == 0 ? (int)(sizeof(kIp32) / sizeof(GR)) : (int)(sizeof(kIp64) / sizeof(GR));
+  }
+  for (int i = 0; i < n; ++i)
+    if (plan_for(prec, rule, d, max_lds, list[i].G, list[i].RPL, 0, out)) return true;
+  return false;
+}
+
+// "G,CPL,RPL" (used to tune launch shapes; CTFISS_PLAN in the environment).
+bool plan_from_string(const char* spec, int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
+  int G = 0, cpl = 0, rpl = 0;
+  if (!spec || std::sscanf(spec, "%d,%d,%d", &G, &cpl, &rpl) != 3) return false;
+  return plan_for(prec, rule, d, max_lds, G, rpl, cpl, out);
 }
 
 // Split of the bins for the activation partial sums: enough workgroups to
@@ -49,31 +80,6 @@ VSplit choose_vsplit(const Dims& d) {
   if (fchunk < 4) fchunk = 4;
   nch = (d.F + fchunk - 1) / fchunk;
   return VSplit{nch, fchunk};
-}
-
-hipError_t launch_wupdate(int prec, int rule, const Plan& p, const Dims& d, const Ptrs& ptr, double floor,
-                          bool apply_mu, hipStream_t s) {
-  return prec == 0 ? wupdate_t<float>(rule, p, d, ptr, floor, apply_mu, s)
-                   : wupdate_t<double>(rule, p, d, ptr, floor, apply_mu, s);
-}
-hipError_t launch_vpart(int prec, const Dims& d, const VSplit& vs, const Ptrs& ptr, bool tap0, hipStream_t s) {
-  return prec == 0 ? vpart_t<float>(d, vs, ptr, tap0, s) : vpart_t<double>(d, vs, ptr, tap0, s);
-}
-hipError_t launch_vfinal(int prec, const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0,
-                         hipStream_t s) {
-  return prec == 0 ? vfinal_t<float>(d, vs, ptr, floor, tap0, s) : vfinal_t<double>(d, vs, ptr, floor, tap0, s);
-}
-hipError_t launch_apply_mu(int prec, const Dims& d, const Ptrs& ptr, hipStream_t s) {
-  return prec == 0 ? apply_mu_t<float>(d, ptr, s) : apply_mu_t<double>(d, ptr, s);
-}
-hipError_t launch_images(int prec, const Dims& d, const Ptrs& ptr, void* C, hipStream_t s) {
-  return prec == 0 ? images_t<float>(d, ptr, C, s) : images_t<double>(d, ptr, C, s);
-}
-hipError_t launch_nll(int prec, const Dims& d, const Ptrs& ptr, hipStream_t s) {
-  return prec == 0 ? nll_t<float>(d, ptr, s) : nll_t<double>(d, ptr, s);
-}
-hipError_t launch_identity(int prec, const Dims& d, void* W, hipStream_t s) {
-  return prec == 0 ? identity_t<float>(d, W, s) : identity_t<double>(d, W, s);
 }
 
 __global__ void k_zero_status(int* status) {
@@ -93,10 +99,10 @@ using namespace ctfiss;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kClasses = 5;
+constexpr int kClasses = 7;
 
 struct Layout {
-  size_t W, B, V, P, P0, musq, mu, vnum, vden, nllpart, status, total;
+  size_t W, B, V, ilam, P, P0, musq, mu, vnum, vden, nllpart, status, total;
 };
 
 struct TimedLaunch {
@@ -129,8 +135,10 @@ int validate_shape(const ctfiss_shape* sh, int precision, Dims* d) {
   d->Mb = (int)mb;
   d->rm.Mb = (int)mb;
   d->rm.N = sh->N;
+  d->lmax = 0;
   int r = 0;
   for (int n = 0; n < sh->N; ++n) {
+    if (sh->taps[n] > d->lmax) d->lmax = sh->taps[n];
     d->rm.r0[n] = r;
     d->rm.L[n] = sh->taps[n];
     for (int l = 0; l < sh->taps[n]; ++l, ++r) {
@@ -154,6 +162,7 @@ Layout make_layout(const Dims& d, int precision) {
   L.W = take((size_t)d.F * d.Mb * d.Mb * cs);
   L.B = take((size_t)d.N * d.F * d.K * rs);
   L.V = take((size_t)d.N * d.K * d.T * rs);
+  L.ilam = take((size_t)d.N * d.F * d.T * rs);
   L.P = take((size_t)d.N * d.F * d.T * rs);
   L.P0 = take((size_t)d.N * d.F * d.T * rs);
   L.musq = take((size_t)d.F * d.Mb * rs);
@@ -257,7 +266,12 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return CTFISS_E_HIP;
   Plan plan;
-  if (!choose_plan(precision, rule, d, (size_t)max_lds, &plan)) return CTFISS_E_UNSUPPORTED;
+  const char* spec = std::getenv("CTFISS_PLAN");
+  if (spec && *spec) {
+    if (!plan_from_string(spec, precision, rule, d, (size_t)max_lds, &plan)) return CTFISS_E_UNSUPPORTED;
+  } else if (!choose_plan(precision, rule, d, (size_t)max_lds, &plan)) {
+    return CTFISS_E_UNSUPPORTED;
+  }
   if (images_lds(d) > (size_t)max_lds || nll_lds(d) > (size_t)max_lds) return CTFISS_E_UNSUPPORTED;
   ctfiss_ctx* c = new (std::nothrow) ctfiss_ctx();
   if (!c) return CTFISS_E_ARG;
@@ -275,6 +289,7 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   c->ptr.W = c->ws + lay.W;
   c->ptr.B = c->ws + lay.B;
   c->ptr.V = c->ws + lay.V;
+  c->ptr.ilam = c->ws + lay.ilam;
   c->ptr.P = c->ws + lay.P;
   c->ptr.P0 = vrule == CTFISS_VRULE_PAPER_TAP0 ? static_cast<void*>(c->ws + lay.P0) : nullptr;
   c->ptr.musq = c->ws + lay.musq;
@@ -312,7 +327,7 @@ int ctfiss_set_state(ctfiss_ctx* c, const void* W, const void* B, const void* V)
   if (W)
     e = hipMemcpyAsync(c->ptr.W, W, (size_t)d.F * d.Mb * d.Mb * 2 * rs, hipMemcpyDeviceToDevice, c->stream);
   else
-    e = launch_identity(c->prec, d, c->ptr.W, c->stream);
+    e = c->prec == CTFISS_FP32 ? identity_t<float>(d, c->ptr.W, c->stream) : identity_t<double>(d, c->ptr.W, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->ptr.B, B, (size_t)d.N * d.F * d.K * rs, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
@@ -327,18 +342,31 @@ int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
   if (!c || n_iter < 0) return CTFISS_E_ARG;
   if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
   const bool tap0 = c->vrule == CTFISS_VRULE_PAPER_TAP0;
+  const bool f32 = c->prec == CTFISS_FP32;
+  const Dims& d = c->d;
+  const Ptrs& p = c->ptr;
+  hipStream_t s = c->stream;
   for (int it = 0; it < n_iter; ++it) {
-    hipError_t e = timed(c, 0, [&] {
-      return launch_wupdate(c->prec, c->rule, c->plan, c->d, c->ptr, c->floor, it > 0, c->stream);
-    });
+    const bool mu = it > 0;  // the previous iteration's scale is still to be applied
+    hipError_t e = timed(c, 5, [&] { return f32 ? lambda_t<float>(d, p, mu, s) : lambda_t<double>(d, p, mu, s); });
     if (e == hipSuccess)
-      e = timed(c, 1, [&] { return launch_vpart(c->prec, c->d, c->vs, c->ptr, tap0, c->stream); });
+      e = timed(c, 0, [&] {
+        return f32 ? wupdate_t<float>(c->rule, c->plan, d, p, mu, s) : wupdate_t<double>(c->rule, c->plan, d, p, mu, s);
+      });
     if (e == hipSuccess)
-      e = timed(c, 2, [&] { return launch_vfinal(c->prec, c->d, c->vs, c->ptr, c->floor, tap0, c->stream); });
+      e = timed(c, 6, [&] {
+        return f32 ? nmfb_t<float>(d, p, c->floor, mu, s) : nmfb_t<double>(d, p, c->floor, mu, s);
+      });
+    if (e == hipSuccess)
+      e = timed(c, 1, [&] { return f32 ? vpart_t<float>(d, c->vs, p, tap0, s) : vpart_t<double>(d, c->vs, p, tap0, s); });
+    if (e == hipSuccess)
+      e = timed(c, 2, [&] {
+        return f32 ? vfinal_t<float>(d, c->vs, p, c->floor, tap0, s) : vfinal_t<double>(d, c->vs, p, c->floor, tap0, s);
+      });
     if (e != hipSuccess) return CTFISS_E_HIP;
   }
   if (n_iter > 0) {
-    hipError_t e = timed(c, 3, [&] { return launch_apply_mu(c->prec, c->d, c->ptr, c->stream); });
+    hipError_t e = timed(c, 3, [&] { return f32 ? apply_mu_t<float>(d, p, s) : apply_mu_t<double>(d, p, s); });
     if (e != hipSuccess) return CTFISS_E_HIP;
   }
   return CTFISS_OK;
@@ -361,7 +389,9 @@ int ctfiss_get_state(ctfiss_ctx* c, void* W, void* B, void* V) {
 int ctfiss_source_images(ctfiss_ctx* c, void* C) {
   if (!c || !C) return CTFISS_E_ARG;
   if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
-  hipError_t e = timed(c, 4, [&] { return launch_images(c->prec, c->d, c->ptr, C, c->stream); });
+  hipError_t e = timed(c, 4, [&] {
+    return c->prec == CTFISS_FP32 ? images_t<float>(c->d, c->ptr, C, c->stream) : images_t<double>(c->d, c->ptr, C, c->stream);
+  });
   return e == hipSuccess ? CTFISS_OK : CTFISS_E_HIP;
 }
 
@@ -369,7 +399,7 @@ int ctfiss_nll(ctfiss_ctx* c, double* out) {
   if (!c || !out) return CTFISS_E_ARG;
   if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
   std::vector<double> part((size_t)c->d.F);
-  hipError_t e = launch_nll(c->prec, c->d, c->ptr, c->stream);
+  hipError_t e = c->prec == CTFISS_FP32 ? nll_t<float>(c->d, c->ptr, c->stream) : nll_t<double>(c->d, c->ptr, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(part.data(), c->ptr.nllpart, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

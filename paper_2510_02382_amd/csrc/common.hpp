@@ -106,39 +106,43 @@ __device__ __forceinline__ bool finite_pos(R v) {
   return v > R(0) && isfinite(v);  // false for NaN, 0, negatives, +inf
 }
 
-// Largest workgroup the W-update kernels are compiled for.  The per-lane
-// footprint (y, phi and the broadcast y_r: 5 reals per frame, plus ~48
-// registers of addressing and scalars) sets the VGPRs a lane needs; a SIMD
-// has 512 per lane, so at most floor(512 / need) waves of the workgroup may
+// Largest workgroup the W-update kernels are compiled for.  A lane holds RPL
+// rows of CPL frames of y plus RPL rows of its W slice (2 reals per complex,
+// doubled for FP64) and ~40 registers of addressing and scalars; a SIMD has
+// 512 VGPRs per lane, so at most floor(512 / need) waves of the workgroup may
 // share it, i.e. 256 * that many threads (4 SIMDs per CU).
-__host__ __device__ constexpr int iter_max_threads(int rsize, int cpl) {
-  return (512 / (cpl * 5 * rsize / 4 + 48)) * 256 > 1024 ? 1024 : (512 / (cpl * 5 * rsize / 4 + 48)) * 256;
+__host__ __device__ constexpr int iter_need_vgprs(int rsize, int cpl, int rpl) {
+  return rpl * (2 * cpl + 8) * (rsize / 4) + 40;
+}
+__host__ __device__ constexpr int iter_max_threads(int rsize, int cpl, int rpl) {
+  return (512 / iter_need_vgprs(rsize, cpl, rpl)) * 256 > 1024 ? 1024
+                                                                : (512 / iter_need_vgprs(rsize, cpl, rpl)) * 256;
 }
 
 // ------------------------------------------------------------------ LDS layout
-// Per-bin on-chip layout of the W-update kernels.  Region A first holds the
-// observation block and the demixing matrix, and after the sweep the per-row
-// powers |y|^2 (the two uses never overlap in time).
+// Per-bin on-chip layout of the W-update kernels (TP = G * CPL padded frames).
 struct IterLds {
-  size_t x, w, a, lam, p, b, yb, wb, q, aug, u, fac, misc, total;
+  size_t x, w, phi, p, yb, wb, q, aug, u, fac, misc, total;
+  int lx, lp, tp, lmax;
 };
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-__host__ __device__ inline IterLds iter_lds_layout(int M, int T, int Mb, int N, int K, int rsize, bool ip) {
+__host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, int N, int lmax, int G, int cpl,
+                                                   int rsize, bool ip) {
   IterLds L{};
   const size_t cs = 2 * (size_t)rsize;
-  size_t xw = align_up((size_t)M * T * cs, 16) + align_up((size_t)Mb * Mb * cs, 16);
-  size_t aa = align_up((size_t)Mb * T * rsize, 16);
+  L.tp = G * cpl;
+  L.lx = D - 1 + L.tp;
+  L.lp = lmax - 1 + L.tp;
+  L.lmax = lmax;
+  (void)T;
   size_t off = 0;
-  L.x = off;
-  L.w = off + align_up((size_t)M * T * cs, 16);
-  L.a = off;
-  off += (xw > aa ? xw : aa);
-  L.lam = off; off += align_up((size_t)N * T * rsize, 16);
-  L.p = off; off += align_up((size_t)N * T * rsize, 16);
-  L.b = off; off += align_up((size_t)N * K * rsize, 16);
-  L.yb = off; off += align_up((size_t)2 * T * cs, 16);
+  L.x = off; off += align_up((size_t)M * L.lx * cs, 16);
+  L.w = off; off += align_up((size_t)Mb * Mb * cs, 16);
+  L.phi = off; off += align_up((size_t)N * L.lp * rsize, 16);
+  L.p = off; off += align_up((size_t)N * L.tp * rsize, 16);
+  L.yb = off; off += align_up((size_t)2 * L.tp * cs, 16);
   L.wb = off; off += align_up((size_t)2 * Mb * cs, 16);
   if (ip) {
     L.q = off; off += align_up((size_t)Mb * Mb * cs, 16);

@@ -1,22 +1,23 @@
 // W-update kernels of one CTF-MNMF iteration: one workgroup per frequency bin.
 //
 // Each workgroup
-//   1. applies the pending scale of the previous iteration to W_f and b_f
-//      (Eqs. (19)-(21)), forms the source variances lambda_{n,f,t} = b v
-//      and the stacked observation block on chip;
+//   1. applies the pending scale of the previous iteration to W_f (Eqs. (19)-(21)),
+//      stages the observation block (zero-padded so that stacked delayed frames
+//      need no bounds tests) and the inverse source variances 1/lambda_{n,f,t}
+//      (precomputed by k_lambda) in LDS;
 //   2. demixes, y = W_f xbar (Eq. (4)), into registers;
 //   3. runs the W update: the ISS sweep (Eqs. (11), (16)) or the IP sweep
 //      (Eqs. (9), (10));
-//   4. writes W_f, the tap-aligned powers P_{n,f,t'} = sum_l |y_{(n,l),f,t'+l}|^2,
-//      the row power sums used for the scale of Eq. (19), and the updated
-//      bases b_f of Eq. (17) (a T-long reduction per (n, k), done here while
-//      lambda and P of the bin are on chip).
+//   4. writes W_f, the tap-aligned powers P_{n,f,t'} = sum_l |y_{(n,l),f,t'+l}|^2
+//      (and the tap-0 power for the PAPER_TAP0 rule), and the row power sums
+//      used by the scale of Eq. (19).
 //
-// Register layout of the demixed signals: the block is split into groups of
-// G lanes; group g owns row p = g of Y_f and lane q of the group holds the
-// frames t = q + G*j, j < CPL.  A row's frame reductions are therefore
-// G-lane DPP butterflies, and each ISS step needs one LDS broadcast of y_r
-// and one barrier.
+// Register layout of the demixed signals: the workgroup is split into groups
+// of G lanes; group g owns rows p = g*RPL + i (i < RPL) and lane q of the group
+// holds frames t = q + G*j (j < CPL) of each.  Frame reductions are G-lane DPP
+// butterflies; each ISS step needs one LDS broadcast of y_r and one barrier.
+// The weight of row p = (n, l) at frame t is phi[n][t - l], read from the
+// per-source inverse-variance row in LDS (zero before the first frame).
 #pragma once
 
 #include "common.hpp"
@@ -25,30 +26,26 @@ namespace ctfiss {
 
 template <typename R>
 struct IterArgs {
-  const Cx<R>* X;  // [M][F][T] observation
-  Cx<R>* W;        // [F][Mb][Mb] demixing matrices (in/out)
-  R* B;            // [N][F][K] bases (in/out)
-  const R* V;      // [N][K][T] activations
-  R* P;            // [N][F][T] tap-aligned power (out)
-  R* P0;           // [N][F][T] tap-0 power (out, activation rule PAPER_TAP0) or null
-  R* musq;         // [F][Mb] row power sums (out)
-  const R* mu;     // [Mb] scale of the previous iteration still to apply, or null
+  const Cx<R>* X;   // [M][F][T] observation
+  Cx<R>* W;         // [F][Mb][Mb] demixing matrices (in/out)
+  const R* ilam;    // [N][F][T] 1 / lambda
+  R* P;             // [N][F][T] tap-aligned power (out)
+  R* P0;            // [N][F][T] tap-0 power (out, PAPER_TAP0) or null
+  R* musq;          // [Mb][F] row power sums (out)
+  const R* mu;      // [Mb] scale of the previous iteration still to apply to W, or null
   int* status;
   int F, T, M, D, K;
-  R floor;
   RowMap rm;
 };
 
 template <typename R>
 struct BinLds {
-  Cx<R>* x;    // [M][T]
+  Cx<R>* x;    // [M][LX]  x[m][D-1 + t] = X[m][f][t], zero elsewhere
   Cx<R>* w;    // [Mb][Mb]
-  R* a;        // [Mb][T] |y|^2 (aliases x, w after the sweep)
-  R* lam;      // [N][T]
-  R* p;        // [N][T]
-  R* b;        // [N][K]
-  Cx<R>* yb;   // [2][T] broadcast of y_r
-  Cx<R>* wb;   // [2][Mb] broadcast of w_r^H
+  R* phi;      // [N][LP]  phi[n][Lmax-1 + t] = 1/lambda_{n,f,t} for t < T, zero elsewhere
+  R* p;        // [N][TP]  tap-aligned power accumulator
+  Cx<R>* yb;   // [2][TP]  broadcast of y_r
+  Cx<R>* wb;   // [2][Mb]  broadcast of w_r^H
   Cx<R>* q;    // [Mb][Mb]  (IP)
   Cx<R>* aug;  // [Mb][Mb+1] (IP)
   Cx<R>* u;    // [Mb] (IP)
@@ -61,10 +58,8 @@ __device__ __forceinline__ BinLds<R> carve(unsigned char* base, const IterLds& L
   BinLds<R> s;
   s.x = reinterpret_cast<Cx<R>*>(base + L.x);
   s.w = reinterpret_cast<Cx<R>*>(base + L.w);
-  s.a = reinterpret_cast<R*>(base + L.a);
-  s.lam = reinterpret_cast<R*>(base + L.lam);
+  s.phi = reinterpret_cast<R*>(base + L.phi);
   s.p = reinterpret_cast<R*>(base + L.p);
-  s.b = reinterpret_cast<R*>(base + L.b);
   s.yb = reinterpret_cast<Cx<R>*>(base + L.yb);
   s.wb = reinterpret_cast<Cx<R>*>(base + L.wb);
   s.q = reinterpret_cast<Cx<R>*>(base + L.q);
@@ -75,20 +70,19 @@ __device__ __forceinline__ BinLds<R> carve(unsigned char* base, const IterLds& L
   return s;
 }
 
-// Stage 1: scaled b_f and W_f, the observation block and lambda into LDS.
+// Fast reciprocal / reciprocal square root: hardware v_rcp / v_rsq (1 ulp) in
+// FP32, IEEE division and square root in FP64.
+__device__ __forceinline__ float fast_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double fast_rcp(double v) { return 1.0 / v; }
+__device__ __forceinline__ float fast_rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double fast_rsqrt(double v) { return 1.0 / sqrt(v); }
+
+// Stage 1: scaled W_f, zero-padded observation block and inverse variances into LDS.
 template <typename R>
-__device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, int f) {
+__device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f) {
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int T = a.T, M = a.M, K = a.K, F = a.F, Mb = a.rm.Mb, N = a.rm.N;
-  for (int i = tid; i < N * K; i += nthr) {
-    const int n = i / K, k = i - n * K;
-    R b = a.B[((size_t)n * F + f) * K + k];
-    if (a.mu) {
-      const R m = a.mu[a.rm.r0[n]];
-      b = b / (m * m);
-    }
-    s.b[i] = b;
-  }
+  const int T = a.T, M = a.M, F = a.F, Mb = a.rm.Mb, N = a.rm.N;
+  const int LX = L.lx, LP = L.lp, TP = L.tp, Dm1 = a.D - 1, Lm1 = L.lmax - 1;
   const Cx<R>* Wf = a.W + (size_t)f * Mb * Mb;
   for (int i = tid; i < Mb * Mb; i += nthr) {
     Cx<R> w = Wf[i];
@@ -99,201 +93,215 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, int f) {
     }
     s.w[i] = w;
   }
-  for (int i = tid; i < M * T; i += nthr) {
-    const int m = i / T, t = i - m * T;
-    s.x[i] = a.X[((size_t)m * F + f) * T + t];
+  for (int i = tid; i < M * LX; i += nthr) {
+    const int m = i / LX, t = i - m * LX - Dm1;
+    s.x[i] = (t >= 0 && t < T) ? a.X[((size_t)m * F + f) * T + t] : Cx<R>{R(0), R(0)};
   }
-  __syncthreads();
-  for (int i = tid; i < N * T; i += nthr) {
-    const int n = i / T, t = i - n * T;
-    const R* Vn = a.V + (size_t)n * K * T + t;
-    R acc = 0;
-    for (int k = 0; k < K; ++k) acc += s.b[n * K + k] * Vn[(size_t)k * T];
-    s.lam[i] = acc;
+  for (int i = tid; i < N * LP; i += nthr) {
+    const int n = i / LP, t = i - n * LP - Lm1;
+    s.phi[i] = (t >= 0 && t < T) ? a.ilam[((size_t)n * F + f) * T + t] : R(0);
   }
+  for (int i = tid; i < N * TP; i += nthr) s.p[i] = R(0);
+  for (int i = tid; i < 2 * TP; i += nthr) s.yb[i] = Cx<R>{R(0), R(0)};
   __syncthreads();
 }
 
-// Stage 2: y_p[t] = sum_c W[p][c] xbar_c[t] for the lane's frames, and the
-// row weights phi_p[t] = 1 / lambda_{n(p), t - l(p)} (0 for t < l(p)).
-template <typename R, int G, int CPL>
-__device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>& s, int p, int q,
-                                           Cx<R> (&y)[CPL], R (&ph)[CPL]) {
-  const int T = a.T, M = a.M, D = a.D, Mb = a.rm.Mb;
+// Stage 2: y_p[t] = sum_c W[p][c] xbar_c[t] for the lane's rows and frames.
+template <typename R, int G, int CPL, int RPL>
+__device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int g,
+                                           int q, Cx<R> (&y)[RPL][CPL]) {
+  const int M = a.M, D = a.D, Mb = a.rm.Mb, LX = L.lx, Dm1 = D - 1;
 #pragma unroll
-  for (int j = 0; j < CPL; ++j) y[j] = Cx<R>{R(0), R(0)};
-  const Cx<R>* wrow = s.w + p * Mb;
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) y[i][j] = Cx<R>{R(0), R(0)};
   for (int d = 0; d < D; ++d) {
     for (int m = 0; m < M; ++m) {
-      const Cx<R> w = wrow[d * M + m];
-      const Cx<R>* xm = s.x + m * T;
+      const int c = d * M + m;
+      Cx<R> w[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int p = g * RPL + i;
+        w[i] = p < Mb ? s.w[p * Mb + c] : Cx<R>{R(0), R(0)};
+      }
+      const Cx<R>* xm = s.x + m * LX + Dm1 - d + q;
 #pragma unroll
       for (int j = 0; j < CPL; ++j) {
-        const int t = q + G * j;
-        if (t >= d && t < T) y[j] = cfma(w, xm[t - d], y[j]);
+        const Cx<R> xv = xm[G * j];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) y[i][j] = cfma(w[i], xv, y[i][j]);
       }
     }
   }
-  const int n = a.rm.src[p], l = a.rm.tap[p];
+  // Padded frames t >= T: a delayed block still reads real frames there
+  // (x[t - d] with t - d < T), so clear them; the rank-1 updates keep them zero
+  // and they add nothing to the frame sums.
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
-    const int t = q + G * j;
-    ph[j] = (t >= l && t < T) ? R(1) / s.lam[n * T + (t - l)] : R(0);
+    if (q + G * j >= a.T) {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) y[i][j] = Cx<R>{R(0), R(0)};
+    }
   }
 }
 
-// Stage 4: W_f out, |y|^2 -> LDS, row powers, tap-aligned powers, bases.
-template <typename R, int G, int CPL>
-__device__ void epilogue(const IterArgs<R>& a, const BinLds<R>& s, int f, int g, int q, const Cx<R> (&y)[CPL]) {
-  const int T = a.T, Mb = a.rm.Mb, N = a.rm.N, K = a.K, F = a.F;
+// Stage 4: |y|^2 row sums, tap-aligned powers accumulated tap by tap (a fixed
+// order, so results are bitwise reproducible), P / P0 out.
+template <typename R, int G, int CPL, int RPL>
+__device__ void epilogue(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int g, int q,
+                         const Cx<R> (&y)[RPL][CPL]) {
+  const int T = a.T, Mb = a.rm.Mb, N = a.rm.N, F = a.F, TP = L.tp;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  __syncthreads();  // every read of the x / w region is over before |y|^2 overwrites it
-  if (g < Mb) {
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int p = g * RPL + i;
     R rs = 0;
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      const int t = q + G * j;
-      if (t < T) {
-        const R v = cabs2(y[j]);
-        s.a[g * T + t] = v;
-        rs += v;
+    for (int j = 0; j < CPL; ++j) rs += cabs2(y[i][j]);
+    rs = group_sum<G>(rs);
+    if (p < Mb && q == 0) a.musq[(size_t)p * F + f] = rs;
+  }
+  for (int l = 0; l < L.lmax; ++l) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int p = g * RPL + i;
+      if (p < Mb && a.rm.tap[p] == l) {
+        R* pn = s.p + a.rm.src[p] * TP - l;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+          const int t = q + G * j;
+          if (t >= l) pn[t] += cabs2(y[i][j]);
+        }
+        if (l == 0 && a.P0) {
+          R* p0 = a.P0 + ((size_t)a.rm.src[p] * F + f) * T;
+#pragma unroll
+          for (int j = 0; j < CPL; ++j) {
+            const int t = q + G * j;
+            if (t < T) p0[t] = cabs2(y[i][j]);
+          }
+        }
       }
     }
-    rs = group_sum<G>(rs);
-    if (q == 0) a.musq[(size_t)f * Mb + g] = rs;
+    __syncthreads();
   }
-  __syncthreads();
   for (int i = tid; i < N * T; i += nthr) {
     const int n = i / T, t = i - n * T;
-    const int r0 = a.rm.r0[n], L = a.rm.L[n];
-    R acc = 0;
-    for (int l = 0; l < L && t + l < T; ++l) acc += s.a[(r0 + l) * T + t + l];
-    s.p[i] = acc;
-    a.P[((size_t)n * F + f) * T + t] = acc;
-    if (a.P0) a.P0[((size_t)n * F + f) * T + t] = s.a[r0 * T + t];
-  }
-  __syncthreads();
-  // Eq. (17) with t' = t - l: num = sum_t' P v / lambda^2, den = sum_t' C v / lambda,
-  // C_{n,t'} = #{l < L_n : t' + l < T}.  One (n, k) pair per group.
-  const int ngroups = nthr / G;
-  for (int nk = tid / G; nk < N * K; nk += ngroups) {
-    const int n = nk / K, k = nk - n * K;
-    const R* Vk = a.V + ((size_t)n * K + k) * T;
-    const int L = a.rm.L[n];
-    R num = 0, den = 0;
-    for (int t = q; t < T; t += G) {
-      const R il = R(1) / s.lam[n * T + t];
-      const R v = Vk[t];
-      const R c = (R)min(L, T - t);
-      num += s.p[n * T + t] * v * il * il;
-      den += c * v * il;
-    }
-    num = group_sum<G>(num);
-    den = group_sum<G>(den);
-    if (q == 0) {
-      R bn = s.b[nk] * sqrt(num / den);
-      if (!isfinite(bn)) latch(a.status, kFaultMu);
-      bn = bn > a.floor ? bn : a.floor;
-      a.B[((size_t)n * F + f) * K + k] = bn;
-    }
+    a.P[((size_t)n * F + f) * T + t] = s.p[n * TP + t];
   }
 }
 
 // ------------------------------------------------------------------ ISS
-template <typename R, int G, int CPL>
-__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL)) k_iss(IterArgs<R> a, IterLds L) {
+template <typename R, int G, int CPL, int RPL>
+__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(IterArgs<R> a, IterLds L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
   const int f = blockIdx.x, tid = threadIdx.x;
   const int g = tid / G, q = tid - g * G;
-  const int T = a.T, Mb = a.rm.Mb;
+  const int T = a.T, Mb = a.rm.Mb, TP = L.tp, LP = L.lp, Lm1 = L.lmax - 1;
   constexpr int WPL = (kMaxRows + G - 1) / G;
 
-  load_bin(a, s, f);
+  load_bin(a, s, L, f);
 
-  Cx<R> y[CPL];
-  R ph[CPL];
-  Cx<R> wreg[WPL];
-  const bool active = g < Mb;
-  if (active) {
-    demix_lane<R, G, CPL>(a, s, g, q, y, ph);
+  Cx<R> y[RPL][CPL];
+  demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y);
+
+  Cx<R> wreg[RPL][WPL];
+  const R* phr[RPL];  // weight row of each owned row, pre-shifted by its tap
 #pragma unroll
-    for (int i = 0; i < WPL; ++i) {
-      const int c = q + G * i;
-      wreg[i] = c < Mb ? s.w[g * Mb + c] : Cx<R>{R(0), R(0)};
+  for (int i = 0; i < RPL; ++i) {
+    const int p = g * RPL + i;
+    const bool ok = p < Mb;
+    phr[i] = s.phi + (ok ? a.rm.src[p] * LP + Lm1 - a.rm.tap[p] : 0) + q;
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+      const int c = q + G * k;
+      wreg[i][k] = (ok && c < Mb) ? s.w[p * Mb + c] : Cx<R>{R(0), R(0)};
     }
-  } else {
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      y[j] = Cx<R>{R(0), R(0)};
-      ph[j] = R(0);
-    }
-#pragma unroll
-    for (int i = 0; i < WPL; ++i) wreg[i] = Cx<R>{R(0), R(0)};
   }
 
-  // ISS sweep: for each r, a_p = sum_t phi_p y_p conj(y_r), d_p = sum_t phi_p |y_r|^2
+  // ISS sweep over r: a_p = sum_t phi_p y_p conj(y_r), d_p = sum_t phi_p |y_r|^2
   // (the common 1/T cancels in a_p / d_p), z_p = a_p / d_p, z_r = 1 - (d_r / T)^{-1/2};
   // then y_p -= z_p y_r and W[p, :] -= z_p W[r, :] with the pre-update row r.
   const R invT = R(1) / R(T);
   for (int r = 0; r < Mb; ++r) {
-    Cx<R>* yb = s.yb + (r & 1) * T;
+    Cx<R>* yb = s.yb + (r & 1) * TP;
     Cx<R>* wb = s.wb + (r & 1) * Mb;
-    if (g == r) {
+    if (g == r / RPL) {
+      const int io = r - g * RPL;
 #pragma unroll
-      for (int j = 0; j < CPL; ++j) {
-        const int t = q + G * j;
-        if (t < T) yb[t] = y[j];
-      }
+      for (int i = 0; i < RPL; ++i) {
+        if (i == io) {
 #pragma unroll
-      for (int i = 0; i < WPL; ++i) {
-        const int c = q + G * i;
-        if (c < Mb) wb[c] = wreg[i];
+          for (int j = 0; j < CPL; ++j) yb[q + G * j] = y[i][j];
+#pragma unroll
+          for (int k = 0; k < WPL; ++k) {
+            const int c = q + G * k;
+            if (c < Mb) wb[c] = wreg[i][k];
+          }
+        }
       }
     }
     __syncthreads();
-    if (active) {
-      Cx<R> yr[CPL];
-      R ar = 0, ai = 0, dd = 0;
+    R ar[RPL], ai[RPL], dd[RPL];
 #pragma unroll
-      for (int j = 0; j < CPL; ++j) {
-        const int t = q + G * j;
-        yr[j] = t < T ? yb[t] : Cx<R>{R(0), R(0)};
-        const Cx<R> sv = cmulc(y[j], yr[j]);
-        ar += ph[j] * sv.x;
-        ai += ph[j] * sv.y;
-        dd += ph[j] * cabs2(yr[j]);
+    for (int i = 0; i < RPL; ++i) ar[i] = ai[i] = dd[i] = R(0);
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const Cx<R> yr = yb[q + G * j];
+      const R pr = cabs2(yr);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const R ph = phr[i][G * j];
+        const Cx<R> sv = cmulc(y[i][j], yr);
+        ar[i] += ph * sv.x;
+        ai[i] += ph * sv.y;
+        dd[i] += ph * pr;
       }
-      ar = group_sum<G>(ar);
-      ai = group_sum<G>(ai);
-      dd = group_sum<G>(dd);
-      Cx<R> z;
-      if (g == r) {
-        const R dr = dd * invT;
+    }
+    Cx<R> z[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      ar[i] = group_sum<G>(ar[i]);
+      ai[i] = group_sum<G>(ai[i]);
+      dd[i] = group_sum<G>(dd[i]);
+      const int p = g * RPL + i;
+      if (p == r) {
+        const R dr = dd[i] * invT;
         if (!finite_pos(dr)) latch(a.status, kFaultIssDenominator);
-        z = Cx<R>{R(1) - R(1) / sqrt(dr), R(0)};
+        z[i] = Cx<R>{R(1) - fast_rsqrt(dr), R(0)};
       } else {
-        if (!finite_pos(dd)) latch(a.status, kFaultIssDenominator);
-        z = Cx<R>{ar / dd, ai / dd};
+        if (p < Mb && !finite_pos(dd[i])) latch(a.status, kFaultIssDenominator);
+        const R inv = fast_rcp(dd[i]);
+        z[i] = Cx<R>{ar[i] * inv, ai[i] * inv};
       }
+    }
 #pragma unroll
-      for (int j = 0; j < CPL; ++j) y[j] = cfms(z, yr[j], y[j]);
+    for (int j = 0; j < CPL; ++j) {
+      const Cx<R> yr = yb[q + G * j];
 #pragma unroll
-      for (int i = 0; i < WPL; ++i) {
-        const int c = q + G * i;
-        if (c < Mb) wreg[i] = cfms(z, wb[c], wreg[i]);
+      for (int i = 0; i < RPL; ++i) y[i][j] = cfms(z[i], yr, y[i][j]);
+    }
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+      const int c = q + G * k;
+      if (c < Mb) {
+        const Cx<R> wr = wb[c];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) wreg[i][k] = cfms(z[i], wr, wreg[i][k]);
       }
     }
   }
 
-  if (active) {
 #pragma unroll
-    for (int i = 0; i < WPL; ++i) {
-      const int c = q + G * i;
-      if (c < Mb) a.W[((size_t)f * Mb + g) * Mb + c] = wreg[i];
+  for (int i = 0; i < RPL; ++i) {
+    const int p = g * RPL + i;
+#pragma unroll
+    for (int k = 0; k < WPL; ++k) {
+      const int c = q + G * k;
+      if (p < Mb && c < Mb) a.W[((size_t)f * Mb + p) * Mb + c] = wreg[i][k];
     }
   }
-  epilogue<R, G, CPL>(a, s, f, g, q, y);
+  epilogue<R, G, CPL, RPL>(a, s, L, f, g, q, y);
 }
 
 // ------------------------------------------------------------------ IP
@@ -350,36 +358,32 @@ __device__ void solve_augmented(Cx<R>* A, Cx<R>* u, Cx<R>* fac, int* misc, int n
   __syncthreads();
 }
 
-template <typename R, int G, int CPL>
-__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL)) k_ip(IterArgs<R> a, IterLds L) {
+template <typename R, int G, int CPL, int RPL>
+__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_ip(IterArgs<R> a, IterLds L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
   const int f = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
   const int g = tid / G, q = tid - g * G;
-  const int T = a.T, M = a.M, Mb = a.rm.Mb;
+  const int T = a.T, M = a.M, Mb = a.rm.Mb, LX = L.lx, LP = L.lp, Dm1 = a.D - 1, Lm1 = L.lmax - 1;
   const R invT = R(1) / R(T);
 
-  load_bin(a, s, f);
+  load_bin(a, s, L, f);
 
   for (int r = 0; r < Mb; ++r) {
     const int n = a.rm.src[r], l = a.rm.tap[r];
-    // weights of row r (s.p is free until the epilogue)
-    for (int t = tid; t < T; t += nthr) s.p[t] = t >= l ? R(1) / s.lam[n * T + (t - l)] : R(0);
-    __syncthreads();
+    const R* phr = s.phi + n * LP + Lm1 - l;  // phr[t] = 1/lambda_{n, t - l}, 0 for t < l
     // Q_r = (1/T) sum_t phi_r xbar xbar^H, Eq. (8): upper triangle, mirrored.
     for (int e = tid; e < Mb * Mb; e += nthr) {
       const int i = e / Mb, j = e - (e / Mb) * Mb;
       if (i > j) continue;
       const int di = i / M, mi = i - di * M, dj = j / M, mj = j - dj * M;
-      int t0 = di > dj ? di : dj;
-      t0 = t0 > l ? t0 : l;
+      const Cx<R>* xi = s.x + mi * LX + Dm1 - di;
+      const Cx<R>* xj = s.x + mj * LX + Dm1 - dj;
       R accx = 0, accy = 0;
-      const Cx<R>* xi = s.x + mi * T - di;
-      const Cx<R>* xj = s.x + mj * T - dj;
-      for (int t = t0; t < T; ++t) {
+      for (int t = l; t < T; ++t) {
         const Cx<R> pr = cmulc(xi[t], xj[t]);
-        accx += s.p[t] * pr.x;
-        accy += s.p[t] * pr.y;
+        accx += phr[t] * pr.x;
+        accy += phr[t] * pr.y;
       }
       s.q[i * Mb + j] = Cx<R>{accx * invT, accy * invT};
       if (i != j) s.q[j * Mb + i] = Cx<R>{accx * invT, -accy * invT};
@@ -417,15 +421,9 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL)) k_ip(IterArg
 
   // W_f out, then y = W xbar of the final W for the shared epilogue.
   for (int i = tid; i < Mb * Mb; i += nthr) a.W[(size_t)f * Mb * Mb + i] = s.w[i];
-  Cx<R> y[CPL];
-  R ph[CPL];
-  if (g < Mb) {
-    demix_lane<R, G, CPL>(a, s, g, q, y, ph);
-  } else {
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) y[j] = Cx<R>{R(0), R(0)};
-  }
-  epilogue<R, G, CPL>(a, s, f, g, q, y);
+  Cx<R> y[RPL][CPL];
+  demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y);
+  epilogue<R, G, CPL, RPL>(a, s, L, f, g, q, y);
 }
 
 }  // namespace ctfiss

@@ -8,13 +8,14 @@
 namespace ctfiss {
 
 struct Dims {
-  int F, T, M, D, N, K, Mb;
+  int F, T, M, D, N, K, Mb, lmax;
   RowMap rm;
 };
 
-// Launch shape of the W-update kernels: groups of G lanes, CPL frames per lane.
+// Launch shape of the W-update kernels: groups of G lanes, CPL frames per lane,
+// RPL rows per lane.
 struct Plan {
-  int G, CPL, threads;
+  int G, CPL, RPL, threads;
   size_t lds;
 };
 
@@ -24,6 +25,7 @@ struct Ptrs {
   void* W;
   void* B;
   void* V;
+  void* ilam;
   void* P;
   void* P0;
   void* musq;
@@ -38,20 +40,21 @@ struct VSplit {
   int nch, fchunk;
 };
 
-// Group sizes G and frames per lane CPL instantiated for each precision.
-constexpr int kG32[] = {16, 32};
+// Instantiated launch shapes.
 constexpr int kCpl32[] = {4, 8, 12, 16, 20, 24, 28, 32};
-constexpr int kG64[] = {32, 64, 16};
 constexpr int kCpl64[] = {4, 6, 8, 10, 12, 16};
 
 bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out);
+bool plan_from_string(const char* spec, int prec, int rule, const Dims& d, size_t max_lds, Plan* out);
 VSplit choose_vsplit(const Dims& d);
 
-// Kernel launchers (prec 0 = FP32, 1 = FP64).  All are asynchronous on s.
 // Typed launchers, defined once per precision.
 template <typename R>
-hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, double floor, bool apply_mu,
-                     hipStream_t s);
+hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s);
+template <typename R>
+hipError_t lambda_t(const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s);
+template <typename R>
+hipError_t nmfb_t(const Dims& d, const Ptrs& ptr, double floor, bool apply_mu, hipStream_t s);
 template <typename R>
 hipError_t vpart_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, bool tap0, hipStream_t s);
 template <typename R>
@@ -64,16 +67,9 @@ template <typename R>
 hipError_t nll_t(const Dims& d, const Ptrs& ptr, hipStream_t s);
 template <typename R>
 hipError_t identity_t(const Dims& d, void* W, hipStream_t s);
+template <typename R>
+bool have_wkernel(int rule, int G, int cpl, int rpl);
 
-hipError_t launch_wupdate(int prec, int rule, const Plan& p, const Dims& d, const Ptrs& ptr, double floor,
-                          bool apply_mu, hipStream_t s);
-hipError_t launch_vpart(int prec, const Dims& d, const VSplit& vs, const Ptrs& ptr, bool tap0, hipStream_t s);
-hipError_t launch_vfinal(int prec, const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0,
-                         hipStream_t s);
-hipError_t launch_apply_mu(int prec, const Dims& d, const Ptrs& ptr, hipStream_t s);
-hipError_t launch_images(int prec, const Dims& d, const Ptrs& ptr, void* C, hipStream_t s);
-hipError_t launch_nll(int prec, const Dims& d, const Ptrs& ptr, hipStream_t s);
-hipError_t launch_identity(int prec, const Dims& d, void* W, hipStream_t s);
 hipError_t launch_zero_status(int* status, hipStream_t s);
 size_t images_lds(const Dims& d);
 size_t nll_lds(const Dims& d);

@@ -11,61 +11,70 @@ namespace ctfiss {
 template <typename R>
 using WFn = void (*)(IterArgs<R>, IterLds);
 
-template <typename R, int G, int CPL>
+template <typename R, int G, int CPL, int RPL>
 WFn<R> wfn(int rule) {
-  return rule == 0 ? &k_iss<R, G, CPL> : &k_ip<R, G, CPL>;
+  if (rule == 0) return &k_iss<R, G, CPL, RPL>;
+  if constexpr (RPL == 1) return &k_ip<R, G, CPL, 1>;
+  return nullptr;
 }
 
-template <typename R, int G>
+template <typename R, int G, int RPL>
 WFn<R> pick_cpl(int rule, int cpl) {
   if constexpr (sizeof(R) == 4) {
     switch (cpl) {
-      case 4: return wfn<R, G, 4>(rule);
-      case 8: return wfn<R, G, 8>(rule);
-      case 12: return wfn<R, G, 12>(rule);
-      case 16: return wfn<R, G, 16>(rule);
-      case 20: return wfn<R, G, 20>(rule);
-      case 24: return wfn<R, G, 24>(rule);
-      case 28: return wfn<R, G, 28>(rule);
-      case 32: return wfn<R, G, 32>(rule);
+      case 4: return wfn<R, G, 4, RPL>(rule);
+      case 8: return wfn<R, G, 8, RPL>(rule);
+      case 12: return wfn<R, G, 12, RPL>(rule);
+      case 16: return wfn<R, G, 16, RPL>(rule);
+      case 20: return wfn<R, G, 20, RPL>(rule);
+      case 24: return wfn<R, G, 24, RPL>(rule);
+      case 28: return wfn<R, G, 28, RPL>(rule);
+      case 32: return wfn<R, G, 32, RPL>(rule);
       default: return nullptr;
     }
   } else {
     switch (cpl) {
-      case 4: return wfn<R, G, 4>(rule);
-      case 6: return wfn<R, G, 6>(rule);
-      case 8: return wfn<R, G, 8>(rule);
-      case 10: return wfn<R, G, 10>(rule);
-      case 12: return wfn<R, G, 12>(rule);
-      case 16: return wfn<R, G, 16>(rule);
+      case 4: return wfn<R, G, 4, RPL>(rule);
+      case 6: return wfn<R, G, 6, RPL>(rule);
+      case 8: return wfn<R, G, 8, RPL>(rule);
+      case 10: return wfn<R, G, 10, RPL>(rule);
+      case 12: return wfn<R, G, 12, RPL>(rule);
+      case 16: return wfn<R, G, 16, RPL>(rule);
       default: return nullptr;
     }
   }
 }
 
+template <typename R, int G>
+WFn<R> pick_rpl(int rule, int cpl, int rpl) {
+  if (rpl == 1) return pick_cpl<R, G, 1>(rule, cpl);
+  if (rpl == 2) return pick_cpl<R, G, 2>(rule, cpl);
+  return nullptr;
+}
+
 template <typename R>
-WFn<R> pick(int rule, int G, int cpl) {
-  if constexpr (sizeof(R) == 4) {
-    if (G == 16) return pick_cpl<R, 16>(rule, cpl);
-    if (G == 32) return pick_cpl<R, 32>(rule, cpl);
-  } else {
-    if (G == 16) return pick_cpl<R, 16>(rule, cpl);
-    if (G == 32) return pick_cpl<R, 32>(rule, cpl);
-    if (G == 64) return pick_cpl<R, 64>(rule, cpl);
+WFn<R> pick(int rule, int G, int cpl, int rpl) {
+  if (G == 16) return pick_rpl<R, 16>(rule, cpl, rpl);
+  if (G == 32) return pick_rpl<R, 32>(rule, cpl, rpl);
+  if constexpr (sizeof(R) == 8) {
+    if (G == 64) return pick_rpl<R, 64>(rule, cpl, rpl);
   }
   return nullptr;
 }
 
 template <typename R>
-hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, double floor, bool apply_mu,
-                     hipStream_t s) {
-  WFn<R> fn = pick<R>(rule, p.G, p.CPL);
+bool have_wkernel(int rule, int G, int cpl, int rpl) {
+  return pick<R>(rule, G, cpl, rpl) != nullptr;
+}
+
+template <typename R>
+hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s) {
+  WFn<R> fn = pick<R>(rule, p.G, p.CPL, p.RPL);
   if (!fn) return hipErrorInvalidValue;
   IterArgs<R> a;
   a.X = static_cast<const Cx<R>*>(ptr.X);
   a.W = static_cast<Cx<R>*>(ptr.W);
-  a.B = static_cast<R*>(ptr.B);
-  a.V = static_cast<const R*>(ptr.V);
+  a.ilam = static_cast<const R*>(ptr.ilam);
   a.P = static_cast<R*>(ptr.P);
   a.P0 = static_cast<R*>(ptr.P0);
   a.musq = static_cast<R*>(ptr.musq);
@@ -76,9 +85,8 @@ hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, do
   a.M = d.M;
   a.D = d.D;
   a.K = d.K;
-  a.floor = (R)floor;
   a.rm = d.rm;
-  const IterLds L = iter_lds_layout(d.M, d.T, d.Mb, d.N, d.K, (int)sizeof(R), rule != 0);
+  const IterLds L = iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, (int)sizeof(R), rule != 0);
   if (L.total > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     if (e != hipSuccess) return e;
@@ -88,15 +96,18 @@ hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, do
 }
 
 template <typename R>
-VArgs<R> make_vargs(const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0) {
-  VArgs<R> a;
-  a.B = static_cast<const R*>(ptr.B);
+NmfArgs<R> make_nargs(const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0, bool apply_mu) {
+  NmfArgs<R> a;
+  a.B = static_cast<R*>(ptr.B);
   a.V = static_cast<R*>(ptr.V);
-  a.P = static_cast<const R*>(tap0 ? ptr.P0 : ptr.P);
+  a.ilam = static_cast<R*>(ptr.ilam);
+  a.P = static_cast<const R*>(ptr.P);
+  a.P0 = static_cast<const R*>(ptr.P0);
   a.vnum = static_cast<R*>(ptr.vnum);
   a.vden = static_cast<R*>(ptr.vden);
   a.musq = static_cast<const R*>(ptr.musq);
   a.mu = static_cast<R*>(ptr.mu);
+  a.mu_prev = apply_mu ? static_cast<const R*>(ptr.mu) : nullptr;
   a.status = ptr.status;
   a.F = d.F;
   a.T = d.T;
@@ -110,19 +121,36 @@ VArgs<R> make_vargs(const Dims& d, const VSplit& vs, const Ptrs& ptr, double flo
 }
 
 template <typename R>
+hipError_t lambda_t(const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s) {
+  NmfArgs<R> a = make_nargs<R>(d, VSplit{1, d.F}, ptr, 0.0, false, apply_mu);
+  dim3 grid((d.T + kTile - 1) / kTile, (d.F + 15) / 16, d.N);
+  hipLaunchKernelGGL(k_lambda<R>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t nmfb_t(const Dims& d, const Ptrs& ptr, double floor, bool apply_mu, hipStream_t s) {
+  NmfArgs<R> a = make_nargs<R>(d, VSplit{1, d.F}, ptr, floor, false, apply_mu);
+  int fb = 256 / d.K;
+  if (fb > 16) fb = 16;
+  dim3 grid((d.F + fb - 1) / fb, d.N);
+  hipLaunchKernelGGL(k_nmf_b<R>, grid, dim3(256), 0, s, a, fb);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t vpart_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, bool tap0, hipStream_t s) {
-  VArgs<R> a = make_vargs<R>(d, vs, ptr, 0.0, tap0);
-  dim3 grid((d.T + kVTile - 1) / kVTile, vs.nch, d.N);
+  NmfArgs<R> a = make_nargs<R>(d, vs, ptr, 0.0, tap0, false);
+  dim3 grid((d.T + kTile - 1) / kTile, vs.nch, d.N);
   hipLaunchKernelGGL(k_vpart<R>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t vfinal_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0, hipStream_t s) {
-  VArgs<R> a = make_vargs<R>(d, vs, ptr, floor, tap0);
-  const int n = d.N * d.K * d.T;
-  dim3 grid((n + 255) / 256 + 1);
-  hipLaunchKernelGGL(k_vfinal<R>, grid, dim3(256), 0, s, a);
+  NmfArgs<R> a = make_nargs<R>(d, vs, ptr, floor, tap0, false);
+  const int nv = (d.N * d.K * d.T + 255) / 256;
+  hipLaunchKernelGGL(k_vfinal<R>, dim3(nv + d.Mb), dim3(256), 0, s, a, nv);
   return hipGetLastError();
 }
 
@@ -196,7 +224,10 @@ hipError_t identity_t(const Dims& d, void* W, hipStream_t s) {
 }
 
 #define CTFISS_INSTANTIATE(R)                                                                                  \
-  template hipError_t wupdate_t<R>(int, const Plan&, const Dims&, const Ptrs&, double, bool, hipStream_t);     \
+  template hipError_t wupdate_t<R>(int, const Plan&, const Dims&, const Ptrs&, bool, hipStream_t);             \
+  template hipError_t lambda_t<R>(const Dims&, const Ptrs&, bool, hipStream_t);                               \
+  template hipError_t nmfb_t<R>(const Dims&, const Ptrs&, double, bool, hipStream_t);                         \
+  template bool have_wkernel<R>(int, int, int, int);                                                          \
   template hipError_t vpart_t<R>(const Dims&, const VSplit&, const Ptrs&, bool, hipStream_t);                 \
   template hipError_t vfinal_t<R>(const Dims&, const VSplit&, const Ptrs&, double, bool, hipStream_t);        \
   template hipError_t apply_mu_t<R>(const Dims&, const Ptrs&, hipStream_t);                                  \
