@@ -56,7 +56,7 @@ def run_config(sep, X, B0, V0, n_iter):
     return sep.source_images()
 
 
-def time_path(torch, Separator, wl, Xc, B0, V0, precision, rule, steps, warmup, profile=False):
+def time_path(torch, Separator, wl, Xc, B0, V0, precision, rule, steps, warmup, profile=0):
     sep = Separator(wl.F, wl.T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision=precision, rule=rule)
     rd = torch.float32 if precision == "fp32" else torch.float64
     cd = torch.complex64 if precision == "fp32" else torch.complex128
@@ -67,14 +67,14 @@ def time_path(torch, Separator, wl, Xc, B0, V0, precision, rule, steps, warmup, 
         run_config(sep, X, B, V, wl.n_iter)
     torch.cuda.synchronize()
     if profile:
-        sep.set_profiling(True)
+        sep.set_profiling(profile)
     t0 = time.perf_counter()
     for _ in range(steps):
         C = run_config(sep, X, B, V, wl.n_iter)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     status = sep.status()
-    stats = {k: sep.kernel_stats(k) for k in range(5)} if profile else None
+    stats = {k: sep.kernel_stats(k) for k in range(7)} if profile else None
     sep.close()
     return dt, C, status, stats
 
@@ -100,6 +100,8 @@ def main() -> int:
     ap.add_argument("--side-steps", type=int, default=2, help="timed steps of the FP64 and IP paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="time only the FP32 ISS path")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -107,8 +109,17 @@ def main() -> int:
               "(the bin-sharded multi-GPU path is a design, not built)", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "copies": 3}))
+        return 0
 
     from datagen import WORKLOADS, init_nmf, make_mixture
     from paper_2510_02382_amd import Separator
@@ -124,16 +135,18 @@ def main() -> int:
     V0 = torch.from_numpy(V0n).to(dev)
     units = wl.F * wl.T * wl.n_iter
 
-    log("timing FP32 ISS")
+    log("timing FP32 ISS (HIP events around the W-update kernel)")
     dt, C32, st32, stats = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", args.steps, args.warmup,
-                                     profile=True)
+                                     profile=1)
     value = units * args.steps / dt
     n_iss, ms_iss = stats[0]
     avg_iss_ms = ms_iss / max(n_iss, 1)
     flops_launch = wl.F * wl.T * iss_flops_per_unit(wl.mbar, wl.N, wl.K)
     achieved = flops_launch / (avg_iss_ms * 1e-3) / 1e12
-    kernel_ms = {name: (stats[i][1] / max(stats[i][0], 1)) for i, name in
-                 enumerate(["w_update_iss", "v_partial", "v_final_mu", "final_rescale", "images"])}
+    log("per-kernel breakdown (separate profiled steps, every kernel timed)")
+    _, _, _, allstats = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", 1, 0, profile=-1)
+    names = ["w_update_iss", "v_partial", "v_final_mu", "final_rescale", "images", "lambda", "basis_update"]
+    kernel_ms = {names[i]: allstats[i][1] / max(allstats[i][0], 1) for i in range(7)}
     log(f"FP32 ISS: {dt / args.steps * 1e3:.3f} ms/step, {value:.4e} F·T·it/s, k_iss avg {avg_iss_ms * 1e3:.1f} us "
         f"({achieved:.1f} TFLOP/s), status {st32}")
 

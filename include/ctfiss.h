@@ -137,14 +137,16 @@ int ctfiss_destroy(ctfiss_ctx* ctx);
 /* Static description of a status code. */
 const char* ctfiss_status_string(int status);
 
-/* Kernel timing: when enabled, ctfiss_iterate and ctfiss_source_images record
- * HIP events around each kernel launch on the context's stream.
- * ctfiss_kernel_stats synchronises and returns, for kernel class `which`
- * (0 = W update [ISS or IP sweep kernel], 1 = activation partial sums,
- * 2 = activation update and scale, 3 = final rescale, 4 = source images,
- * 5 = source-variance product lambda = b v, 6 = basis update), the launches
- * and summed milliseconds since profiling was enabled. */
-int ctfiss_set_profiling(ctfiss_ctx* ctx, int enable);
+/* Kernel timing: ctfiss_set_profiling(ctx, mask) records HIP events around
+ * every launch of each kernel class whose bit is set in mask (0 disables,
+ * -1 times every class) on the context's stream, in ctfiss_iterate and
+ * ctfiss_source_images.  Kernel classes: 0 = W update [ISS or IP sweep],
+ * 1 = activation partial sums, 2 = activation update and scale, 3 = final
+ * rescale, 4 = source images, 5 = source-variance product lambda = b v,
+ * 6 = basis update.  ctfiss_kernel_stats synchronises and returns, for class
+ * `which`, the launches and summed milliseconds since the last
+ * ctfiss_set_profiling call. */
+int ctfiss_set_profiling(ctfiss_ctx* ctx, int mask);
 int ctfiss_kernel_stats(ctfiss_ctx* ctx, int which, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus

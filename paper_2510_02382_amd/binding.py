@@ -155,8 +155,9 @@ def ctfiss_destroy(ctx) -> None:
     _check(_lib.ctfiss_destroy(ctx), "ctfiss_destroy")
 
 
-def ctfiss_set_profiling(ctx, enable: bool) -> None:
-    _check(_lib.ctfiss_set_profiling(ctx, 1 if enable else 0), "ctfiss_set_profiling")
+def ctfiss_set_profiling(ctx, mask: int) -> None:
+    """mask: bit i times kernel class i; -1 times all, 0 disables."""
+    _check(_lib.ctfiss_set_profiling(ctx, int(mask)), "ctfiss_set_profiling")
 
 
 def ctfiss_kernel_stats(ctx, which: int) -> tuple[int, float]:

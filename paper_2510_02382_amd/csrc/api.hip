@@ -69,17 +69,11 @@ bool plan_from_string(const char* spec, int prec, int rule, const Dims& d, size_
   return plan_for(prec, rule, d, max_lds, G, rpl, cpl, out);
 }
 
-// Split of the bins for the activation partial sums: enough workgroups to
-// cover the chip twice, bins per chunk a multiple of 4.
+// Split of the bins for the activation partial sums: chunks of 64 bins (four
+// 16-bin MFMA sub-tiles per wave).
 VSplit choose_vsplit(const Dims& d) {
-  const int tiles = (d.T + 63) / 64;
-  int nch = (512 + d.N * tiles - 1) / (d.N * tiles);
-  if (nch < 1) nch = 1;
-  int fchunk = (d.F + nch - 1) / nch;
-  fchunk = (fchunk + 3) / 4 * 4;
-  if (fchunk < 4) fchunk = 4;
-  nch = (d.F + fchunk - 1) / fchunk;
-  return VSplit{nch, fchunk};
+  const int fchunk = 64;
+  return VSplit{(d.F + fchunk - 1) / fchunk, fchunk};
 }
 
 __global__ void k_zero_status(int* status) {
@@ -188,7 +182,7 @@ struct ctfiss_ctx {
   Plan plan;
   VSplit vs;
   bool have_input, have_state;
-  bool prof;
+  int prof;  // bit mask of timed kernel classes
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> pool;
   int64_t launches[kClasses];
@@ -209,7 +203,7 @@ hipError_t ev_get(ctfiss_ctx* c, hipEvent_t* e) {
 // Runs one launch, bracketed by events when profiling is on.
 template <typename Fn>
 hipError_t timed(ctfiss_ctx* c, int cls, Fn&& fn) {
-  if (!c->prof) return fn();
+  if (!(c->prof & (1 << cls))) return fn();
   TimedLaunch t{cls, nullptr, nullptr};
   hipError_t e = ev_get(c, &t.a);
   if (e == hipSuccess) e = ev_get(c, &t.b);
@@ -299,7 +293,7 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   c->ptr.nllpart = reinterpret_cast<double*>(c->ws + lay.nllpart);
   c->ptr.status = reinterpret_cast<int*>(c->ws + lay.status);
   c->have_input = c->have_state = false;
-  c->prof = false;
+  c->prof = 0;
   for (int i = 0; i < kClasses; ++i) {
     c->launches[i] = 0;
     c->ms[i] = 0.0;
@@ -446,10 +440,10 @@ const char* ctfiss_status_string(int status) {
   }
 }
 
-int ctfiss_set_profiling(ctfiss_ctx* c, int enable) {
+int ctfiss_set_profiling(ctfiss_ctx* c, int mask) {
   if (!c) return CTFISS_E_ARG;
   if (drain_timing(c) != hipSuccess) return CTFISS_E_HIP;
-  c->prof = enable != 0;
+  c->prof = mask;
   for (int i = 0; i < kClasses; ++i) {
     c->launches[i] = 0;
     c->ms[i] = 0.0;

@@ -123,7 +123,7 @@ NmfArgs<R> make_nargs(const Dims& d, const VSplit& vs, const Ptrs& ptr, double f
 template <typename R>
 hipError_t lambda_t(const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s) {
   NmfArgs<R> a = make_nargs<R>(d, VSplit{1, d.F}, ptr, 0.0, false, apply_mu);
-  dim3 grid((d.T + kTile - 1) / kTile, (d.F + 15) / 16, d.N);
+  dim3 grid((d.T + 63) / 64, (d.F + 15) / 16, d.N);
   hipLaunchKernelGGL(k_lambda<R>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -131,17 +131,19 @@ hipError_t lambda_t(const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s
 template <typename R>
 hipError_t nmfb_t(const Dims& d, const Ptrs& ptr, double floor, bool apply_mu, hipStream_t s) {
   NmfArgs<R> a = make_nargs<R>(d, VSplit{1, d.F}, ptr, floor, false, apply_mu);
-  int fb = 256 / d.K;
-  if (fb > 16) fb = 16;
-  dim3 grid((d.F + fb - 1) / fb, d.N);
-  hipLaunchKernelGGL(k_nmf_b<R>, grid, dim3(256), 0, s, a, fb);
+  // one wave per 32 (FP32) or 16 (FP64) frames, at most 16 waves (they loop over longer signals)
+  const int fpw = sizeof(R) == 4 ? 32 : 16;
+  int waves = (d.T + fpw - 1) / fpw;
+  if (waves > 16) waves = 16;
+  dim3 grid((d.F + 15) / 16, d.N);
+  hipLaunchKernelGGL(k_nmf_b<R>, grid, dim3(64 * waves), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t vpart_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, bool tap0, hipStream_t s) {
   NmfArgs<R> a = make_nargs<R>(d, vs, ptr, 0.0, tap0, false);
-  dim3 grid((d.T + kTile - 1) / kTile, vs.nch, d.N);
+  dim3 grid((d.T + 15) / 16, vs.nch, d.N);
   hipLaunchKernelGGL(k_vpart<R>, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }

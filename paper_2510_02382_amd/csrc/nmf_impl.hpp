@@ -28,8 +28,6 @@ struct NmfArgs {
   RowMap rm;
 };
 
-constexpr int kTile = 64;   // frames per workgroup tile
-constexpr int kFSub = 4;    // bins per LDS sub-tile (one per wave)
 
 template <typename R>
 __device__ __forceinline__ R pending_scale(const NmfArgs<R>& a, int n) {
@@ -38,154 +36,251 @@ __device__ __forceinline__ R pending_scale(const NmfArgs<R>& a, int n) {
   return R(1) / (m * m);
 }
 
-// 1/lambda_{n,f,t} with lambda = (b / mu^2) v.  256 threads: 64 frames x 4 bin lanes,
-// 16 bins per workgroup.
+// ------------------------------------------------------------------ MFMA
+// 16x16x4 matrix-core tiles (one wave = 64 lanes).  Lane l = 16*lq + lr holds
+// A[lr][lq] and B[lq][lr] of the 16x4 and 4x16 operands, and accumulator
+// element v < 4 of the 16x16 result in row acc_row(lq, v), column lr: row
+// 4*lq + v for the FP32 instruction, lq + 4*v for the FP64 one (measured on
+// gfx950).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename R>
+struct Acc4;
+template <>
+struct Acc4<float> {
+  typedef f32x4 type;
+};
+template <>
+struct Acc4<double> {
+  typedef f64x4 type;
+};
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename R>
+__device__ __forceinline__ int acc_row(int lq, int v) {
+  return sizeof(R) == 4 ? 4 * lq + v : lq + 4 * v;
+}
+template <typename R>
+__device__ __forceinline__ typename Acc4<R>::type acc_zero() {
+  typename Acc4<R>::type z;
+  z[0] = z[1] = z[2] = z[3] = R(0);
+  return z;
+}
+
+// 1/lambda_{n,f,t} with lambda = (b / mu^2) v: one 16 (bins) x 16 (frames) tile
+// per wave, K/4 MFMA steps.  Grid (ceil(T/64), ceil(F/16), N), 4 waves per
+// workgroup covering 64 frames.
 template <typename R>
 __global__ void __launch_bounds__(256) k_lambda(NmfArgs<R> a) {
-  __shared__ R sV[kMaxK][kTile];
-  __shared__ R sB[16][kMaxK];
+  constexpr int KS = kMaxK / 4;
   const int T = a.T, K = a.K, F = a.F;
-  const int t0 = blockIdx.x * kTile, f0 = blockIdx.y * 16, n = blockIdx.z;
-  const int tl = threadIdx.x & (kTile - 1), fl = threadIdx.x / kTile;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  const int n = blockIdx.z, f0 = blockIdx.y * 16, t0 = blockIdx.x * 64 + wave * 16;
+  if (t0 >= T) return;
+  const int nks = (K + 3) / 4;
   const R sc = pending_scale(a, n);
-  for (int i = threadIdx.x; i < K * kTile; i += blockDim.x) {
-    const int k = i / kTile, t = t0 + (i - k * kTile);
-    sV[k][i - k * kTile] = t < T ? a.V[((size_t)n * K + k) * T + t] : R(0);
+  const R* Bn = a.B + (size_t)n * F * K;
+  const R* Vn = a.V + (size_t)n * K * T;
+  const int fa = f0 + lr, tb = t0 + lr;
+  R av[KS], bv[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = 4 * s + lq;
+    const bool ok = s < nks && k < K;
+    av[s] = (ok && fa < F) ? Bn[(size_t)fa * K + k] : R(0);
+    bv[s] = (ok && tb < T) ? Vn[(size_t)k * T + tb] : R(0);
   }
-  for (int i = threadIdx.x; i < 16 * K; i += blockDim.x) {
-    const int fi = i / K, k = i - fi * K;
-    sB[fi][k] = f0 + fi < F ? a.B[((size_t)n * F + f0 + fi) * K + k] * sc : R(0);
-  }
-  __syncthreads();
-  const int t = t0 + tl;
-  if (t >= T) return;
-  for (int fi = fl; fi < 16 && f0 + fi < F; fi += 4) {
-    R lam = 0;
-    for (int k = 0; k < K; ++k) lam += sB[fi][k] * sV[k][tl];
-    if (!finite_pos(lam)) latch(a.status, kFaultMu);
-    a.ilam[((size_t)n * F + f0 + fi) * T + t] = R(1) / lam;
+  typename Acc4<R>::type acc = acc_zero<R>();
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    if (s < nks) acc = mfma16(av[s] * sc, bv[s], acc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int f = f0 + acc_row<R>(lq, v);
+    if (f < F && tb < T) {
+      const R lam = acc[v];
+      if (!finite_pos(lam)) latch(a.status, kFaultMu);
+      a.ilam[((size_t)n * F + f) * T + tb] = R(1) / lam;
+    }
   }
 }
 
 // Basis update, Eq. (17), with t' = t - l:
-//   num_k = sum_t' P_{t'} v_{k,t'} / lambda_{t'}^2,  den_k = sum_t' C_{t'} v_{k,t'} / lambda_{t'},
+//   num_{f,k} = sum_t' P_{f,t'} v_{k,t'} / lambda_{f,t'}^2,  den_{f,k} = sum_t' C_{t'} v_{k,t'} / lambda_{f,t'},
 //   C_{t'} = #{l < L_n : t' + l < T};  b <- max((b / mu^2) sqrt(num / den), floor).
-// 256 threads per workgroup, FB bins per workgroup, one (bin, k) pair per thread.
+// (F x T)(T x K) contractions on MFMA: one workgroup per 16 bins, its 4 waves
+// split the frames, partial tiles are summed in LDS in wave order.
 template <typename R>
-__global__ void __launch_bounds__(256) k_nmf_b(NmfArgs<R> a, int FB) {
-  __shared__ R sV[kMaxK][kTile];
-  __shared__ R sE1[16][kTile];
-  __shared__ R sE2[16][kTile];
+__global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) {
+  constexpr int KT = kMaxK / 16;
+  constexpr int ST = sizeof(R) == 4 ? 8 : 4;  // MFMA steps (4 frames each) per wave and round
+  __shared__ R red[2][KT][4][64];
   const int T = a.T, K = a.K, F = a.F;
-  const int f0 = blockIdx.x * FB, n = blockIdx.y;
+  const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  const int n = blockIdx.y, f0 = blockIdx.x * 16;
   const int L = a.rm.L[n];
-  const int pair = threadIdx.x, fi = pair / K, k = pair - fi * K;
-  const bool own = fi < FB && f0 + fi < F;
-  R num = 0, den = 0;
-  for (int t0 = 0; t0 < T; t0 += kTile) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < K * kTile; i += blockDim.x) {
-      const int kk = i / kTile, t = t0 + (i - kk * kTile);
-      sV[kk][i - kk * kTile] = t < T ? a.V[((size_t)n * K + kk) * T + t] : R(0);
-    }
-    for (int i = threadIdx.x; i < FB * kTile; i += blockDim.x) {
-      const int ff = i / kTile, t = t0 + (i - ff * kTile);
-      R e1 = 0, e2 = 0;
-      if (t < T && f0 + ff < F) {
-        const size_t o = ((size_t)n * F + f0 + ff) * T + t;
-        const R il = a.ilam[o];
-        e1 = a.P[o] * il * il;
-        e2 = (R)min(L, T - t) * il;
+  const int nkt = (K + 15) / 16;
+  const R* Pn = a.P + (size_t)n * F * T;
+  const R* In = a.ilam + (size_t)n * F * T;
+  const R* Vn = a.V + (size_t)n * K * T;
+  const int fa = f0 + lr;
+  typename Acc4<R>::type num[KT], den[KT];
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt) num[kt] = den[kt] = acc_zero<R>();
+  // rounds of ST steps; every wave's operand loads of a round are issued before its MFMAs
+  for (int base = wave * ST; 4 * base < T; base += nwave * ST) {
+    R e1[ST], e2[ST], bv[ST][KT];
+#pragma unroll
+    for (int st = 0; st < ST; ++st) {
+      const int t = 4 * (base + st) + lq;
+      e1[st] = e2[st] = R(0);
+      if (fa < F && t < T) {
+        const R il = In[(size_t)fa * T + t];
+        e1[st] = Pn[(size_t)fa * T + t] * il * il;
+        e2[st] = (R)min(L, T - t) * il;
       }
-      sE1[ff][i - ff * kTile] = e1;
-      sE2[ff][i - ff * kTile] = e2;
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        const int k = 16 * kt + lr;
+        bv[st][kt] = (kt < nkt && k < K && t < T) ? Vn[(size_t)k * T + t] : R(0);
+      }
     }
-    __syncthreads();
-    if (own) {
-#pragma unroll 8
-      for (int tl = 0; tl < kTile; ++tl) {
-        num += sE1[fi][tl] * sV[k][tl];
-        den += sE2[fi][tl] * sV[k][tl];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      if (kt < nkt) {
+#pragma unroll
+        for (int st = 0; st < ST; ++st) {
+          num[kt] = mfma16(e1[st], bv[st][kt], num[kt]);
+          den[kt] = mfma16(e2[st], bv[st][kt], den[kt]);
+        }
       }
     }
   }
-  if (own) {
-    const size_t o = ((size_t)n * F + f0 + fi) * K + k;
-    R b = a.B[o] * pending_scale(a, n) * sqrt(num / den);
-    if (!isfinite(b)) latch(a.status, kFaultMu);
-    a.B[o] = b > a.floor ? b : a.floor;
+  // sum the per-wave tiles in wave order
+  for (int w = 0; w < nwave; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          red[0][kt][v][l] = (w == 0 ? R(0) : red[0][kt][v][l]) + num[kt][v];
+          red[1][kt][v][l] = (w == 0 ? R(0) : red[1][kt][v][l]) + den[kt][v];
+        }
+    }
+    __syncthreads();
+  }
+  if (wave != 0) return;
+  const R sc = pending_scale(a, n);
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt) {
+    if (kt >= nkt) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int f = f0 + acc_row<R>(lq, v), k = 16 * kt + lr;
+      if (f < F && k < K) {
+        const size_t o = ((size_t)n * F + f) * K + k;
+        R b = a.B[o] * sc * sqrt(red[0][kt][v][l] / red[1][kt][v][l]);
+        if (!isfinite(b)) latch(a.status, kFaultMu);
+        a.B[o] = b > a.floor ? b : a.floor;
+      }
+    }
   }
 }
 
 // Partial sums over one chunk of bins of
 //   num[k][t] = sum_f b_{f,k} P'_{f,t} / lambda_{f,t}^2,  den[k][t] = sum_f b_{f,k} / lambda_{f,t},
-// with lambda = b v recomputed from the updated bases.  256 threads:
-// thread (kg, tl) owns frame t0 + tl and bases k = kg, kg + 4, ...
+// with lambda = b v recomputed from the updated bases.  One wave per 16 frames
+// of one chunk: per 16-bin sub-tile, lambda on MFMA (K/4 steps), the two
+// weights in the accumulator layout, then b^T times them on MFMA (the bin
+// index of the accumulator rows is the reduction index, 4 MFMA steps).
 template <typename R>
 __global__ void __launch_bounds__(256) k_vpart(NmfArgs<R> a) {
-  __shared__ R sV[kMaxK][kTile];
-  __shared__ R sB[kFSub][kMaxK];
-  __shared__ R sE1[kFSub][kTile];
-  __shared__ R sE2[kFSub][kTile];
+  constexpr int KT = kMaxK / 16;
+  constexpr int KS = kMaxK / 4;
+  __shared__ R red[2][KT][4][64];
   const int T = a.T, K = a.K, F = a.F;
-  const int t0 = blockIdx.x * kTile, ch = blockIdx.y, n = blockIdx.z;
-  const int f0 = ch * a.fchunk;
-  const int f1 = min(F, f0 + a.fchunk);
-  const int tl = threadIdx.x & (kTile - 1), kg = threadIdx.x / kTile;
-  const int t = t0 + tl;
-  const bool tin = t < T;
-  const R* Pn = (a.tap0 ? a.P0 : a.P) + (size_t)n * F * T;
-  for (int i = threadIdx.x; i < K * kTile; i += blockDim.x) {
-    const int k = i / kTile, tt = t0 + (i - k * kTile);
-    sV[k][i - k * kTile] = tt < T ? a.V[((size_t)n * K + k) * T + tt] : R(1);
-  }
-  constexpr int KPT = kMaxK / 4;
-  R num[KPT], den[KPT];
-#pragma unroll
-  for (int i = 0; i < KPT; ++i) num[i] = den[i] = R(0);
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  const int n = blockIdx.z, ch = blockIdx.y, t0 = blockIdx.x * 16;
+  const int f1 = min(F, ch * a.fchunk + a.fchunk);
+  const int fs = ch * a.fchunk + 16 * wave;  // this wave's 16-bin sub-tile
+  const int nkt = (K + 15) / 16, nks = (K + 3) / 4;
   const R* Bn = a.B + (size_t)n * F * K;
-  for (int fs = f0; fs < f1; fs += kFSub) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < kFSub * K; i += blockDim.x) {
-      const int fi = i / K, k = i - fi * K;
-      sB[fi][k] = fs + fi < f1 ? Bn[(size_t)(fs + fi) * K + k] : R(0);
-    }
-    __syncthreads();
-    {
-      const int fi = kg, f = fs + fi;
-      R e1 = 0, e2 = 0;
-      if (f < f1 && tin) {
-        R lam = 0;
-        for (int k = 0; k < K; ++k) lam += sB[fi][k] * sV[k][tl];
-        const R il = R(1) / lam;
-        e1 = Pn[(size_t)f * T + t] * il * il;
-        e2 = il;
-      }
-      sE1[fi][tl] = e1;
-      sE2[fi][tl] = e2;
-    }
-    __syncthreads();
-    const int nf = min(kFSub, f1 - fs);
-    for (int fi = 0; fi < nf; ++fi) {
-      const R e1 = sE1[fi][tl], e2 = sE2[fi][tl];
+  const R* Vn = a.V + (size_t)n * K * T;
+  const R* Pn = (a.tap0 ? a.P0 : a.P) + (size_t)n * F * T;
+  const int tb = t0 + lr, fa = fs + lr;
+  R av[KS], vop[KS];
 #pragma unroll
-      for (int i = 0; i < KPT; ++i) {
-        const int k = kg + 4 * i;
-        if (k < K) {
-          num[i] += sB[fi][k] * e1;
-          den[i] += sB[fi][k] * e2;
-        }
+  for (int s = 0; s < KS; ++s) {
+    const int k = 4 * s + lq;
+    const bool ok = s < nks && k < K;
+    vop[s] = (ok && tb < T) ? Vn[(size_t)k * T + tb] : R(0);
+    av[s] = (ok && fa < f1) ? Bn[(size_t)fa * K + k] : R(0);
+  }
+  R pv[4], bt[KT][4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int f = fs + acc_row<R>(lq, v);
+    pv[v] = (f < f1 && tb < T) ? Pn[(size_t)f * T + tb] : R(0);
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const int k = 16 * kt + lr;
+      bt[kt][v] = (kt < nkt && f < f1 && k < K) ? Bn[(size_t)f * K + k] : R(0);
+    }
+  }
+  typename Acc4<R>::type lam = acc_zero<R>();
+#pragma unroll
+  for (int s = 0; s < KS; ++s)
+    if (s < nks) lam = mfma16(av[s], vop[s], lam);
+  R e1[4], e2[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int f = fs + acc_row<R>(lq, v);
+    e1[v] = e2[v] = R(0);
+    if (f < f1 && tb < T) {
+      const R il = R(1) / lam[v];
+      e1[v] = pv[v] * il * il;
+      e2[v] = il;
+    }
+  }
+  typename Acc4<R>::type num[KT], den[KT];
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt) {
+    num[kt] = den[kt] = acc_zero<R>();
+    if (kt < nkt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        num[kt] = mfma16(bt[kt][v], e1[v], num[kt]);
+        den[kt] = mfma16(bt[kt][v], e2[v], den[kt]);
       }
     }
   }
-  if (tin) {
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
 #pragma unroll
-    for (int i = 0; i < KPT; ++i) {
-      const int k = kg + 4 * i;
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          red[0][kt][v][l] = (w == 0 ? R(0) : red[0][kt][v][l]) + num[kt][v];
+          red[1][kt][v][l] = (w == 0 ? R(0) : red[1][kt][v][l]) + den[kt][v];
+        }
+    }
+    __syncthreads();
+  }
+  if (wave != 0 || tb >= T) return;
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt) {
+    if (kt >= nkt) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = 16 * kt + acc_row<R>(lq, v);
       if (k < K) {
-        const size_t o = (((size_t)n * a.nch + ch) * K + k) * T + t;
-        a.vnum[o] = num[i];
-        a.vden[o] = den[i];
+        const size_t o = (((size_t)n * a.nch + ch) * K + k) * T + tb;
+        a.vnum[o] = red[0][kt][v][l];
+        a.vden[o] = red[1][kt][v][l];
       }
     }
   }
@@ -219,6 +314,7 @@ __global__ void __launch_bounds__(256) k_vfinal(NmfArgs<R> a, int nvblocks) {
   if (i >= N * K * T) return;
   const int n = i / (K * T), k = (i / T) % K, t = i % T;
   R num = 0, den = 0;
+#pragma unroll 8
   for (int ch = 0; ch < a.nch; ++ch) {
     const size_t o = (((size_t)n * a.nch + ch) * K + k) * T + t;
     num += a.vnum[o];

@@ -78,8 +78,13 @@ class Separator:
         """0 if no device fault was latched, else the device fault code (synchronises)."""
         return b.ctfiss_sync_status(self.ctx)[1]
 
-    def set_profiling(self, enable: bool) -> None:
-        b.ctfiss_set_profiling(self.ctx, enable)
+    def set_profiling(self, mask) -> None:
+        """mask: bit i times kernel class i (see ctfiss_set_profiling); True = all, False = none."""
+        if mask is True:
+            mask = -1
+        elif mask is False:
+            mask = 0
+        b.ctfiss_set_profiling(self.ctx, int(mask))
 
     def kernel_stats(self, which: int):
         return b.ctfiss_kernel_stats(self.ctx, which)
