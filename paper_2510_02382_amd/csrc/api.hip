@@ -8,7 +8,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/ctfiss.h"
+#include "ctfiss.h"
 #include "launch.hpp"
 #include "out_impl.hpp"
 

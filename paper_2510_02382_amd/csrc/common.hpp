@@ -101,6 +101,12 @@ __device__ __forceinline__ void latch(int* status, int code) {
   if (status) atomicCAS(status, 0, code);
 }
 
+// One atomic per wave: the lowest lane whose flag is set latches the code.
+__device__ __forceinline__ void latch_wave(int* status, bool bad, int code) {
+  const unsigned long long m = __ballot(bad ? 1 : 0);
+  if (m && (int)(threadIdx.x & 63) == __ffsll((long long)m) - 1) latch(status, code);
+}
+
 template <typename R>
 __device__ __forceinline__ bool finite_pos(R v) {
   return v > R(0) && isfinite(v);  // false for NaN, 0, negatives, +inf
@@ -121,8 +127,10 @@ __host__ __device__ constexpr int iter_max_threads(int rsize, int cpl, int rpl) 
 
 // ------------------------------------------------------------------ LDS layout
 // Per-bin on-chip layout of the W-update kernels (TP = G * CPL padded frames).
+// During the sweep: x, w, phi, yb, wb (+ q, aug, u, fac for IP).  After it the
+// per-row powers |y|^2, a[Mb][TP], reuse the same bytes from offset 0.
 struct IterLds {
-  size_t x, w, phi, p, yb, wb, q, aug, u, fac, misc, total;
+  size_t x, w, phi, yb, wb, q, aug, u, fac, a, misc, total;
   int lx, lp, tp, lmax;
 };
 
@@ -141,7 +149,6 @@ __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, 
   L.x = off; off += align_up((size_t)M * L.lx * cs, 16);
   L.w = off; off += align_up((size_t)Mb * Mb * cs, 16);
   L.phi = off; off += align_up((size_t)N * L.lp * rsize, 16);
-  L.p = off; off += align_up((size_t)N * L.tp * rsize, 16);
   L.yb = off; off += align_up((size_t)2 * L.tp * cs, 16);
   L.wb = off; off += align_up((size_t)2 * Mb * cs, 16);
   if (ip) {
@@ -152,6 +159,9 @@ __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, 
   } else {
     L.q = L.aug = L.u = L.fac = 0;
   }
+  L.a = 0;
+  const size_t asz = align_up((size_t)Mb * L.tp * rsize, 16);
+  if (asz > off) off = asz;
   L.misc = off; off += 64;
   L.total = off;
   return L;

@@ -43,13 +43,13 @@ struct BinLds {
   Cx<R>* x;    // [M][LX]  x[m][D-1 + t] = X[m][f][t], zero elsewhere
   Cx<R>* w;    // [Mb][Mb]
   R* phi;      // [N][LP]  phi[n][Lmax-1 + t] = 1/lambda_{n,f,t} for t < T, zero elsewhere
-  R* p;        // [N][TP]  tap-aligned power accumulator
   Cx<R>* yb;   // [2][TP]  broadcast of y_r
   Cx<R>* wb;   // [2][Mb]  broadcast of w_r^H
   Cx<R>* q;    // [Mb][Mb]  (IP)
   Cx<R>* aug;  // [Mb][Mb+1] (IP)
   Cx<R>* u;    // [Mb] (IP)
   Cx<R>* fac;  // [Mb+1] (IP)
+  R* a;        // [Mb][TP] |y|^2 after the sweep (reuses the bytes above)
   int* misc;
 };
 
@@ -59,13 +59,13 @@ __device__ __forceinline__ BinLds<R> carve(unsigned char* base, const IterLds& L
   s.x = reinterpret_cast<Cx<R>*>(base + L.x);
   s.w = reinterpret_cast<Cx<R>*>(base + L.w);
   s.phi = reinterpret_cast<R*>(base + L.phi);
-  s.p = reinterpret_cast<R*>(base + L.p);
   s.yb = reinterpret_cast<Cx<R>*>(base + L.yb);
   s.wb = reinterpret_cast<Cx<R>*>(base + L.wb);
   s.q = reinterpret_cast<Cx<R>*>(base + L.q);
   s.aug = reinterpret_cast<Cx<R>*>(base + L.aug);
   s.u = reinterpret_cast<Cx<R>*>(base + L.u);
   s.fac = reinterpret_cast<Cx<R>*>(base + L.fac);
+  s.a = reinterpret_cast<R*>(base + L.a);
   s.misc = reinterpret_cast<int*>(base + L.misc);
   return s;
 }
@@ -101,7 +101,6 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
     const int n = i / LP, t = i - n * LP - Lm1;
     s.phi[i] = (t >= 0 && t < T) ? a.ilam[((size_t)n * F + f) * T + t] : R(0);
   }
-  for (int i = tid; i < N * TP; i += nthr) s.p[i] = R(0);
   for (int i = tid; i < 2 * TP; i += nthr) s.yb[i] = Cx<R>{R(0), R(0)};
   __syncthreads();
 }
@@ -115,22 +114,24 @@ __device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>
   for (int i = 0; i < RPL; ++i)
 #pragma unroll
     for (int j = 0; j < CPL; ++j) y[i][j] = Cx<R>{R(0), R(0)};
-  for (int d = 0; d < D; ++d) {
-    for (int m = 0; m < M; ++m) {
-      const int c = d * M + m;
-      Cx<R> w[RPL];
+  // xbar_c[t] = x[m][D-1 + t - d] for c = d*M + m; two columns per trip so the
+  // LDS loads of one overlap the FMAs of the other.
+  const int nc = D * M;
+#pragma unroll 2
+  for (int c = 0; c < nc; ++c) {
+    const int d = c / M, m = c - d * M;
+    Cx<R> w[RPL];
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int p = g * RPL + i;
-        w[i] = p < Mb ? s.w[p * Mb + c] : Cx<R>{R(0), R(0)};
-      }
-      const Cx<R>* xm = s.x + m * LX + Dm1 - d + q;
+    for (int i = 0; i < RPL; ++i) {
+      const int p = g * RPL + i;
+      w[i] = p < Mb ? s.w[p * Mb + c] : Cx<R>{R(0), R(0)};
+    }
+    const Cx<R>* xm = s.x + m * LX + Dm1 - d + q;
 #pragma unroll
-      for (int j = 0; j < CPL; ++j) {
-        const Cx<R> xv = xm[G * j];
+    for (int j = 0; j < CPL; ++j) {
+      const Cx<R> xv = xm[G * j];
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) y[i][j] = cfma(w[i], xv, y[i][j]);
-      }
+      for (int i = 0; i < RPL; ++i) y[i][j] = cfma(w[i], xv, y[i][j]);
     }
   }
   // Padded frames t >= T: a delayed block still reads real frames there
@@ -145,48 +146,39 @@ __device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>
   }
 }
 
-// Stage 4: |y|^2 row sums, tap-aligned powers accumulated tap by tap (a fixed
-// order, so results are bitwise reproducible), P / P0 out.
+// Stage 4: |y|^2 row sums and rows into LDS, then the tap-aligned powers
+// P_n[t] = sum_{l < L_n, t + l < T} |y_{(n,l)}[t + l]|^2 summed in tap order
+// (bitwise reproducible), P / P0 out.  Starts with a barrier: the |y|^2 rows
+// overwrite the sweep's LDS buffers.
 template <typename R, int G, int CPL, int RPL>
 __device__ void epilogue(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int g, int q,
                          const Cx<R> (&y)[RPL][CPL]) {
   const int T = a.T, Mb = a.rm.Mb, N = a.rm.N, F = a.F, TP = L.tp;
   const int tid = threadIdx.x, nthr = blockDim.x;
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int p = g * RPL + i;
     R rs = 0;
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) rs += cabs2(y[i][j]);
+    for (int j = 0; j < CPL; ++j) {
+      const R v = cabs2(y[i][j]);
+      rs += v;
+      if (p < Mb) s.a[p * TP + q + G * j] = v;
+    }
     rs = group_sum<G>(rs);
     if (p < Mb && q == 0) a.musq[(size_t)p * F + f] = rs;
   }
-  for (int l = 0; l < L.lmax; ++l) {
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      const int p = g * RPL + i;
-      if (p < Mb && a.rm.tap[p] == l) {
-        R* pn = s.p + a.rm.src[p] * TP - l;
-#pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-          const int t = q + G * j;
-          if (t >= l) pn[t] += cabs2(y[i][j]);
-        }
-        if (l == 0 && a.P0) {
-          R* p0 = a.P0 + ((size_t)a.rm.src[p] * F + f) * T;
-#pragma unroll
-          for (int j = 0; j < CPL; ++j) {
-            const int t = q + G * j;
-            if (t < T) p0[t] = cabs2(y[i][j]);
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
+  __syncthreads();
   for (int i = tid; i < N * T; i += nthr) {
     const int n = i / T, t = i - n * T;
-    a.P[((size_t)n * F + f) * T + t] = s.p[n * TP + t];
+    const int r0 = a.rm.r0[n], Ln = a.rm.L[n];
+    const R* ar = s.a + r0 * TP + t;
+    R acc = 0;
+    for (int l = 0; l < Ln && t + l < T; ++l) acc += ar[l * TP + l];
+    const size_t o = ((size_t)n * F + f) * T + t;
+    a.P[o] = acc;
+    if (a.P0) a.P0[o] = ar[0];
   }
 }
 
@@ -223,6 +215,7 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(I
   // (the common 1/T cancels in a_p / d_p), z_p = a_p / d_p, z_r = 1 - (d_r / T)^{-1/2};
   // then y_p -= z_p y_r and W[p, :] -= z_p W[r, :] with the pre-update row r.
   const R invT = R(1) / R(T);
+  bool bad = false;
   for (int r = 0; r < Mb; ++r) {
     Cx<R>* yb = s.yb + (r & 1) * TP;
     Cx<R>* wb = s.wb + (r & 1) * Mb;
@@ -245,14 +238,16 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(I
     R ar[RPL], ai[RPL], dd[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) ar[i] = ai[i] = dd[i] = R(0);
+    Cx<R> yr[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) yr[j] = yb[q + G * j];
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
-      const Cx<R> yr = yb[q + G * j];
-      const R pr = cabs2(yr);
+      const R pr = cabs2(yr[j]);
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const R ph = phr[i][G * j];
-        const Cx<R> sv = cmulc(y[i][j], yr);
+        const Cx<R> sv = cmulc(y[i][j], yr[j]);
         ar[i] += ph * sv.x;
         ai[i] += ph * sv.y;
         dd[i] += ph * pr;
@@ -267,19 +262,18 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(I
       const int p = g * RPL + i;
       if (p == r) {
         const R dr = dd[i] * invT;
-        if (!finite_pos(dr)) latch(a.status, kFaultIssDenominator);
+        bad |= !finite_pos(dr);
         z[i] = Cx<R>{R(1) - fast_rsqrt(dr), R(0)};
       } else {
-        if (p < Mb && !finite_pos(dd[i])) latch(a.status, kFaultIssDenominator);
+        bad |= p < Mb && !finite_pos(dd[i]);
         const R inv = fast_rcp(dd[i]);
         z[i] = Cx<R>{ar[i] * inv, ai[i] * inv};
       }
     }
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
-      const Cx<R> yr = yb[q + G * j];
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) y[i][j] = cfms(z[i], yr, y[i][j]);
+      for (int i = 0; i < RPL; ++i) y[i][j] = cfms(z[i], yr[j], y[i][j]);
     }
 #pragma unroll
     for (int k = 0; k < WPL; ++k) {
@@ -292,6 +286,7 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(I
     }
   }
 
+  latch_wave(a.status, bad, kFaultIssDenominator);
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int p = g * RPL + i;

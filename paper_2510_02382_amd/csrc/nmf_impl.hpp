@@ -98,15 +98,17 @@ __global__ void __launch_bounds__(256) k_lambda(NmfArgs<R> a) {
 #pragma unroll
   for (int s = 0; s < KS; ++s)
     if (s < nks) acc = mfma16(av[s] * sc, bv[s], acc);
+  bool bad = false;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int f = f0 + acc_row<R>(lq, v);
     if (f < F && tb < T) {
       const R lam = acc[v];
-      if (!finite_pos(lam)) latch(a.status, kFaultMu);
+      bad |= !finite_pos(lam);
       a.ilam[((size_t)n * F + f) * T + tb] = R(1) / lam;
     }
   }
+  latch_wave(a.status, bad, kFaultMu);
 }
 
 // Basis update, Eq. (17), with t' = t - l:
@@ -322,7 +324,7 @@ __global__ void __launch_bounds__(256) k_vfinal(NmfArgs<R> a, int nvblocks) {
   }
   const R c = a.tap0 ? R(1) : (R)min(a.rm.L[n], T - t);
   R v = a.V[i] * sqrt(num / (c * den));
-  if (!isfinite(v)) latch(a.status, kFaultMu);
+  latch_wave(a.status, !isfinite(v), kFaultMu);
   a.V[i] = v > a.floor ? v : a.floor;
 }
 
