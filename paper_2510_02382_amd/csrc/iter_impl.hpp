@@ -198,12 +198,14 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(I
   demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y);
 
   Cx<R> wreg[RPL][WPL];
-  const R* phr[RPL];  // weight row of each owned row, pre-shifted by its tap
+  R ph[RPL][CPL];  // weights of the lane's rows and frames, phi[n][t - l]
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int p = g * RPL + i;
     const bool ok = p < Mb;
-    phr[i] = s.phi + (ok ? a.rm.src[p] * LP + Lm1 - a.rm.tap[p] : 0) + q;
+    const R* phr = s.phi + (ok ? a.rm.src[p] * LP + Lm1 - a.rm.tap[p] : 0) + q;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) ph[i][j] = ok ? phr[G * j] : R(0);
 #pragma unroll
     for (int k = 0; k < WPL; ++k) {
       const int c = q + G * k;
@@ -246,11 +248,10 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(I
       const R pr = cabs2(yr[j]);
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        const R ph = phr[i][G * j];
         const Cx<R> sv = cmulc(y[i][j], yr[j]);
-        ar[i] += ph * sv.x;
-        ai[i] += ph * sv.y;
-        dd[i] += ph * pr;
+        ar[i] += ph[i][j] * sv.x;
+        ai[i] += ph[i][j] * sv.y;
+        dd[i] += ph[i][j] * pr;
       }
     }
     Cx<R> z[RPL];
