@@ -79,7 +79,7 @@ def time_path(torch, Separator, wl, Xc, B0, V0, precision, rule, steps, warmup, 
     return dt, C, status, stats
 
 
-def cpu_baseline(wl, X, B0, V0, n_iter=3):
+def cpu_baseline(wl, X, B0, V0, n_iter=10):
     from threadpoolctl import threadpool_limits
 
     from oracle import ctf_iss as o

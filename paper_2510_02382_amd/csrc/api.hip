@@ -40,7 +40,7 @@ bool plan_for(int prec, int rule, const Dims& d, size_t max_lds, int G, int RPL,
     if (!ok) return false;
     const size_t lds = iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, G, cpl, rs, rule != 0).total;
     if (lds > max_lds) return false;
-    *out = Plan{G, cpl, RPL, threads, lds};
+    *out = Plan{G, cpl, RPL, threads, lds, 0};
     return true;
   }
   return false;
@@ -96,7 +96,7 @@ constexpr size_t kAlign = 256;
 constexpr int kClasses = 7;
 
 struct Layout {
-  size_t W, B, V, ilam, P, P0, musq, mu, vnum, vden, nllpart, status, total;
+  size_t W, B, V, ilam, P, P0, musq, mu, vnum, vden, nllpart, status, work, total;
 };
 
 struct TimedLaunch {
@@ -165,6 +165,7 @@ Layout make_layout(const Dims& d, int precision) {
   L.vden = take((size_t)d.N * vs.nch * d.K * d.T * rs);
   L.nllpart = take((size_t)d.F * sizeof(double));
   L.status = take(kAlign);
+  L.work = take(kAlign);
   L.total = off;
   return L;
 }
@@ -267,6 +268,14 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
     return CTFISS_E_UNSUPPORTED;
   }
   if (images_lds(d) > (size_t)max_lds || nll_lds(d) > (size_t)max_lds) return CTFISS_E_UNSUPPORTED;
+  // Persistent W-update workgroups: as many as fit on the device at once
+  // (CTFISS_WBLOCKS in the environment overrides it, for tuning); any count
+  // >= 1 gives the same result, since the workgroups share out the bins.
+  plan.blocks = precision == CTFISS_FP32 ? resident_wblocks<float>(rule, plan, d) : resident_wblocks<double>(rule, plan, d);
+  if (const char* wb = std::getenv("CTFISS_WBLOCKS")) {
+    const int n = std::atoi(wb);
+    if (n > 0) plan.blocks = n < d.F ? n : d.F;
+  }
   ctfiss_ctx* c = new (std::nothrow) ctfiss_ctx();
   if (!c) return CTFISS_E_ARG;
   c->d = d;
@@ -292,6 +301,7 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   c->ptr.vden = c->ws + lay.vden;
   c->ptr.nllpart = reinterpret_cast<double*>(c->ws + lay.nllpart);
   c->ptr.status = reinterpret_cast<int*>(c->ws + lay.status);
+  c->ptr.work = reinterpret_cast<int*>(c->ws + lay.work);
   c->have_input = c->have_state = false;
   c->prof = 0;
   for (int i = 0; i < kClasses; ++i) {

@@ -22,7 +22,7 @@ enum Fault : int {
 };
 
 template <typename R>
-struct Cx {
+struct alignas(2 * sizeof(R)) Cx {  // aligned to its size: one 64/128-bit access
   R x, y;
 };
 

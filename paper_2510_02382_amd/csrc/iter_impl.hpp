@@ -34,6 +34,7 @@ struct IterArgs {
   R* musq;          // [Mb][F] row power sums (out)
   const R* mu;      // [Mb] scale of the previous iteration still to apply to W, or null
   int* status;
+  int* work;        // bin counter of the persistent workgroups (zeroed before the launch)
   int F, T, M, D, K;
   RowMap rm;
 };
@@ -77,12 +78,27 @@ __device__ __forceinline__ double fast_rcp(double v) { return 1.0 / v; }
 __device__ __forceinline__ float fast_rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ double fast_rsqrt(double v) { return 1.0 / sqrt(v); }
 
+// Lane index hidden from the optimiser: values derived from it (frame and
+// row masks, LDS offsets) are then recomputed per bin instead of being hoisted
+// out of the persistent bin loop and held in registers across it.
+__device__ __forceinline__ int lane_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+// Same for a workgroup-uniform size used as a divisor: the division's
+// reciprocal is then formed per bin rather than kept live across the loop.
+__device__ __forceinline__ int per_bin(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
 // Stage 1: scaled W_f, zero-padded observation block and inverse variances into LDS.
 template <typename R>
-__device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f) {
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int T = a.T, M = a.M, F = a.F, Mb = a.rm.Mb, N = a.rm.N;
-  const int LX = L.lx, LP = L.lp, TP = L.tp, Dm1 = a.D - 1, Lm1 = L.lmax - 1;
+__device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid) {
+  const int nthr = blockDim.x;
+  const int T = a.T, M = a.M, F = a.F, Mb = per_bin(a.rm.Mb), N = a.rm.N;
+  const int LX = per_bin(L.lx), LP = per_bin(L.lp), TP = L.tp, Dm1 = a.D - 1, Lm1 = L.lmax - 1;
   const Cx<R>* Wf = a.W + (size_t)f * Mb * Mb;
   for (int i = tid; i < Mb * Mb; i += nthr) {
     Cx<R> w = Wf[i];
@@ -109,7 +125,7 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
 template <typename R, int G, int CPL, int RPL>
 __device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int g,
                                            int q, Cx<R> (&y)[RPL][CPL]) {
-  const int M = a.M, D = a.D, Mb = a.rm.Mb, LX = L.lx, Dm1 = D - 1;
+  const int M = per_bin(a.M), D = a.D, Mb = a.rm.Mb, LX = L.lx, Dm1 = D - 1;
 #pragma unroll
   for (int i = 0; i < RPL; ++i)
 #pragma unroll
@@ -151,10 +167,10 @@ __device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>
 // (bitwise reproducible), P / P0 out.  Starts with a barrier: the |y|^2 rows
 // overwrite the sweep's LDS buffers.
 template <typename R, int G, int CPL, int RPL>
-__device__ void epilogue(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int g, int q,
-                         const Cx<R> (&y)[RPL][CPL]) {
-  const int T = a.T, Mb = a.rm.Mb, N = a.rm.N, F = a.F, TP = L.tp;
-  const int tid = threadIdx.x, nthr = blockDim.x;
+__device__ void epilogue(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid, int g,
+                         int q, const Cx<R> (&y)[RPL][CPL]) {
+  const int T = per_bin(a.T), Mb = a.rm.Mb, N = a.rm.N, F = a.F, TP = L.tp;
+  const int nthr = blockDim.x;
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
@@ -184,15 +200,13 @@ __device__ void epilogue(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
 
 // ------------------------------------------------------------------ ISS
 template <typename R, int G, int CPL, int RPL>
-__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(IterArgs<R> a, IterLds L) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const BinLds<R> s = carve<R>(smem, L);
-  const int f = blockIdx.x, tid = threadIdx.x;
+__device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f) {
+  const int tid = lane_tid();
   const int g = tid / G, q = tid - g * G;
   const int T = a.T, Mb = a.rm.Mb, TP = L.tp, LP = L.lp, Lm1 = L.lmax - 1;
   constexpr int WPL = (kMaxRows + G - 1) / G;
 
-  load_bin(a, s, L, f);
+  load_bin(a, s, L, f, tid);
 
   Cx<R> y[RPL][CPL];
   demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y);
@@ -216,7 +230,7 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(I
   // ISS sweep over r: a_p = sum_t phi_p y_p conj(y_r), d_p = sum_t phi_p |y_r|^2
   // (the common 1/T cancels in a_p / d_p), z_p = a_p / d_p, z_r = 1 - (d_r / T)^{-1/2};
   // then y_p -= z_p y_r and W[p, :] -= z_p W[r, :] with the pre-update row r.
-  const R invT = R(1) / R(T);
+  const R invT = R(1) / R(per_bin(T));
   bool bad = false;
   for (int r = 0; r < Mb; ++r) {
     Cx<R>* yb = s.yb + (r & 1) * TP;
@@ -243,15 +257,19 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(I
     Cx<R> yr[CPL];
 #pragma unroll
     for (int j = 0; j < CPL; ++j) yr[j] = yb[q + G * j];
+    // With t = phi_p y_r: a_p += y_p conj(t) and d_p += Re(t conj(y_r)), eight
+    // FMA-class operations per row and frame.
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
-      const R pr = cabs2(yr[j]);
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        const Cx<R> sv = cmulc(y[i][j], yr[j]);
-        ar[i] += ph[i][j] * sv.x;
-        ai[i] += ph[i][j] * sv.y;
-        dd[i] += ph[i][j] * pr;
+        const R tx = ph[i][j] * yr[j].x, ty = ph[i][j] * yr[j].y;
+        ar[i] += y[i][j].x * tx;
+        ar[i] += y[i][j].y * ty;
+        ai[i] += y[i][j].y * tx;
+        ai[i] -= y[i][j].x * ty;
+        dd[i] += tx * yr[j].x;
+        dd[i] += ty * yr[j].y;
       }
     }
     Cx<R> z[RPL];
@@ -297,7 +315,25 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(I
       if (p < Mb && c < Mb) a.W[((size_t)f * Mb + p) * Mb + c] = wreg[i][k];
     }
   }
-  epilogue<R, G, CPL, RPL>(a, s, L, f, g, q, y);
+  epilogue<R, G, CPL, RPL>(a, s, L, f, tid, g, q, y);
+}
+
+// Persistent workgroups: each pulls bins from a.work until all F are taken,
+// so every CU keeps its resident workgroups busy regardless of how the
+// dispatcher first placed them.
+template <typename R>
+__device__ __forceinline__ int next_bin(const IterArgs<R>& a, const BinLds<R>& s) {
+  __syncthreads();  // the previous bin's LDS traffic is over
+  if (threadIdx.x == 0) s.misc[0] = atomicAdd(a.work, 1);
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(s.misc[0]);  // uniform: bin addressing stays scalar
+}
+
+template <typename R, int G, int CPL, int RPL>
+__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(IterArgs<R> a, IterLds L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BinLds<R> s = carve<R>(smem, L);
+  for (int f = next_bin(a, s); f < a.F; f = next_bin(a, s)) iss_bin<R, G, CPL, RPL>(a, s, L, f);
 }
 
 // ------------------------------------------------------------------ IP
@@ -355,15 +391,13 @@ __device__ void solve_augmented(Cx<R>* A, Cx<R>* u, Cx<R>* fac, int* misc, int n
 }
 
 template <typename R, int G, int CPL, int RPL>
-__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_ip(IterArgs<R> a, IterLds L) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const BinLds<R> s = carve<R>(smem, L);
-  const int f = blockIdx.x, tid = threadIdx.x, nthr = blockDim.x;
+__device__ void ip_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f) {
+  const int tid = lane_tid(), nthr = blockDim.x;
   const int g = tid / G, q = tid - g * G;
   const int T = a.T, M = a.M, Mb = a.rm.Mb, LX = L.lx, LP = L.lp, Dm1 = a.D - 1, Lm1 = L.lmax - 1;
-  const R invT = R(1) / R(T);
+  const R invT = R(1) / R(per_bin(T));
 
-  load_bin(a, s, L, f);
+  load_bin(a, s, L, f, tid);
 
   for (int r = 0; r < Mb; ++r) {
     const int n = a.rm.src[r], l = a.rm.tap[r];
@@ -419,7 +453,14 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_ip(It
   for (int i = tid; i < Mb * Mb; i += nthr) a.W[(size_t)f * Mb * Mb + i] = s.w[i];
   Cx<R> y[RPL][CPL];
   demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y);
-  epilogue<R, G, CPL, RPL>(a, s, L, f, g, q, y);
+  epilogue<R, G, CPL, RPL>(a, s, L, f, tid, g, q, y);
+}
+
+template <typename R, int G, int CPL, int RPL>
+__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_ip(IterArgs<R> a, IterLds L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BinLds<R> s = carve<R>(smem, L);
+  for (int f = next_bin(a, s); f < a.F; f = next_bin(a, s)) ip_bin<R, G, CPL, RPL>(a, s, L, f);
 }
 
 }  // namespace ctfiss

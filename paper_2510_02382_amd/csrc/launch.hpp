@@ -17,6 +17,7 @@ struct Dims {
 struct Plan {
   int G, CPL, RPL, threads;
   size_t lds;
+  int blocks;  // persistent workgroups launched (resident ones; at most F)
 };
 
 // Type-erased device pointers of one context.
@@ -34,6 +35,7 @@ struct Ptrs {
   void* vden;
   double* nllpart;
   int* status;
+  int* work;
 };
 
 struct VSplit {
@@ -69,6 +71,8 @@ template <typename R>
 hipError_t identity_t(const Dims& d, void* W, hipStream_t s);
 template <typename R>
 bool have_wkernel(int rule, int G, int cpl, int rpl);
+template <typename R>
+int resident_wblocks(int rule, const Plan& p, const Dims& d);
 
 hipError_t launch_zero_status(int* status, hipStream_t s);
 size_t images_lds(const Dims& d);

@@ -67,6 +67,21 @@ bool have_wkernel(int rule, int G, int cpl, int rpl) {
   return pick<R>(rule, G, cpl, rpl) != nullptr;
 }
 
+// Workgroups of the W-update kernel that fit on the device at once.
+template <typename R>
+int resident_wblocks(int rule, const Plan& p, const Dims& d) {
+  WFn<R> fn = pick<R>(rule, p.G, p.CPL, p.RPL);
+  int dev = 0, cus = 0, per_cu = 0;
+  if (!fn || hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (p.lds > 65536 &&
+      hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, p.threads, p.lds) != hipSuccess) return 0;
+  const long long n = (long long)per_cu * cus;
+  return n < 1 ? 0 : (int)(n < d.F ? n : d.F);
+}
+
 template <typename R>
 hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s) {
   WFn<R> fn = pick<R>(rule, p.G, p.CPL, p.RPL);
@@ -80,6 +95,7 @@ hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bo
   a.musq = static_cast<R*>(ptr.musq);
   a.mu = apply_mu ? static_cast<const R*>(ptr.mu) : nullptr;
   a.status = ptr.status;
+  a.work = ptr.work;
   a.F = d.F;
   a.T = d.T;
   a.M = d.M;
@@ -91,7 +107,7 @@ hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bo
     hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, dim3(d.F), dim3(p.threads), L.total, s, a, L);
+  hipLaunchKernelGGL(fn, dim3(p.blocks > 0 ? p.blocks : d.F), dim3(p.threads), L.total, s, a, L);
   return hipGetLastError();
 }
 
@@ -109,6 +125,7 @@ NmfArgs<R> make_nargs(const Dims& d, const VSplit& vs, const Ptrs& ptr, double f
   a.mu = static_cast<R*>(ptr.mu);
   a.mu_prev = apply_mu ? static_cast<const R*>(ptr.mu) : nullptr;
   a.status = ptr.status;
+  a.work = ptr.work;
   a.F = d.F;
   a.T = d.T;
   a.K = d.K;
@@ -230,6 +247,7 @@ hipError_t identity_t(const Dims& d, void* W, hipStream_t s) {
   template hipError_t lambda_t<R>(const Dims&, const Ptrs&, bool, hipStream_t);                               \
   template hipError_t nmfb_t<R>(const Dims&, const Ptrs&, double, bool, hipStream_t);                         \
   template bool have_wkernel<R>(int, int, int, int);                                                          \
+  template int resident_wblocks<R>(int, const Plan&, const Dims&);                                            \
   template hipError_t vpart_t<R>(const Dims&, const VSplit&, const Ptrs&, bool, hipStream_t);                 \
   template hipError_t vfinal_t<R>(const Dims&, const VSplit&, const Ptrs&, double, bool, hipStream_t);        \
   template hipError_t apply_mu_t<R>(const Dims&, const Ptrs&, hipStream_t);                                  \

@@ -23,6 +23,7 @@ struct NmfArgs {
   R* mu;             // [Mb] scale of this iteration (out of k_vfinal)
   const R* mu_prev;  // [Mb] pending scale of the previous iteration, or null
   int* status;
+  int* work;         // bin counter of the W-update kernel, zeroed here by k_lambda
   int F, T, K, nch, fchunk, tap0;
   R floor;
   RowMap rm;
@@ -80,6 +81,7 @@ __global__ void __launch_bounds__(256) k_lambda(NmfArgs<R> a) {
   const int T = a.T, K = a.K, F = a.F;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
   const int n = blockIdx.z, f0 = blockIdx.y * 16, t0 = blockIdx.x * 64 + wave * 16;
+  if (a.work && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *a.work = 0;
   if (t0 >= T) return;
   const int nks = (K + 3) / 4;
   const R sc = pending_scale(a, n);
