@@ -86,7 +86,12 @@ typedef struct {
 
 typedef struct ctfiss_ctx ctfiss_ctx;
 
-/* Bytes of device workspace a context of this shape and precision needs. */
+/* Bytes of device workspace a context of this shape and precision needs: the
+ * state (W, B, V), the per-iteration intermediates (1/lambda, tap-aligned
+ * powers, activation partial sums, row power sums, scales) and the demixed
+ * rows Y = W xbar [F][Mbar][T], which the ISS rule carries from one iteration
+ * to the next instead of recomputing (the sweep and the rescale apply the same
+ * row operations to W and Y, so the two agree up to rounding). */
 int ctfiss_workspace_size(const ctfiss_shape* shape, int precision, size_t* bytes);
 
 /* Create a context.  rule: ctfiss_rule; vrule: ctfiss_vrule; floor >= 0 is

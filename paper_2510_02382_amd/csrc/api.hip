@@ -96,7 +96,7 @@ constexpr size_t kAlign = 256;
 constexpr int kClasses = 7;
 
 struct Layout {
-  size_t W, B, V, ilam, P, P0, musq, mu, vnum, vden, nllpart, status, work, total;
+  size_t W, B, V, ilam, P, P0, musq, mu, vnum, vden, nllpart, status, work, Y, total;
 };
 
 struct TimedLaunch {
@@ -166,6 +166,7 @@ Layout make_layout(const Dims& d, int precision) {
   L.nllpart = take((size_t)d.F * sizeof(double));
   L.status = take(kAlign);
   L.work = take(kAlign);
+  L.Y = take((size_t)d.F * d.Mb * d.T * cs);
   L.total = off;
   return L;
 }
@@ -183,6 +184,7 @@ struct ctfiss_ctx {
   Plan plan;
   VSplit vs;
   bool have_input, have_state;
+  bool y_valid;  // the carried Y holds W xbar of the current W (ISS)
   int prof;  // bit mask of timed kernel classes
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> pool;
@@ -302,7 +304,8 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   c->ptr.nllpart = reinterpret_cast<double*>(c->ws + lay.nllpart);
   c->ptr.status = reinterpret_cast<int*>(c->ws + lay.status);
   c->ptr.work = reinterpret_cast<int*>(c->ws + lay.work);
-  c->have_input = c->have_state = false;
+  c->ptr.Y = c->ws + lay.Y;
+  c->have_input = c->have_state = c->y_valid = false;
   c->prof = 0;
   for (int i = 0; i < kClasses; ++i) {
     c->launches[i] = 0;
@@ -320,6 +323,7 @@ int ctfiss_set_input(ctfiss_ctx* c, const void* X) {
   if (!c || !X) return CTFISS_E_ARG;
   c->ptr.X = X;
   c->have_input = true;
+  c->y_valid = false;
   return CTFISS_OK;
 }
 
@@ -339,6 +343,7 @@ int ctfiss_set_state(ctfiss_ctx* c, const void* W, const void* B, const void* V)
   if (e == hipSuccess) e = launch_zero_status(c->ptr.status, c->stream);
   if (e != hipSuccess) return CTFISS_E_HIP;
   c->have_state = true;
+  c->y_valid = false;
   return CTFISS_OK;
 }
 
@@ -355,8 +360,10 @@ int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
     hipError_t e = timed(c, 5, [&] { return f32 ? lambda_t<float>(d, p, mu, s) : lambda_t<double>(d, p, mu, s); });
     if (e == hipSuccess)
       e = timed(c, 0, [&] {
-        return f32 ? wupdate_t<float>(c->rule, c->plan, d, p, mu, s) : wupdate_t<double>(c->rule, c->plan, d, p, mu, s);
+        return f32 ? wupdate_t<float>(c->rule, c->plan, d, p, mu, c->y_valid, s)
+                   : wupdate_t<double>(c->rule, c->plan, d, p, mu, c->y_valid, s);
       });
+    if (e == hipSuccess && c->rule == CTFISS_RULE_ISS) c->y_valid = true;
     if (e == hipSuccess)
       e = timed(c, 6, [&] {
         return f32 ? nmfb_t<float>(d, p, c->floor, mu, s) : nmfb_t<double>(d, p, c->floor, mu, s);
@@ -370,7 +377,8 @@ int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
     if (e != hipSuccess) return CTFISS_E_HIP;
   }
   if (n_iter > 0) {
-    hipError_t e = timed(c, 3, [&] { return f32 ? apply_mu_t<float>(d, p, s) : apply_mu_t<double>(d, p, s); });
+    const bool sy = c->y_valid;
+    hipError_t e = timed(c, 3, [&] { return f32 ? apply_mu_t<float>(d, p, sy, s) : apply_mu_t<double>(d, p, sy, s); });
     if (e != hipSuccess) return CTFISS_E_HIP;
   }
   return CTFISS_OK;

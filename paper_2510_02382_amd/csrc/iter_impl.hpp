@@ -35,6 +35,8 @@ struct IterArgs {
   const R* mu;      // [Mb] scale of the previous iteration still to apply to W, or null
   int* status;
   int* work;        // bin counter of the persistent workgroups (zeroed before the launch)
+  Cx<R>* Y;         // [F][Mb][T] demixed rows carried between iterations (ISS), or null
+  int yload;        // 1: start from the carried Y (rows scaled by the pending mu), 0: Y = W xbar
   int F, T, M, D, K;
   RowMap rm;
 };
@@ -95,7 +97,8 @@ __device__ __forceinline__ int per_bin(int v) {
 
 // Stage 1: scaled W_f, zero-padded observation block and inverse variances into LDS.
 template <typename R>
-__device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid) {
+__device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid,
+                         bool need_x) {
   const int nthr = blockDim.x;
   const int T = a.T, M = a.M, F = a.F, Mb = per_bin(a.rm.Mb), N = a.rm.N;
   const int LX = per_bin(L.lx), LP = per_bin(L.lp), TP = L.tp, Dm1 = a.D - 1, Lm1 = L.lmax - 1;
@@ -109,7 +112,7 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
     }
     s.w[i] = w;
   }
-  for (int i = tid; i < M * LX; i += nthr) {
+  for (int i = tid; i < (need_x ? M * LX : 0); i += nthr) {
     const int m = i / LX, t = i - m * LX - Dm1;
     s.x[i] = (t >= 0 && t < T) ? a.X[((size_t)m * F + f) * T + t] : Cx<R>{R(0), R(0)};
   }
@@ -162,6 +165,29 @@ __device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>
   }
 }
 
+// Stage 2 (carried): the lane's rows and frames of the stored Y, divided by the
+// pending row scale exactly as W is in load_bin; zero for t >= T.
+template <typename R, int G, int CPL, int RPL>
+__device__ __forceinline__ void load_rows(const IterArgs<R>& a, int f, int g, int q, Cx<R> (&y)[RPL][CPL]) {
+  const int T = a.T, Mb = a.rm.Mb;
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int p = g * RPL + i;
+    const bool ok = p < Mb;
+    const R m = (ok && a.mu) ? a.mu[p] : R(1);
+    const Cx<R>* yr = a.Y + ((size_t)f * Mb + (ok ? p : 0)) * T + q;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      Cx<R> v = (ok && q + G * j < T) ? yr[G * j] : Cx<R>{R(0), R(0)};
+      if (a.mu) {
+        v.x = v.x / m;
+        v.y = v.y / m;
+      }
+      y[i][j] = v;
+    }
+  }
+}
+
 // Stage 4: |y|^2 row sums and rows into LDS, then the tap-aligned powers
 // P_n[t] = sum_{l < L_n, t + l < T} |y_{(n,l)}[t + l]|^2 summed in tap order
 // (bitwise reproducible), P / P0 out.  Starts with a barrier: the |y|^2 rows
@@ -206,10 +232,17 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
   const int T = a.T, Mb = a.rm.Mb, TP = L.tp, LP = L.lp, Lm1 = L.lmax - 1;
   constexpr int WPL = (kMaxRows + G - 1) / G;
 
-  load_bin(a, s, L, f, tid);
+  load_bin(a, s, L, f, tid, !a.yload);
 
+  // Y = W xbar equals the previous iteration's Y with rows divided by mu: the
+  // sweep applies the same rank-1 steps to W and Y, and the rescale divides the
+  // rows of both.  Carrying it replaces the demix contraction (Mbar^2 complex
+  // MACs per frame) by one read and one write of Y.
   Cx<R> y[RPL][CPL];
-  demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y);
+  if (a.yload)
+    load_rows<R, G, CPL, RPL>(a, f, g, q, y);
+  else
+    demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y);
 
   Cx<R> wreg[RPL][WPL];
   R ph[RPL][CPL];  // weights of the lane's rows and frames, phi[n][t - l]
@@ -314,6 +347,12 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
       const int c = q + G * k;
       if (p < Mb && c < Mb) a.W[((size_t)f * Mb + p) * Mb + c] = wreg[i][k];
     }
+    if (a.Y && p < Mb) {
+      Cx<R>* yr = a.Y + ((size_t)f * Mb + p) * T + q;
+#pragma unroll
+      for (int j = 0; j < CPL; ++j)
+        if (q + G * j < T) yr[G * j] = y[i][j];
+    }
   }
   epilogue<R, G, CPL, RPL>(a, s, L, f, tid, g, q, y);
 }
@@ -397,7 +436,7 @@ __device__ void ip_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& 
   const int T = a.T, M = a.M, Mb = a.rm.Mb, LX = L.lx, LP = L.lp, Dm1 = a.D - 1, Lm1 = L.lmax - 1;
   const R invT = R(1) / R(per_bin(T));
 
-  load_bin(a, s, L, f, tid);
+  load_bin(a, s, L, f, tid, true);
 
   for (int r = 0; r < Mb; ++r) {
     const int n = a.rm.src[r], l = a.rm.tap[r];

@@ -36,6 +36,7 @@ struct Ptrs {
   double* nllpart;
   int* status;
   int* work;
+  void* Y;  // [F][Mb][T] carried demixed rows (ISS)
 };
 
 struct VSplit {
@@ -52,7 +53,7 @@ VSplit choose_vsplit(const Dims& d);
 
 // Typed launchers, defined once per precision.
 template <typename R>
-hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s);
+hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload, hipStream_t s);
 template <typename R>
 hipError_t lambda_t(const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s);
 template <typename R>
@@ -62,7 +63,7 @@ hipError_t vpart_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, bool tap0, 
 template <typename R>
 hipError_t vfinal_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0, hipStream_t s);
 template <typename R>
-hipError_t apply_mu_t(const Dims& d, const Ptrs& ptr, hipStream_t s);
+hipError_t apply_mu_t(const Dims& d, const Ptrs& ptr, bool scale_y, hipStream_t s);
 template <typename R>
 hipError_t images_t(const Dims& d, const Ptrs& ptr, void* C, hipStream_t s);
 template <typename R>

@@ -83,7 +83,7 @@ int resident_wblocks(int rule, const Plan& p, const Dims& d) {
 }
 
 template <typename R>
-hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s) {
+hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload, hipStream_t s) {
   WFn<R> fn = pick<R>(rule, p.G, p.CPL, p.RPL);
   if (!fn) return hipErrorInvalidValue;
   IterArgs<R> a;
@@ -96,6 +96,8 @@ hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bo
   a.mu = apply_mu ? static_cast<const R*>(ptr.mu) : nullptr;
   a.status = ptr.status;
   a.work = ptr.work;
+  a.Y = rule == 0 ? static_cast<Cx<R>*>(ptr.Y) : nullptr;
+  a.yload = (rule == 0 && yload) ? 1 : 0;
   a.F = d.F;
   a.T = d.T;
   a.M = d.M;
@@ -174,10 +176,11 @@ hipError_t vfinal_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, double flo
 }
 
 template <typename R>
-hipError_t apply_mu_t(const Dims& d, const Ptrs& ptr, hipStream_t s) {
-  const size_t n = (size_t)d.F * d.Mb * d.Mb + (size_t)d.N * d.F * d.K;
+hipError_t apply_mu_t(const Dims& d, const Ptrs& ptr, bool scale_y, hipStream_t s) {
+  const size_t n = (size_t)d.F * d.Mb * d.Mb + (size_t)d.N * d.F * d.K + (scale_y ? (size_t)d.F * d.Mb * d.T : 0);
   hipLaunchKernelGGL(k_apply_mu<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                     static_cast<Cx<R>*>(ptr.W), static_cast<R*>(ptr.B), static_cast<const R*>(ptr.mu), d.F, d.K,
+                     static_cast<Cx<R>*>(ptr.W), static_cast<R*>(ptr.B),
+                     scale_y ? static_cast<Cx<R>*>(ptr.Y) : nullptr, static_cast<const R*>(ptr.mu), d.F, d.T, d.K,
                      d.rm);
   return hipGetLastError();
 }
@@ -243,14 +246,14 @@ hipError_t identity_t(const Dims& d, void* W, hipStream_t s) {
 }
 
 #define CTFISS_INSTANTIATE(R)                                                                                  \
-  template hipError_t wupdate_t<R>(int, const Plan&, const Dims&, const Ptrs&, bool, hipStream_t);             \
+  template hipError_t wupdate_t<R>(int, const Plan&, const Dims&, const Ptrs&, bool, bool, hipStream_t);       \
   template hipError_t lambda_t<R>(const Dims&, const Ptrs&, bool, hipStream_t);                               \
   template hipError_t nmfb_t<R>(const Dims&, const Ptrs&, double, bool, hipStream_t);                         \
   template bool have_wkernel<R>(int, int, int, int);                                                          \
   template int resident_wblocks<R>(int, const Plan&, const Dims&);                                            \
   template hipError_t vpart_t<R>(const Dims&, const VSplit&, const Ptrs&, bool, hipStream_t);                 \
   template hipError_t vfinal_t<R>(const Dims&, const VSplit&, const Ptrs&, double, bool, hipStream_t);        \
-  template hipError_t apply_mu_t<R>(const Dims&, const Ptrs&, hipStream_t);                                  \
+  template hipError_t apply_mu_t<R>(const Dims&, const Ptrs&, bool, hipStream_t);                            \
   template hipError_t images_t<R>(const Dims&, const Ptrs&, void*, hipStream_t);                             \
   template hipError_t nll_t<R>(const Dims&, const Ptrs&, hipStream_t);                                       \
   template hipError_t identity_t<R>(const Dims&, void*, hipStream_t);

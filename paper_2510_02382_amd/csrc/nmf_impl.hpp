@@ -330,11 +330,13 @@ __global__ void __launch_bounds__(256) k_vfinal(NmfArgs<R> a, int nvblocks) {
   a.V[i] = v > a.floor ? v : a.floor;
 }
 
-// W row r /= mu_r and b_n /= mu_{(n,0)}^2, Eqs. (20)-(21) applied to W and b.
+// W row r /= mu_r and b_n /= mu_{(n,0)}^2, Eqs. (20)-(21) applied to W and b;
+// row r of the carried Y (when given) /= mu_r, keeping Y = W xbar.
 template <typename R>
-__global__ void __launch_bounds__(256) k_apply_mu(Cx<R>* W, R* B, const R* mu, int F, int K, RowMap rm) {
+__global__ void __launch_bounds__(256) k_apply_mu(Cx<R>* W, R* B, Cx<R>* Y, const R* mu, int F, int T, int K,
+                                                  RowMap rm) {
   const int Mb = rm.Mb, N = rm.N;
-  const size_t nw = (size_t)F * Mb * Mb, nb = (size_t)N * F * K;
+  const size_t nw = (size_t)F * Mb * Mb, nb = (size_t)N * F * K, ny = Y ? (size_t)F * Mb * T : 0;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nw) {
     const R m = mu[(i / Mb) % Mb];
@@ -345,6 +347,11 @@ __global__ void __launch_bounds__(256) k_apply_mu(Cx<R>* W, R* B, const R* mu, i
     const int n = (int)(j / ((size_t)F * K));
     const R m = mu[rm.r0[n]];
     B[j] = B[j] * (R(1) / (m * m));  // the same rounding as pending_scale
+  } else if (i < nw + nb + ny) {
+    const size_t j = i - nw - nb;
+    const R m = mu[(j / T) % Mb];
+    Cx<R> y = Y[j];
+    Y[j] = Cx<R>{y.x / m, y.y / m};
   }
 }
 
