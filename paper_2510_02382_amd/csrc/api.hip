@@ -57,6 +57,17 @@ bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
     list = prec == 0 ? kIp32 : kIp64;
     n = prec == 0 ? (int)(sizeof(kIp32) / sizeof(GR)) : (int)(sizeof(kIp64) / sizeof(GR));
   }
+  // FP32 ISS: 32-lane groups when they need at most 10 frames per lane.  The
+  // workgroup then has 3 waves per SIMD for Mbar = 24 (a 16-lane one has 2 on
+  // two SIMDs and 1 on the others) and two fit per CU, which shortens a bin's
+  // latency and the tail of the bin loop.
+  if (rule == 0 && prec == 0) {
+    Plan p;
+    if (plan_for(prec, rule, d, max_lds, 32, 1, 0, &p) && p.CPL <= 10) {
+      *out = p;
+      return true;
+    }
+  }
   for (int i = 0; i < n; ++i)
     if (plan_for(prec, rule, d, max_lds, list[i].G, list[i].RPL, 0, out)) return true;
   return false;

@@ -120,6 +120,12 @@ __device__ __forceinline__ bool finite_pos(R v) {
 __host__ __device__ constexpr int iter_need_vgprs(int rsize, int cpl, int rpl) {
   return rpl * (2 * cpl + 8) * (rsize / 4) + 40;
 }
+// Occupancy target of the ISS kernel (minimum waves per SIMD): FP32 with one
+// row per lane group and at most 10 frames per lane fits in 80 VGPRs, so two
+// 12-wave workgroups (G = 32) share a CU; elsewhere the launch bound decides.
+__host__ __device__ constexpr int iter_min_waves(int rsize, int cpl, int rpl) {
+  return (rsize == 4 && rpl == 1 && cpl <= 10) ? 6 : 1;
+}
 __host__ __device__ constexpr int iter_max_threads(int rsize, int cpl, int rpl) {
   return (512 / iter_need_vgprs(rsize, cpl, rpl)) * 256 > 1024 ? 1024
                                                                 : (512 / iter_need_vgprs(rsize, cpl, rpl)) * 256;

@@ -369,7 +369,8 @@ __device__ __forceinline__ int next_bin(const IterArgs<R>& a, const BinLds<R>& s
 }
 
 template <typename R, int G, int CPL, int RPL>
-__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss(IterArgs<R> a, IterLds L) {
+__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_min_waves(sizeof(R), CPL, RPL))
+    k_iss(IterArgs<R> a, IterLds L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
   for (int f = next_bin(a, s); f < a.F; f = next_bin(a, s)) iss_bin<R, G, CPL, RPL>(a, s, L, f);

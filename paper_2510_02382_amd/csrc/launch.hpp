@@ -44,7 +44,7 @@ struct VSplit {
 };
 
 // Instantiated launch shapes.
-constexpr int kCpl32[] = {4, 8, 12, 16, 20, 24, 28, 32};
+constexpr int kCpl32[] = {4, 8, 10, 12, 16, 20, 24, 28, 32};
 constexpr int kCpl64[] = {4, 6, 8, 10, 12, 16};
 
 bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out);

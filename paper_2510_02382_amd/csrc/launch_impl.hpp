@@ -24,6 +24,7 @@ WFn<R> pick_cpl(int rule, int cpl) {
     switch (cpl) {
       case 4: return wfn<R, G, 4, RPL>(rule);
       case 8: return wfn<R, G, 8, RPL>(rule);
+      case 10: return wfn<R, G, 10, RPL>(rule);
       case 12: return wfn<R, G, 12, RPL>(rule);
       case 16: return wfn<R, G, 16, RPL>(rule);
       case 20: return wfn<R, G, 20, RPL>(rule);

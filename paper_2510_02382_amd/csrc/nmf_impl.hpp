@@ -179,6 +179,7 @@ __global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) {
   }
   if (wave != 0) return;
   const R sc = pending_scale(a, n);
+  bool bad = false;
 #pragma unroll
   for (int kt = 0; kt < KT; ++kt) {
     if (kt >= nkt) continue;
@@ -188,11 +189,12 @@ __global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) {
       if (f < F && k < K) {
         const size_t o = ((size_t)n * F + f) * K + k;
         R b = a.B[o] * sc * sqrt(red[0][kt][v][l] / red[1][kt][v][l]);
-        if (!isfinite(b)) latch(a.status, kFaultMu);
+        bad |= !isfinite(b);
         a.B[o] = b > a.floor ? b : a.floor;
       }
     }
   }
+  latch_wave(a.status, bad, kFaultMu);  // one atomic per wave, not per lane
 }
 
 // Partial sums over one chunk of bins of
