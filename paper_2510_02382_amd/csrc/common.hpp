@@ -138,7 +138,14 @@ __host__ __device__ constexpr int iter_max_threads(int rsize, int cpl, int rpl) 
 struct IterLds {
   size_t x, w, phi, yb, wb, q, aug, u, fac, a, misc, total;
   int lx, lp, tp, lmax;
+  int rc;  // IP: rows whose inverse weighted covariances are held at once
 };
+
+// LDS one workgroup may use on gfx950.
+constexpr size_t kMaxLdsBytes = 163840;
+// Rows per run of inverse weighted covariances: their accumulators live in
+// registers (6 complex doubles or 12 complex floats).
+__host__ __device__ constexpr int ip_max_chunk(int rsize) { return rsize == 8 ? 6 : 12; }
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -155,15 +162,31 @@ __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, 
   L.x = off; off += align_up((size_t)M * L.lx * cs, 16);
   L.w = off; off += align_up((size_t)Mb * Mb * cs, 16);
   L.phi = off; off += align_up((size_t)N * L.lp * rsize, 16);
-  L.yb = off; off += align_up((size_t)2 * L.tp * cs, 16);
-  L.wb = off; off += align_up((size_t)2 * Mb * cs, 16);
+  if (!ip) {  // the ISS broadcasts of y_r and w_r
+    L.yb = off; off += align_up((size_t)2 * L.tp * cs, 16);
+    L.wb = off; off += align_up((size_t)2 * Mb * cs, 16);
+  } else {
+    L.yb = L.wb = 0;
+  }
   if (ip) {
-    L.q = off; off += align_up((size_t)Mb * Mb * cs, 16);
-    L.aug = off; off += align_up((size_t)Mb * (Mb + 1) * cs, 16);
-    L.u = off; off += align_up((size_t)Mb * cs, 16);
-    L.fac = off; off += align_up((size_t)(Mb + 1) * cs, 16);
+    // aug: H = W^{-1} [Mb][Mb]; u: four Mb-vectors; fac: one Mb column per
+    // wave; q: rc matrices [Mb][Mb] (the inverse weighted covariances, and
+    // the scratch of the first inversion), rc as large as LDS allows.
+    const int waves = (Mb * G + 63) / 64;
+    L.aug = off; off += align_up((size_t)Mb * Mb * cs, 16);
+    L.u = off; off += align_up((size_t)4 * Mb * cs, 16);
+    L.fac = off; off += align_up((size_t)waves * Mb * cs, 16);
+    L.q = off;
+    const size_t mat = align_up((size_t)Mb * Mb * cs, 16);
+    const size_t room = kMaxLdsBytes > off + 64 ? kMaxLdsBytes - off - 64 : 0;  // 64: misc
+    int rc = (int)(room / mat);
+    if (rc > lmax) rc = lmax;
+    if (rc > ip_max_chunk(rsize)) rc = ip_max_chunk(rsize);
+    L.rc = rc < 1 ? 1 : rc;
+    off += (size_t)L.rc * mat;
   } else {
     L.q = L.aug = L.u = L.fac = 0;
+    L.rc = 0;
   }
   L.a = 0;
   const size_t asz = align_up((size_t)Mb * L.tp * rsize, 16);

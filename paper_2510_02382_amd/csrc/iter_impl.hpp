@@ -101,7 +101,7 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
                          bool need_x) {
   const int nthr = blockDim.x;
   const int T = a.T, M = a.M, F = a.F, Mb = per_bin(a.rm.Mb), N = a.rm.N;
-  const int LX = per_bin(L.lx), LP = per_bin(L.lp), TP = L.tp, Dm1 = a.D - 1, Lm1 = L.lmax - 1;
+  const int LX = per_bin(L.lx), LP = per_bin(L.lp), Dm1 = a.D - 1, Lm1 = L.lmax - 1;
   const Cx<R>* Wf = a.W + (size_t)f * Mb * Mb;
   for (int i = tid; i < Mb * Mb; i += nthr) {
     Cx<R> w = Wf[i];
@@ -120,7 +120,6 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
     const int n = i / LP, t = i - n * LP - Lm1;
     s.phi[i] = (t >= 0 && t < T) ? a.ilam[((size_t)n * F + f) * T + t] : R(0);
   }
-  for (int i = tid; i < 2 * TP; i += nthr) s.yb[i] = Cx<R>{R(0), R(0)};
   __syncthreads();
 }
 
@@ -377,117 +376,291 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_mi
 }
 
 // ------------------------------------------------------------------ IP
-// Solves A u = rhs for the n x n system stored as the n x (n+1) augmented
-// matrix A (row-major, LDS) by Gaussian elimination with partial pivoting.
+// The update of Eqs. (9)-(10) for row r, u = (W Q_r)^{-1} e_r normalised by
+// (u^H Q_r u)^{-1/2}, is evaluated as u = Q_r^{-1} h_r with h_r = W^{-1} e_r,
+// and u^H Q_r u = h_r^H u (the same quantities in exact arithmetic).  Q_r
+// does not depend on W, so the inverse weighted covariances of a run of rows
+// of one source are formed and inverted together (one matrix per wave); H =
+// W^{-1} is inverted once per bin and kept current across the sweep by the
+// Sherman-Morrison update for a changed row of W.
+
+// Orders the LDS accesses of one wave (its lanes then see each other's writes).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename R>
-__device__ void solve_augmented(Cx<R>* A, Cx<R>* u, Cx<R>* fac, int* misc, int n, int* status) {
-  const int tid = threadIdx.x, nthr = blockDim.x, ld = n + 1;
+__device__ __forceinline__ Cx<R> crecip(Cx<R> v) {
+  const R d = cabs2(v);
+  return Cx<R>{v.x / d, -v.y / d};
+}
+
+// In-place Gauss-Jordan inversion of the n x n matrix A (LDS, row-major) by
+// one wave; col is an n-vector of LDS scratch.  pivot: partial pivoting by
+// row exchanges, undone as column exchanges at the end (perm: n ints of LDS);
+// without it the matrix must be Hermitian positive definite (then every pivot
+// is real and positive up to rounding).  Returns false on a non-positive or
+// non-finite pivot.
+template <typename R, bool PIVOT>
+__device__ bool wave_invert(Cx<R>* A, Cx<R>* col, int* perm, int n) {
+  const int lane = threadIdx.x & 63;
+  bool ok = true;
   for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      int piv = k;
-      R best = cabs2(A[k * ld + k]);
-      for (int i = k + 1; i < n; ++i) {
-        const R v = cabs2(A[i * ld + k]);
+    if (PIVOT) {
+      // argmax_{i >= k} |A[i][k]|^2, lowest index on ties
+      R best = R(-1);
+      int arg = k;
+      for (int i0 = k; i0 < n; i0 += 64) {
+        const int i = i0 + lane;
+        R v = i < n ? cabs2(A[i * n + k]) : R(-1);
+        int idx = i;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const R ov = __shfl_xor(v, off);
+          const int oi = __shfl_xor(idx, off);
+          if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+          }
+        }
         if (v > best) {
           best = v;
-          piv = i;
+          arg = idx;
         }
       }
-      if (!finite_pos(best)) latch(status, kFaultIpSingular);
-      misc[0] = piv;
+      ok &= finite_pos(best);
+      if (lane == 0) perm[k] = arg;
+      if (arg != k) {
+        for (int j = lane; j < n; j += 64) {
+          const Cx<R> t = A[k * n + j];
+          A[k * n + j] = A[arg * n + j];
+          A[arg * n + j] = t;
+        }
+      }
+      wave_sync();
     }
-    __syncthreads();
-    const int piv = misc[0];
-    if (piv != k) {
-      for (int j = k + tid; j <= n; j += nthr) {
-        const Cx<R> t = A[k * ld + j];
-        A[k * ld + j] = A[piv * ld + j];
-        A[piv * ld + j] = t;
+    const Cx<R> piv = A[k * n + k];
+    if (PIVOT)
+      ok &= finite_pos(cabs2(piv));
+    else
+      ok &= finite_pos(piv.x);
+    const Cx<R> p = crecip(piv);
+    for (int i = lane; i < n; i += 64) col[i] = A[i * n + k];
+    wave_sync();
+    for (int j = lane; j < n; j += 64) A[k * n + j] = cmul(j == k ? Cx<R>{R(1), R(0)} : A[k * n + j], p);
+    wave_sync();
+    // lane: column j, rows [ib, ie) (two lanes per column when n <= 32); the
+    // loads of 4 rows are issued before their stores, so a lane waits for LDS
+    // once per 4 rows instead of once per entry.
+    {
+      const bool two = n <= 32;
+      const int j = two ? (lane & 31) : lane, hn = two ? (n + 1) / 2 : n;
+      const int ib = two ? (lane >> 5) * hn : 0, ie = ib + hn < n ? ib + hn : n;
+      if (j < n) {
+        const Cx<R> pr = A[k * n + j];
+        for (int i0 = ib; i0 < ie; i0 += 4) {
+          Cx<R> av[4], cv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u < ie ? i0 + u : ie - 1;
+            av[u] = A[i * n + j];
+            cv[u] = col[i];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u;
+            if (i < ie && i != k) A[i * n + j] = cfms(cv[u], pr, j == k ? Cx<R>{R(0), R(0)} : av[u]);
+          }
+        }
       }
     }
-    __syncthreads();
-    const Cx<R> pv = A[k * ld + k];
-    const R den = cabs2(pv);
-    const Cx<R> inv{pv.x / den, -pv.y / den};
-    for (int i = k + 1 + tid; i < n; i += nthr) fac[i] = cmul(A[i * ld + k], inv);
-    __syncthreads();
-    const int w = n - k;  // columns k+1 .. n
-    for (int e = tid; e < (n - k - 1) * w; e += nthr) {
-      const int i = k + 1 + e / w, j = k + 1 + e % w;
-      A[i * ld + j] = cfms(fac[i], A[k * ld + j], A[i * ld + j]);
-    }
-    __syncthreads();
+    wave_sync();
   }
-  if (tid == 0) {
-    for (int i = n - 1; i >= 0; --i) {
-      Cx<R> acc = A[i * ld + n];
-      for (int j = i + 1; j < n; ++j) acc = cfms(A[i * ld + j], u[j], acc);
-      const Cx<R> pv = A[i * ld + i];
-      const R den = cabs2(pv);
-      u[i] = Cx<R>{(acc.x * pv.x + acc.y * pv.y) / den, (acc.y * pv.x - acc.x * pv.y) / den};
+  if (PIVOT) {
+    for (int k = n - 1; k >= 0; --k) {
+      const int q = perm[k];
+      if (q != k)
+        for (int i = lane; i < n; i += 64) {
+          const Cx<R> t = A[i * n + k];
+          A[i * n + k] = A[i * n + q];
+          A[i * n + q] = t;
+        }
+      wave_sync();
     }
   }
-  __syncthreads();
+  return ok;
+}
+
+// Entry e (row-major upper triangle, i <= j) of the weighted covariances of
+// rows c0 .. c0 + rc - 1 (taps) of source n, summed over frames [t0, t1):
+// acc[c] = sum_t phi_n[t - (c0 + c)] xbar_i[t] conj(xbar_j[t]) (phi is zero for t < tap).
+template <typename R>
+__device__ __forceinline__ void ip_cov_entry(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int n,
+                                             int c0, int rc, int e, int t0, int t1, int& i, int& j,
+                                             Cx<R> (&acc)[ip_max_chunk(sizeof(R))]) {
+  const int Mb = a.rm.Mb, M = a.M, LX = L.lx, Dm1 = a.D - 1;
+  i = 0;
+  while (e >= Mb - i) {
+    e -= Mb - i;
+    ++i;
+  }
+  j = i + e;
+  const int di = i / M, mi = i - di * M, dj = j / M, mj = j - dj * M;
+  const Cx<R>* xi = s.x + mi * LX + Dm1 - di;
+  const Cx<R>* xj = s.x + mj * LX + Dm1 - dj;
+  const R* ph = s.phi + n * L.lp + L.lmax - 1 - c0;  // ph[t - c] = phi_n[t - (c0 + c)]
+#pragma unroll
+  for (int c = 0; c < ip_max_chunk(sizeof(R)); ++c) acc[c] = Cx<R>{R(0), R(0)};
+  constexpr int CM = ip_max_chunk(sizeof(R));
+  if (rc == CM) {  // full run: constant offsets, no selects
+    for (int t = t0; t < t1; ++t) {
+      const Cx<R> pr = cmulc(xi[t], xj[t]);
+      R w[CM];
+#pragma unroll
+      for (int c = 0; c < CM; ++c) w[c] = ph[t - c];
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        acc[c].x += w[c] * pr.x;
+        acc[c].y += w[c] * pr.y;
+      }
+    }
+    return;
+  }
+  // Branch-free over the run: rows c >= rc read row rc - 1's weight (in range)
+  // and add it times 0, so the weight loads of a frame are issued together.
+  for (int t = t0; t < t1; ++t) {
+    const Cx<R> pr = cmulc(xi[t], xj[t]);
+    R w[ip_max_chunk(sizeof(R))];
+#pragma unroll
+    for (int c = 0; c < ip_max_chunk(sizeof(R)); ++c) w[c] = ph[t - (c < rc ? c : rc - 1)];
+#pragma unroll
+    for (int c = 0; c < ip_max_chunk(sizeof(R)); ++c) {
+      const R wc = c < rc ? w[c] : R(0);
+      acc[c].x += wc * pr.x;
+      acc[c].y += wc * pr.y;
+    }
+  }
+}
+
+// Writes (add: adds to) entries (i, j) and (j, i) of the rc covariances, scaled by 1/T.
+template <typename R>
+__device__ __forceinline__ void ip_cov_store(const BinLds<R>& s, int Mb, int rc, int i, int j, bool add, R invT,
+                                             const Cx<R> (&acc)[ip_max_chunk(sizeof(R))]) {
+#pragma unroll
+  for (int c = 0; c < ip_max_chunk(sizeof(R)); ++c) {
+    if (c < rc) {
+      Cx<R>* Q = s.q + (size_t)c * Mb * Mb;
+      Cx<R> v{acc[c].x * invT, acc[c].y * invT};
+      if (add) v = cadd(Q[i * Mb + j], v);  // frame ranges added in order
+      Q[i * Mb + j] = v;
+      if (i != j) Q[j * Mb + i] = Cx<R>{v.x, -v.y};
+    }
+  }
 }
 
 template <typename R, int G, int CPL, int RPL>
 __device__ void ip_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f) {
-  const int tid = lane_tid(), nthr = blockDim.x;
+  const int tid = lane_tid(), nthr = blockDim.x, wave = tid >> 6, lane = tid & 63, nwave = (nthr + 63) >> 6;
   const int g = tid / G, q = tid - g * G;
-  const int T = a.T, M = a.M, Mb = a.rm.Mb, LX = L.lx, LP = L.lp, Dm1 = a.D - 1, Lm1 = L.lmax - 1;
-  const R invT = R(1) / R(per_bin(T));
+  const int T = per_bin(a.T), M = per_bin(a.M), Mb = per_bin(a.rm.Mb), LX = L.lx, LP = L.lp;
+  const int Dm1 = a.D - 1, Lm1 = L.lmax - 1;
+  const R invT = R(1) / R(T);
+  Cx<R>* H = s.aug;                 // [Mb][Mb] W^{-1}
+  Cx<R>* hv = s.u;                  // column r of H before its update
+  Cx<R>* dv = s.u + Mb;             // new row r of W minus the old one
+  Cx<R>* gv = s.u + 2 * Mb;         // dv^T H
+  Cx<R>* colw = s.fac + wave * Mb;  // this wave's column scratch
+  bool bad = false;
 
   load_bin(a, s, L, f, tid, true);
-
-  for (int r = 0; r < Mb; ++r) {
-    const int n = a.rm.src[r], l = a.rm.tap[r];
-    const R* phr = s.phi + n * LP + Lm1 - l;  // phr[t] = 1/lambda_{n, t - l}, 0 for t < l
-    // Q_r = (1/T) sum_t phi_r xbar xbar^H, Eq. (8): upper triangle, mirrored.
-    for (int e = tid; e < Mb * Mb; e += nthr) {
-      const int i = e / Mb, j = e - (e / Mb) * Mb;
-      if (i > j) continue;
-      const int di = i / M, mi = i - di * M, dj = j / M, mj = j - dj * M;
-      const Cx<R>* xi = s.x + mi * LX + Dm1 - di;
-      const Cx<R>* xj = s.x + mj * LX + Dm1 - dj;
-      R accx = 0, accy = 0;
-      for (int t = l; t < T; ++t) {
-        const Cx<R> pr = cmulc(xi[t], xj[t]);
-        accx += phr[t] * pr.x;
-        accy += phr[t] * pr.y;
-      }
-      s.q[i * Mb + j] = Cx<R>{accx * invT, accy * invT};
-      if (i != j) s.q[j * Mb + i] = Cx<R>{accx * invT, -accy * invT};
-    }
-    __syncthreads();
-    // [W Q_r | e_r]
-    for (int e = tid; e < Mb * Mb; e += nthr) {
-      const int i = e / Mb, j = e - (e / Mb) * Mb;
-      Cx<R> acc{R(0), R(0)};
-      for (int k = 0; k < Mb; ++k) acc = cfma(s.w[i * Mb + k], s.q[k * Mb + j], acc);
-      s.aug[i * (Mb + 1) + j] = acc;
-    }
-    for (int i = tid; i < Mb; i += nthr) s.aug[i * (Mb + 1) + Mb] = Cx<R>{R(i == r ? 1 : 0), R(0)};
-    __syncthreads();
-    // u = (W Q_r)^{-1} e_r, Eq. (9)
-    solve_augmented(s.aug, s.u, s.fac, s.misc, Mb, a.status);
-    // u <- u (u^H Q_r u)^{-1/2}, Eq. (10); row r of W becomes u^H
-    for (int i = tid; i < Mb; i += nthr) {
-      Cx<R> acc{R(0), R(0)};
-      for (int j = 0; j < Mb; ++j) acc = cfma(s.q[i * Mb + j], s.u[j], acc);
-      s.fac[i] = cmulc(acc, s.u[i]);  // conj(u_i) (Q u)_i
-    }
-    __syncthreads();
-    if (tid == 0) {
-      R sum = 0;
-      for (int i = 0; i < Mb; ++i) sum += s.fac[i].x;
-      if (!finite_pos(sum)) latch(a.status, kFaultIpSingular);
-      s.fac[Mb].x = R(1) / sqrt(sum);
-    }
-    __syncthreads();
-    const R sc = s.fac[Mb].x;
-    for (int c = tid; c < Mb; c += nthr) s.w[r * Mb + c] = Cx<R>{s.u[c].x * sc, -s.u[c].y * sc};
-    __syncthreads();
+  // H = W^{-1} (one wave, partial pivoting); the pivot order goes to the q region
+  if (wave == 0) {
+    for (int e = lane; e < Mb * Mb; e += 64) H[e] = s.w[e];
+    wave_sync();
+    bad |= !wave_invert<R, true>(H, colw, reinterpret_cast<int*>(s.q), Mb);
   }
+  __syncthreads();
+
+  const int U = Mb * (Mb + 1) / 2;
+  int ts_n = nthr / U;
+  ts_n = ts_n < 1 ? 1 : (ts_n > 4 ? 4 : ts_n);
+  for (int n = 0; n < a.rm.N; ++n) {
+    const int Ln = a.rm.L[n];
+    for (int c0 = 0; c0 < Ln; c0 += L.rc) {
+      const int rc = Ln - c0 < L.rc ? Ln - c0 : L.rc;
+      // Q_{(n, c0 + c)}[i][j] = (1/T) sum_{t >= l} phi_n[t - l] xbar_i[t] conj(xbar_j[t]), l = c0 + c,
+      // Eq. (8): one product xbar_i conj(xbar_j) per frame serves every row of the run.
+      // ts_n > 1: thread tid < U ts_n takes entry tid % U over frame range tid / U, and
+      // the ranges are added in order (every thread passes the same barriers);
+      // ts_n = 1: threads loop over the entries.
+      if (ts_n > 1) {
+        const bool act = tid < U * ts_n;
+        const int ts = act ? tid / U : 0, e = act ? tid - ts * U : 0;
+        Cx<R> acc[ip_max_chunk(sizeof(R))];
+        int i = 0, j = 0;
+        if (act) ip_cov_entry<R>(a, s, L, n, c0, rc, e, ts * T / ts_n, (ts + 1) * T / ts_n, i, j, acc);
+        for (int s2 = 0; s2 < ts_n; ++s2) {
+          if (act && ts == s2) ip_cov_store<R>(s, Mb, rc, i, j, s2 > 0, invT, acc);
+          __syncthreads();
+        }
+      } else {
+        for (int e = tid; e < U; e += nthr) {
+          Cx<R> acc[ip_max_chunk(sizeof(R))];
+          int i = 0, j = 0;
+          ip_cov_entry<R>(a, s, L, n, c0, rc, e, 0, T, i, j, acc);
+          ip_cov_store<R>(s, Mb, rc, i, j, false, invT, acc);
+        }
+      }
+      __syncthreads();
+      // invert the rc weighted covariances, one per wave
+      for (int c = wave; c < rc; c += nwave) bad |= !wave_invert<R, false>(s.q + (size_t)c * Mb * Mb, colw, nullptr, Mb);
+      __syncthreads();
+
+      for (int c = 0; c < rc; ++c) {
+        const int r = a.rm.r0[n] + c0 + c;
+        const Cx<R>* Qi = s.q + (size_t)c * Mb * Mb;
+        if (wave == 0) {
+          // u = Q_r^{-1} h_r, s = h_r^H u, new row r = conj(u) / sqrt(s)
+          Cx<R> u{R(0), R(0)}, hr{R(0), R(0)};
+          if (lane < Mb) {
+            hr = H[lane * Mb + r];
+            for (int k = 0; k < Mb; ++k) u = cfma(Qi[lane * Mb + k], H[k * Mb + r], u);
+          }
+          const R sp = lane < Mb ? hr.x * u.x + hr.y * u.y : R(0);  // Re(conj(h) u)
+          const R sv = group_sum<64>(sp);
+          bad |= !finite_pos(sv);
+          const R rs = R(1) / sqrt(sv);
+          if (lane < Mb) {
+            const Cx<R> wn{u.x * rs, -u.y * rs};
+            dv[lane] = csub(wn, s.w[r * Mb + lane]);
+            hv[lane] = hr;
+            s.w[r * Mb + lane] = wn;
+          }
+          wave_sync();
+          // g = d^T H and the denominator 1 + g_r of the rank-one update of H
+          if (lane < Mb) {
+            Cx<R> gj{R(0), R(0)};
+            for (int k = 0; k < Mb; ++k) gj = cfma(dv[k], H[k * Mb + lane], gj);
+            gv[lane] = gj;
+          }
+          wave_sync();
+        }
+        __syncthreads();
+        // H <- H - h_r g^T / (1 + g_r)
+        const Cx<R> den = cadd(Cx<R>{R(1), R(0)}, gv[r]);
+        bad |= !finite_pos(cabs2(den));
+        const Cx<R> rden = crecip(den);
+        for (int e = tid; e < Mb * Mb; e += nthr) {
+          const int i = e / Mb, j = e - (e / Mb) * Mb;
+          H[e] = cfms(cmul(hv[i], rden), gv[j], H[e]);
+        }
+        __syncthreads();
+      }
+    }
+  }
+  latch_wave(a.status, bad, kFaultIpSingular);
 
   // W_f out, then y = W xbar of the final W for the shared epilogue.
   for (int i = tid; i < Mb * Mb; i += nthr) a.W[(size_t)f * Mb * Mb + i] = s.w[i];
