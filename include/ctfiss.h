@@ -154,6 +154,49 @@ const char* ctfiss_status_string(int status);
 int ctfiss_set_profiling(ctfiss_ctx* ctx, int mask);
 int ctfiss_kernel_stats(ctfiss_ctx* ctx, int which, int64_t* launches, double* total_ms);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent mixtures of uneven shape (T, M, D, N, taps, K may differ)
+ * separated together.  Every mixture gets the same iteration as a single
+ * context (same results, bit for bit, for the same shape and precision), but
+ * an iteration is a handful of launches over all mixtures: the W update is
+ * one persistent launch per launch shape over the (mixture, bin) items of
+ * every mixture of that shape, and each NMF step is one launch over the
+ * workgroups of all mixtures.  The IP rule is accepted and runs mixture by
+ * mixture.  Mixture i uses its own device buffers exactly as a context does
+ * (X[i] [M_i][F_i][T_i], W[i], B[i], V[i], C[i]: same layouts and types). */
+typedef struct ctfiss_batch ctfiss_batch;
+
+/* Workspace bytes for n >= 1 mixtures of the given shapes (host array). */
+int ctfiss_batch_workspace_size(const ctfiss_shape* shapes, int32_t n, int precision, size_t* bytes);
+
+/* Create a batch; arguments as ctfiss_create, with one shape per mixture.
+ * The workspace (ctfiss_batch_workspace_size bytes, 256-byte aligned) holds
+ * every mixture's context workspace and the work tables. */
+int ctfiss_batch_create(const ctfiss_shape* shapes, int32_t n, int precision, int rule, int vrule, double floor,
+                        void* workspace, size_t workspace_bytes, void* stream, ctfiss_batch** out);
+
+/* X: host array of n device pointers.  Writes the work tables (device copies
+ * on the batch's stream) and synchronises the stream. */
+int ctfiss_batch_set_input(ctfiss_batch* b, const void* const* X);
+
+/* Host arrays of n device pointers; W may be NULL (identity for every
+ * mixture) and so may any of its entries. */
+int ctfiss_batch_set_state(ctfiss_batch* b, const void* const* W, const void* const* B, const void* const* V);
+
+/* n_iter iterations of every mixture (as ctfiss_iterate). */
+int ctfiss_batch_iterate(ctfiss_batch* b, int32_t n_iter);
+
+/* Source images of every mixture into C[i] (host array of device pointers). */
+int ctfiss_batch_source_images(ctfiss_batch* b, void* const* C);
+
+/* Synchronise; CTFISS_E_NUMERIC if any mixture latched a device fault, with
+ * the first such mixture's index in *mixture and its code in *fault_code
+ * (both nullable). */
+int ctfiss_batch_sync_status(ctfiss_batch* b, int32_t* mixture, int32_t* fault_code);
+
+/* Release the batch (not the workspace or any device buffer). */
+int ctfiss_batch_destroy(ctfiss_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,6 +31,8 @@ EXPORTS = (
     "ctfiss_workspace_size", "ctfiss_create", "ctfiss_set_input", "ctfiss_set_state", "ctfiss_iterate",
     "ctfiss_get_state", "ctfiss_source_images", "ctfiss_nll", "ctfiss_sync_status", "ctfiss_destroy",
     "ctfiss_status_string", "ctfiss_set_profiling", "ctfiss_kernel_stats",
+    "ctfiss_batch_workspace_size", "ctfiss_batch_create", "ctfiss_batch_set_input", "ctfiss_batch_set_state",
+    "ctfiss_batch_iterate", "ctfiss_batch_source_images", "ctfiss_batch_sync_status", "ctfiss_batch_destroy",
 )
 
 
@@ -65,6 +67,15 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "ctfiss_status_string": ([i32], ctypes.c_char_p),
         "ctfiss_set_profiling": ([vp, i32], i32),
         "ctfiss_kernel_stats": ([vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)], i32),
+        "ctfiss_batch_workspace_size": ([ctypes.POINTER(Shape), i32, i32, ctypes.POINTER(sz)], i32),
+        "ctfiss_batch_create": ([ctypes.POINTER(Shape), i32, i32, i32, i32, ctypes.c_double, vp, sz, vp,
+                                 ctypes.POINTER(vp)], i32),
+        "ctfiss_batch_set_input": ([vp, ctypes.POINTER(vp)], i32),
+        "ctfiss_batch_set_state": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)], i32),
+        "ctfiss_batch_iterate": ([vp, i32], i32),
+        "ctfiss_batch_source_images": ([vp, ctypes.POINTER(vp)], i32),
+        "ctfiss_batch_sync_status": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "ctfiss_batch_destroy": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -165,3 +176,61 @@ def ctfiss_kernel_stats(ctx, which: int) -> tuple[int, float]:
     ms = ctypes.c_double(0.0)
     _check(_lib.ctfiss_kernel_stats(ctx, int(which), ctypes.byref(n), ctypes.byref(ms)), "ctfiss_kernel_stats")
     return int(n.value), float(ms.value)
+
+
+# ------------------------------------------------------------------ batches
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))(*[None if t is None else int(t.data_ptr()) for t in tensors])
+    return arr
+
+
+def _shape_array(shapes):
+    arr = (Shape * len(shapes))(*shapes)
+    arr._keepalive = [sh._taps_keepalive for sh in shapes]
+    return arr
+
+
+def ctfiss_batch_workspace_size(shapes, precision: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.ctfiss_batch_workspace_size(_shape_array(shapes), len(shapes), int(precision), ctypes.byref(out)),
+           "ctfiss_batch_workspace_size")
+    return int(out.value)
+
+
+def ctfiss_batch_create(shapes, precision: int, rule: int, vrule: int, floor: float, workspace: torch.Tensor,
+                        stream=None) -> ctypes.c_void_p:
+    b = ctypes.c_void_p()
+    _check(_lib.ctfiss_batch_create(_shape_array(shapes), len(shapes), int(precision), int(rule), int(vrule),
+                                    float(floor), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                    _stream(stream), ctypes.byref(b)), "ctfiss_batch_create")
+    return b
+
+
+def ctfiss_batch_set_input(b, X) -> None:
+    _check(_lib.ctfiss_batch_set_input(b, _ptr_array(X)), "ctfiss_batch_set_input")
+
+
+def ctfiss_batch_set_state(b, W, B, V) -> None:
+    _check(_lib.ctfiss_batch_set_state(b, None if W is None else _ptr_array(W), _ptr_array(B), _ptr_array(V)),
+           "ctfiss_batch_set_state")
+
+
+def ctfiss_batch_iterate(b, n_iter: int) -> None:
+    _check(_lib.ctfiss_batch_iterate(b, int(n_iter)), "ctfiss_batch_iterate")
+
+
+def ctfiss_batch_source_images(b, C) -> None:
+    _check(_lib.ctfiss_batch_source_images(b, _ptr_array(C)), "ctfiss_batch_source_images")
+
+
+def ctfiss_batch_sync_status(b) -> tuple[int, int, int]:
+    mix = ctypes.c_int32(-1)
+    code = ctypes.c_int32(0)
+    st = _lib.ctfiss_batch_sync_status(b, ctypes.byref(mix), ctypes.byref(code))
+    if st not in (CTFISS_OK, CTFISS_E_NUMERIC):
+        raise CtfissError(st, "ctfiss_batch_sync_status")
+    return st, int(mix.value), int(code.value)
+
+
+def ctfiss_batch_destroy(b) -> None:
+    _check(_lib.ctfiss_batch_destroy(b), "ctfiss_batch_destroy")

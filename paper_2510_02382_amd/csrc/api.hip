@@ -488,4 +488,293 @@ int ctfiss_kernel_stats(ctfiss_ctx* c, int which, int64_t* launches, double* tot
   return CTFISS_OK;
 }
 
+
+// ------------------------------------------------------------------ batches
+}  // extern "C"
+
+struct ctfiss_batch {
+  int n, prec, rule;
+  hipStream_t stream;
+  char* ws;
+  std::vector<ctfiss_ctx*> ctx;
+  struct Bucket {
+    Plan plan;
+    std::vector<int> mix;  // mixture indices, in table order
+    int wbase;             // first descriptor slot of the bucket in each variant table
+    int sbase;             // first int of the bucket's start[] in the start region
+    size_t lds;
+    int blocks;
+  };
+  std::vector<Bucket> buckets;
+  // device tables (offsets into ws) and their host images
+  size_t off_w, off_ws, off_cnt, off_n, off_ns, tab_bytes, wsz, nsz;
+  int nblocks[4], nmfb_threads;
+  std::vector<unsigned char> host;
+  bool have_input, have_state, y_valid;
+};
+
+namespace {
+
+size_t batch_tables_bytes(int n, size_t wsz, size_t nsz) {
+  // W descriptors: 3 variants x n; W starts: 2n + 2 ints; counters: n ints;
+  // NMF descriptors: (2 + 2 + 1 + 1) x n; NMF starts: 4 (n + 1) ints
+  size_t b = 0;
+  b = align_up(b + 3 * (size_t)n * wsz, kAlign);
+  b = align_up(b + (2 * (size_t)n + 2) * sizeof(int), kAlign);
+  b = align_up(b + (size_t)n * sizeof(int), kAlign);
+  b = align_up(b + 6 * (size_t)n * nsz, kAlign);
+  b = align_up(b + 4 * ((size_t)n + 1) * sizeof(int), kAlign);
+  return b;
+}
+
+size_t desc_w_bytes(int prec) { return prec == CTFISS_FP32 ? wdesc_bytes<float>() : wdesc_bytes<double>(); }
+size_t desc_n_bytes(int prec) { return prec == CTFISS_FP32 ? ndesc_bytes<float>() : ndesc_bytes<double>(); }
+
+}  // namespace
+
+extern "C" {
+
+int ctfiss_batch_workspace_size(const ctfiss_shape* shapes, int32_t n, int precision, size_t* bytes) {
+  if (!shapes || !bytes || n < 1) return CTFISS_E_ARG;
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    size_t b = 0;
+    const int st = ctfiss_workspace_size(&shapes[i], precision, &b);
+    if (st != CTFISS_OK) return st;
+    total = align_up(total + b, kAlign);
+  }
+  *bytes = total + batch_tables_bytes(n, desc_w_bytes(precision), desc_n_bytes(precision));
+  return CTFISS_OK;
+}
+
+int ctfiss_batch_destroy(ctfiss_batch* b) {
+  if (!b) return CTFISS_E_ARG;
+  for (ctfiss_ctx* c : b->ctx)
+    if (c) ctfiss_destroy(c);
+  delete b;
+  return CTFISS_OK;
+}
+
+int ctfiss_batch_create(const ctfiss_shape* shapes, int32_t n, int precision, int rule, int vrule, double floor,
+                        void* workspace, size_t workspace_bytes, void* stream, ctfiss_batch** out) {
+  if (!out || !workspace) return CTFISS_E_ARG;
+  size_t need = 0;
+  int st = ctfiss_batch_workspace_size(shapes, n, precision, &need);
+  if (st != CTFISS_OK) return st;
+  if (workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return CTFISS_E_WORKSPACE;
+  ctfiss_batch* b = new (std::nothrow) ctfiss_batch();
+  if (!b) return CTFISS_E_ARG;
+  b->n = n;
+  b->prec = precision;
+  b->rule = rule;
+  b->stream = static_cast<hipStream_t>(stream);
+  b->ws = static_cast<char*>(workspace);
+  b->have_input = b->have_state = b->y_valid = false;
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    size_t wb = 0;
+    ctfiss_workspace_size(&shapes[i], precision, &wb);
+    ctfiss_ctx* c = nullptr;
+    st = ctfiss_create(&shapes[i], precision, rule, vrule, floor, b->ws + off, wb, stream, &c);
+    if (st != CTFISS_OK) {
+      ctfiss_batch_destroy(b);
+      return st;
+    }
+    b->ctx.push_back(c);
+    off = align_up(off + wb, kAlign);
+  }
+  b->wsz = desc_w_bytes(precision);
+  b->nsz = desc_n_bytes(precision);
+  b->off_w = off;
+  b->off_ws = align_up(b->off_w + 3 * (size_t)n * b->wsz, kAlign);
+  b->off_cnt = align_up(b->off_ws + (2 * (size_t)n + 2) * sizeof(int), kAlign);
+  b->off_n = align_up(b->off_cnt + (size_t)n * sizeof(int), kAlign);
+  b->off_ns = align_up(b->off_n + 6 * (size_t)n * b->nsz, kAlign);
+  b->tab_bytes = align_up(b->off_ns + 4 * ((size_t)n + 1) * sizeof(int), kAlign) - b->off_w;
+  // bucket the mixtures by launch shape of their W update
+  int wbase = 0, sbase = 0;
+  for (int i = 0; i < n; ++i) {
+    const Plan& p = b->ctx[i]->plan;
+    ctfiss_batch::Bucket* bk = nullptr;
+    for (auto& x : b->buckets)
+      if (x.plan.G == p.G && x.plan.CPL == p.CPL && x.plan.RPL == p.RPL && x.plan.threads == p.threads) bk = &x;
+    if (!bk) {
+      b->buckets.push_back(ctfiss_batch::Bucket{p, {}, 0, 0, 0, 0});
+      bk = &b->buckets.back();
+    }
+    bk->mix.push_back(i);
+    const size_t lds = iter_lds_layout(b->ctx[i]->d.M, b->ctx[i]->d.T, b->ctx[i]->d.D, b->ctx[i]->d.Mb,
+                                       b->ctx[i]->d.N, b->ctx[i]->d.lmax, p.G, p.CPL,
+                                       precision == CTFISS_FP32 ? 4 : 8, rule != 0)
+                           .total;
+    if (lds > bk->lds) bk->lds = lds;
+  }
+  if (b->buckets.size() > 256) {  // the lambda launch resets one counter per thread
+    ctfiss_batch_destroy(b);
+    return CTFISS_E_UNSUPPORTED;
+  }
+  for (auto& bk : b->buckets) {
+    bk.wbase = wbase;
+    bk.sbase = sbase;
+    wbase += (int)bk.mix.size();
+    sbase += (int)bk.mix.size() + 1;
+    int bins = 0;
+    for (int i : bk.mix) bins += b->ctx[i]->d.F;
+    const int res = rule == CTFISS_RULE_ISS ? (precision == CTFISS_FP32 ? resident_wblocks_batch<float>(bk.plan, bk.lds)
+                                                                        : resident_wblocks_batch<double>(bk.plan, bk.lds))
+                                            : 1;
+    if (res < 1) {
+      ctfiss_batch_destroy(b);
+      return CTFISS_E_UNSUPPORTED;
+    }
+    bk.blocks = res < bins ? res : bins;
+  }
+  b->host.assign(b->tab_bytes, 0);
+  *out = b;
+  return CTFISS_OK;
+}
+
+int ctfiss_batch_set_input(ctfiss_batch* b, const void* const* X) {
+  if (!b || !X) return CTFISS_E_ARG;
+  for (int i = 0; i < b->n; ++i) {
+    const int st = ctfiss_set_input(b->ctx[i], X[i]);
+    if (st != CTFISS_OK) return st;
+  }
+  const bool f32 = b->prec == CTFISS_FP32;
+  unsigned char* h = b->host.data();
+  auto at = [&](size_t off) { return h + (off - b->off_w); };
+  // W-update tables: per bucket, variants (no pending scale, demix), (pending scale, carried Y),
+  // (no pending scale, carried Y)
+  for (const auto& bk : b->buckets) {
+    int* start = reinterpret_cast<int*>(at(b->off_ws)) + bk.sbase;
+    int acc = 0;
+    for (size_t j = 0; j < bk.mix.size(); ++j) {
+      const ctfiss_ctx* c = b->ctx[bk.mix[j]];
+      start[j] = acc;
+      acc += c->d.F;
+      for (int v = 0; v < 3; ++v) {
+        void* dst = at(b->off_w + ((size_t)v * b->n + bk.wbase + j) * b->wsz);
+        if (f32)
+          fill_wdesc<float>(dst, c->plan, c->d, c->ptr, v == 1, v != 0);
+        else
+          fill_wdesc<double>(dst, c->plan, c->d, c->ptr, v == 1, v != 0);
+      }
+    }
+    start[bk.mix.size()] = acc;
+  }
+  // NMF tables: lambda [2][n], basis [2][n], partials [n], update [n]
+  const int slot[4] = {0, 2, 4, 5};
+  b->nmfb_threads = 64;
+  for (int kind = 0; kind < 4; ++kind) {
+    int* start = reinterpret_cast<int*>(at(b->off_ns)) + kind * (b->n + 1);
+    int acc = 0;
+    for (int i = 0; i < b->n; ++i) {
+      const ctfiss_ctx* c = b->ctx[i];
+      const bool tap0 = c->vrule == CTFISS_VRULE_PAPER_TAP0;
+      start[i] = acc;
+      int blocks = 0, thr = 0;
+      for (int v = 0; v < (kind < 2 ? 2 : 1); ++v) {
+        void* dst = at(b->off_n + ((size_t)(slot[kind] + v) * b->n + i) * b->nsz);
+        blocks = f32 ? fill_ndesc<float>(dst, kind, c->d, c->vs, c->ptr, c->floor, tap0, v == 1, &thr)
+                     : fill_ndesc<double>(dst, kind, c->d, c->vs, c->ptr, c->floor, tap0, v == 1, &thr);
+      }
+      if (kind == 1 && thr > b->nmfb_threads) b->nmfb_threads = thr;
+      acc += blocks;
+    }
+    start[b->n] = acc;
+    b->nblocks[kind] = acc;
+  }
+  hipError_t e = hipMemcpyAsync(b->ws + b->off_w, h, b->tab_bytes, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return CTFISS_E_HIP;
+  b->have_input = true;
+  b->y_valid = false;
+  return CTFISS_OK;
+}
+
+int ctfiss_batch_set_state(ctfiss_batch* b, const void* const* W, const void* const* B, const void* const* V) {
+  if (!b || !B || !V) return CTFISS_E_ARG;
+  for (int i = 0; i < b->n; ++i) {
+    const int st = ctfiss_set_state(b->ctx[i], W ? W[i] : nullptr, B[i], V[i]);
+    if (st != CTFISS_OK) return st;
+  }
+  b->have_state = true;
+  b->y_valid = false;
+  return CTFISS_OK;
+}
+
+int ctfiss_batch_iterate(ctfiss_batch* b, int32_t n_iter) {
+  if (!b || n_iter < 0) return CTFISS_E_ARG;
+  if (!b->have_input || !b->have_state) return CTFISS_E_ORDER;
+  if (b->rule != CTFISS_RULE_ISS) {
+    for (ctfiss_ctx* c : b->ctx) {
+      const int st = ctfiss_iterate(c, n_iter);
+      if (st != CTFISS_OK) return st;
+    }
+    return CTFISS_OK;
+  }
+  const bool f32 = b->prec == CTFISS_FP32;
+  char* w = b->ws;
+  const int* nst = reinterpret_cast<const int*>(w + b->off_ns);
+  int* cnt = reinterpret_cast<int*>(w + b->off_cnt);
+  const int nb = (int)b->buckets.size();
+  hipStream_t s = b->stream;
+  auto ndesc = [&](int slot) { return static_cast<const void*>(w + b->off_n + (size_t)slot * b->n * b->nsz); };
+  auto nmf = [&](int kind, int slot, int threads) {
+    const int* start = nst + kind * (b->n + 1);
+    return f32 ? nmf_batch_t<float>(kind, ndesc(slot), start, b->n, b->nblocks[kind], threads, cnt, nb, s)
+               : nmf_batch_t<double>(kind, ndesc(slot), start, b->n, b->nblocks[kind], threads, cnt, nb, s);
+  };
+  for (int it = 0; it < n_iter; ++it) {
+    const bool mu = it > 0;
+    hipError_t e = nmf(0, mu ? 1 : 0, 256);  // lambda; also zeroes the bucket counters
+    const int v = mu ? 1 : (b->y_valid ? 2 : 0);
+    for (int k = 0; e == hipSuccess && k < nb; ++k) {
+      const auto& bk = b->buckets[k];
+      const void* desc = w + b->off_w + ((size_t)v * b->n + bk.wbase) * b->wsz;
+      const int* start = reinterpret_cast<const int*>(w + b->off_ws) + bk.sbase;
+      e = f32 ? wupdate_batch_t<float>(bk.plan, desc, start, (int)bk.mix.size(), cnt + k, bk.lds, bk.blocks, s)
+              : wupdate_batch_t<double>(bk.plan, desc, start, (int)bk.mix.size(), cnt + k, bk.lds, bk.blocks, s);
+    }
+    if (e == hipSuccess) b->y_valid = true;
+    if (e == hipSuccess) e = nmf(1, mu ? 3 : 2, b->nmfb_threads);
+    if (e == hipSuccess) e = nmf(2, 4, 256);
+    if (e == hipSuccess) e = nmf(3, 5, 256);
+    if (e != hipSuccess) return CTFISS_E_HIP;
+  }
+  if (n_iter > 0) {
+    for (ctfiss_ctx* c : b->ctx) {
+      const hipError_t e = f32 ? apply_mu_t<float>(c->d, c->ptr, b->y_valid, s) : apply_mu_t<double>(c->d, c->ptr, b->y_valid, s);
+      if (e != hipSuccess) return CTFISS_E_HIP;
+    }
+  }
+  return CTFISS_OK;
+}
+
+int ctfiss_batch_source_images(ctfiss_batch* b, void* const* C) {
+  if (!b || !C) return CTFISS_E_ARG;
+  for (int i = 0; i < b->n; ++i) {
+    const int st = ctfiss_source_images(b->ctx[i], C[i]);
+    if (st != CTFISS_OK) return st;
+  }
+  return CTFISS_OK;
+}
+
+int ctfiss_batch_sync_status(ctfiss_batch* b, int32_t* mixture, int32_t* fault_code) {
+  if (!b) return CTFISS_E_ARG;
+  if (mixture) *mixture = -1;
+  if (fault_code) *fault_code = 0;
+  for (int i = 0; i < b->n; ++i) {
+    int32_t code = 0;
+    const int st = ctfiss_sync_status(b->ctx[i], &code);
+    if (st == CTFISS_E_NUMERIC) {
+      if (mixture) *mixture = i;
+      if (fault_code) *fault_code = code;
+      return st;
+    }
+    if (st != CTFISS_OK) return st;
+  }
+  return CTFISS_OK;
+}
+
 }  // extern "C"

@@ -131,6 +131,20 @@ __host__ __device__ constexpr int iter_max_threads(int rsize, int cpl, int rpl) 
                                                                 : (512 / iter_need_vgprs(rsize, cpl, rpl)) * 256;
 }
 
+// Batched launches: start[m] is the first work item (block or bin) of problem
+// m, start[nprob] the total; an item finds its problem by binary search.
+__device__ __forceinline__ int find_problem(const int* start, int nprob, int item) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // ------------------------------------------------------------------ LDS layout
 // Per-bin on-chip layout of the W-update kernels (TP = G * CPL padded frames).
 // During the sweep: x, w, phi, yb, wb (+ q, aug, u, fac for IP).  After it the

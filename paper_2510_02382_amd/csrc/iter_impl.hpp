@@ -91,6 +91,7 @@ __device__ __forceinline__ int lane_tid() {
 // Same for a workgroup-uniform size used as a divisor: the division's
 // reciprocal is then formed per bin rather than kept live across the loop.
 __device__ __forceinline__ int per_bin(int v) {
+  v = __builtin_amdgcn_readfirstlane(v);  // uniform by construction
   asm volatile("" : "+s"(v));
   return v;
 }
@@ -373,6 +374,33 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_mi
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
   for (int f = next_bin(a, s); f < a.F; f = next_bin(a, s)) iss_bin<R, G, CPL, RPL>(a, s, L, f);
+}
+
+// Batched ISS: the persistent workgroups take (problem, bin) items from one
+// counter over the bins of every problem of the launch (same launch shape);
+// each bin is processed exactly as in the single-problem kernel.
+template <typename R>
+struct WDesc {
+  IterArgs<R> a;
+  IterLds L;
+};
+
+template <typename R, int G, int CPL, int RPL>
+__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_min_waves(sizeof(R), CPL, RPL))
+    k_iss_batch(const WDesc<R>* __restrict__ d, const int* __restrict__ start, int nprob, int* work) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int claim;
+  const int total = start[nprob];
+  for (;;) {
+    __syncthreads();  // the previous bin's LDS traffic is over
+    if (threadIdx.x == 0) claim = atomicAdd(work, 1);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(claim);
+    if (item >= total) break;
+    const int m = __builtin_amdgcn_readfirstlane(find_problem(start, nprob, item));
+    const WDesc<R>& D = d[m];
+    iss_bin<R, G, CPL, RPL>(D.a, carve<R>(smem, D.L), D.L, item - start[m]);
+  }
 }
 
 // ------------------------------------------------------------------ IP

@@ -75,6 +75,24 @@ bool have_wkernel(int rule, int G, int cpl, int rpl);
 template <typename R>
 int resident_wblocks(int rule, const Plan& p, const Dims& d);
 
+// Batched launches (many problems of one launch shape per W-update launch).
+template <typename R>
+size_t wdesc_bytes();
+template <typename R>
+void fill_wdesc(void* dst, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload);
+template <typename R>
+int resident_wblocks_batch(const Plan& p, size_t lds);
+template <typename R>
+hipError_t wupdate_batch_t(const Plan& p, const void* desc, const int* start, int nprob, int* work, size_t lds,
+                           int blocks, hipStream_t s);
+template <typename R>
+size_t ndesc_bytes();
+template <typename R>
+int fill_ndesc(void* dst, int kind, const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0,
+               bool apply_mu, int* threads);
+template <typename R>
+hipError_t nmf_batch_t(int kind, const void* desc, const int* start, int nprob, int blocks, int threads, int* zero,
+                       int nzero, hipStream_t s);
 hipError_t launch_zero_status(int* status, hipStream_t s);
 size_t images_lds(const Dims& d);
 size_t nll_lds(const Dims& d);

@@ -1,6 +1,8 @@
 // Typed kernel launchers; included by exactly one translation unit per precision.
 #pragma once
 
+#include <cstring>
+
 #include "iter_impl.hpp"
 #include "launch.hpp"
 #include "nmf_impl.hpp"
@@ -84,9 +86,7 @@ int resident_wblocks(int rule, const Plan& p, const Dims& d) {
 }
 
 template <typename R>
-hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload, hipStream_t s) {
-  WFn<R> fn = pick<R>(rule, p.G, p.CPL, p.RPL);
-  if (!fn) return hipErrorInvalidValue;
+IterArgs<R> make_iargs(int rule, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload) {
   IterArgs<R> a;
   a.X = static_cast<const Cx<R>*>(ptr.X);
   a.W = static_cast<Cx<R>*>(ptr.W);
@@ -105,7 +105,19 @@ hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bo
   a.D = d.D;
   a.K = d.K;
   a.rm = d.rm;
-  const IterLds L = iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, (int)sizeof(R), rule != 0);
+  return a;
+}
+
+inline IterLds wlayout(int rule, const Plan& p, const Dims& d, int rsize) {
+  return iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, rsize, rule != 0);
+}
+
+template <typename R>
+hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload, hipStream_t s) {
+  WFn<R> fn = pick<R>(rule, p.G, p.CPL, p.RPL);
+  if (!fn) return hipErrorInvalidValue;
+  const IterArgs<R> a = make_iargs<R>(rule, d, ptr, apply_mu, yload);
+  const IterLds L = wlayout(rule, p, d, (int)sizeof(R));
   if (L.total > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     if (e != hipSuccess) return e;
@@ -186,6 +198,155 @@ hipError_t apply_mu_t(const Dims& d, const Ptrs& ptr, bool scale_y, hipStream_t 
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ batched
+template <typename R>
+using WBFn = void (*)(const WDesc<R>* __restrict__, const int* __restrict__, int, int*);
+
+template <typename R, int G, int RPL>
+WBFn<R> pickb_cpl(int cpl) {
+  if constexpr (sizeof(R) == 4) {
+    switch (cpl) {
+      case 4: return &k_iss_batch<R, G, 4, RPL>;
+      case 8: return &k_iss_batch<R, G, 8, RPL>;
+      case 10: return &k_iss_batch<R, G, 10, RPL>;
+      case 12: return &k_iss_batch<R, G, 12, RPL>;
+      case 16: return &k_iss_batch<R, G, 16, RPL>;
+      case 20: return &k_iss_batch<R, G, 20, RPL>;
+      case 24: return &k_iss_batch<R, G, 24, RPL>;
+      case 28: return &k_iss_batch<R, G, 28, RPL>;
+      case 32: return &k_iss_batch<R, G, 32, RPL>;
+      default: return nullptr;
+    }
+  } else {
+    switch (cpl) {
+      case 4: return &k_iss_batch<R, G, 4, RPL>;
+      case 6: return &k_iss_batch<R, G, 6, RPL>;
+      case 8: return &k_iss_batch<R, G, 8, RPL>;
+      case 10: return &k_iss_batch<R, G, 10, RPL>;
+      case 12: return &k_iss_batch<R, G, 12, RPL>;
+      case 16: return &k_iss_batch<R, G, 16, RPL>;
+      default: return nullptr;
+    }
+  }
+}
+
+template <typename R>
+WBFn<R> pickb(const Plan& p) {
+  if (p.RPL == 1) {
+    if (p.G == 16) return pickb_cpl<R, 16, 1>(p.CPL);
+    if (p.G == 32) return pickb_cpl<R, 32, 1>(p.CPL);
+    if constexpr (sizeof(R) == 8)
+      if (p.G == 64) return pickb_cpl<R, 64, 1>(p.CPL);
+  } else if (p.RPL == 2) {
+    if (p.G == 16) return pickb_cpl<R, 16, 2>(p.CPL);
+    if (p.G == 32) return pickb_cpl<R, 32, 2>(p.CPL);
+  }
+  return nullptr;
+}
+
+template <typename R>
+size_t wdesc_bytes() {
+  return sizeof(WDesc<R>);
+}
+
+template <typename R>
+void fill_wdesc(void* dst, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload) {
+  WDesc<R> w;
+  w.a = make_iargs<R>(0, d, ptr, apply_mu, yload);
+  w.L = wlayout(0, p, d, (int)sizeof(R));
+  std::memcpy(dst, &w, sizeof(w));
+}
+
+// Workgroups of the batched ISS kernel resident at once for a dynamic LDS size.
+template <typename R>
+int resident_wblocks_batch(const Plan& p, size_t lds) {
+  WBFn<R> fn = pickb<R>(p);
+  int dev = 0, cus = 0, per_cu = 0;
+  if (!fn || hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (lds > 65536 &&
+      hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, p.threads, lds) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+template <typename R>
+hipError_t wupdate_batch_t(const Plan& p, const void* desc, const int* start, int nprob, int* work, size_t lds,
+                           int blocks, hipStream_t s) {
+  WBFn<R> fn = pickb<R>(p);
+  if (!fn || blocks < 1) return hipErrorInvalidValue;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, dim3(blocks), dim3(p.threads), lds, s, static_cast<const WDesc<R>*>(desc), start, nprob, work);
+  return hipGetLastError();
+}
+
+template <typename R>
+size_t ndesc_bytes() {
+  return sizeof(NmfDesc<R>);
+}
+
+// Descriptor of one problem for batched NMF kernel `kind` (0 lambda, 1 basis
+// update, 2 activation partials, 3 activation update); returns its workgroup
+// count (the same grid its single-problem launch uses) and, for kind 1, the
+// threads it needs in *threads.
+template <typename R>
+int fill_ndesc(void* dst, int kind, const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0,
+               bool apply_mu, int* threads) {
+  NmfDesc<R> n;
+  int blocks = 0;
+  if (kind == 0) {
+    n.a = make_nargs<R>(d, VSplit{1, d.F}, ptr, 0.0, false, apply_mu);
+    n.gx = (d.T + 63) / 64;
+    n.gy = (d.F + 15) / 16;
+    n.extra = 0;
+    blocks = n.gx * n.gy * d.N;
+  } else if (kind == 1) {
+    n.a = make_nargs<R>(d, VSplit{1, d.F}, ptr, floor, false, apply_mu);
+    const int fpw = sizeof(R) == 4 ? 32 : 16;
+    int waves = (d.T + fpw - 1) / fpw;
+    if (waves > 16) waves = 16;
+    n.gx = (d.F + 15) / 16;
+    n.gy = d.N;
+    n.extra = waves;
+    blocks = n.gx * d.N;
+    if (threads) *threads = 64 * waves;
+  } else if (kind == 2) {
+    n.a = make_nargs<R>(d, vs, ptr, 0.0, tap0, false);
+    n.gx = (d.T + 15) / 16;
+    n.gy = vs.nch;
+    n.extra = 0;
+    blocks = n.gx * n.gy * d.N;
+  } else {
+    n.a = make_nargs<R>(d, vs, ptr, floor, tap0, false);
+    const int nv = (d.N * d.K * d.T + 255) / 256;
+    n.gx = nv + d.Mb;
+    n.gy = 1;
+    n.extra = nv;
+    blocks = nv + d.Mb;
+  }
+  std::memcpy(dst, &n, sizeof(n));
+  return blocks;
+}
+
+template <typename R>
+hipError_t nmf_batch_t(int kind, const void* desc, const int* start, int nprob, int blocks, int threads, int* zero,
+                       int nzero, hipStream_t s) {
+  const NmfDesc<R>* d = static_cast<const NmfDesc<R>*>(desc);
+  if (kind == 0)
+    hipLaunchKernelGGL(k_lambda_batch<R>, dim3(blocks), dim3(256), 0, s, d, start, nprob, zero, nzero);
+  else if (kind == 1)
+    hipLaunchKernelGGL(k_nmf_b_batch<R>, dim3(blocks), dim3(threads), 0, s, d, start, nprob);
+  else if (kind == 2)
+    hipLaunchKernelGGL(k_vpart_batch<R>, dim3(blocks), dim3(256), 0, s, d, start, nprob);
+  else
+    hipLaunchKernelGGL(k_vfinal_batch<R>, dim3(blocks), dim3(256), 0, s, d, start, nprob);
+  return hipGetLastError();
+}
+
 template <typename R>
 OutArgs<R> make_oargs(const Dims& d, const Ptrs& ptr, void* C) {
   OutArgs<R> a;
@@ -257,6 +418,14 @@ hipError_t identity_t(const Dims& d, void* W, hipStream_t s) {
   template hipError_t apply_mu_t<R>(const Dims&, const Ptrs&, bool, hipStream_t);                            \
   template hipError_t images_t<R>(const Dims&, const Ptrs&, void*, hipStream_t);                             \
   template hipError_t nll_t<R>(const Dims&, const Ptrs&, hipStream_t);                                       \
-  template hipError_t identity_t<R>(const Dims&, void*, hipStream_t);
+  template hipError_t identity_t<R>(const Dims&, void*, hipStream_t);                                        \
+  template size_t wdesc_bytes<R>();                                                                           \
+  template void fill_wdesc<R>(void*, const Plan&, const Dims&, const Ptrs&, bool, bool);                      \
+  template int resident_wblocks_batch<R>(const Plan&, size_t);                                                \
+  template hipError_t wupdate_batch_t<R>(const Plan&, const void*, const int*, int, int*, size_t, int,          \
+                                         hipStream_t);                                                        \
+  template size_t ndesc_bytes<R>();                                                                           \
+  template int fill_ndesc<R>(void*, int, const Dims&, const VSplit&, const Ptrs&, double, bool, bool, int*);  \
+  template hipError_t nmf_batch_t<R>(int, const void*, const int*, int, int, int, int*, int, hipStream_t);
 
 }  // namespace ctfiss

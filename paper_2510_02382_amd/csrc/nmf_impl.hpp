@@ -76,12 +76,12 @@ __device__ __forceinline__ typename Acc4<R>::type acc_zero() {
 // per wave, K/4 MFMA steps.  Grid (ceil(T/64), ceil(F/16), N), 4 waves per
 // workgroup covering 64 frames.
 template <typename R>
-__global__ void __launch_bounds__(256) k_lambda(NmfArgs<R> a) {
+__device__ __forceinline__ void lambda_block(const NmfArgs<R>& a, const int bx, const int by, const int bz) {
   constexpr int KS = kMaxK / 4;
   const int T = a.T, K = a.K, F = a.F;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
-  const int n = blockIdx.z, f0 = blockIdx.y * 16, t0 = blockIdx.x * 64 + wave * 16;
-  if (a.work && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *a.work = 0;
+  const int n = bz, f0 = by * 16, t0 = bx * 64 + wave * 16;
+  if (a.work && bx == 0 && by == 0 && bz == 0 && threadIdx.x == 0) *a.work = 0;
   if (t0 >= T) return;
   const int nks = (K + 3) / 4;
   const R sc = pending_scale(a, n);
@@ -113,19 +113,23 @@ __global__ void __launch_bounds__(256) k_lambda(NmfArgs<R> a) {
   latch_wave(a.status, bad, kFaultMu);
 }
 
+template <typename R>
+__global__ void __launch_bounds__(256) k_lambda(NmfArgs<R> a) { lambda_block<R>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
+
 // Basis update, Eq. (17), with t' = t - l:
 //   num_{f,k} = sum_t' P_{f,t'} v_{k,t'} / lambda_{f,t'}^2,  den_{f,k} = sum_t' C_{t'} v_{k,t'} / lambda_{f,t'},
 //   C_{t'} = #{l < L_n : t' + l < T};  b <- max((b / mu^2) sqrt(num / den), floor).
 // (F x T)(T x K) contractions on MFMA: one workgroup per 16 bins, its 4 waves
 // split the frames, partial tiles are summed in LDS in wave order.
 template <typename R>
-__global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) {
+__device__ __forceinline__ void nmfb_block(const NmfArgs<R>& a, const int bx, const int by, const int nwe) {
   constexpr int KT = kMaxK / 16;
   constexpr int ST = sizeof(R) == 4 ? 8 : 4;  // MFMA steps (4 frames each) per wave and round
   __shared__ R red[2][KT][4][64];
   const int T = a.T, K = a.K, F = a.F;
-  const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
-  const int n = blockIdx.y, f0 = blockIdx.x * 16;
+  // nwe: waves that share the frames (a batched launch may carry more, which stay idle)
+  const int wave = threadIdx.x >> 6, nwave = nwe, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  const int n = by, f0 = bx * 16;
   const int L = a.rm.L[n];
   const int nkt = (K + 15) / 16;
   const R* Pn = a.P + (size_t)n * F * T;
@@ -136,7 +140,7 @@ __global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) {
 #pragma unroll
   for (int kt = 0; kt < KT; ++kt) num[kt] = den[kt] = acc_zero<R>();
   // rounds of ST steps; every wave's operand loads of a round are issued before its MFMAs
-  for (int base = wave * ST; 4 * base < T; base += nwave * ST) {
+  for (int base = wave * ST; wave < nwave && 4 * base < T; base += nwave * ST) {
     R e1[ST], e2[ST], bv[ST][KT];
 #pragma unroll
     for (int st = 0; st < ST; ++st) {
@@ -197,6 +201,9 @@ __global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) {
   latch_wave(a.status, bad, kFaultMu);  // one atomic per wave, not per lane
 }
 
+template <typename R>
+__global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) { nmfb_block<R>(a, blockIdx.x, blockIdx.y, blockDim.x >> 6); }
+
 // Partial sums over one chunk of bins of
 //   num[k][t] = sum_f b_{f,k} P'_{f,t} / lambda_{f,t}^2,  den[k][t] = sum_f b_{f,k} / lambda_{f,t},
 // with lambda = b v recomputed from the updated bases.  One wave per 16 frames
@@ -204,13 +211,13 @@ __global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) {
 // weights in the accumulator layout, then b^T times them on MFMA (the bin
 // index of the accumulator rows is the reduction index, 4 MFMA steps).
 template <typename R>
-__global__ void __launch_bounds__(256) k_vpart(NmfArgs<R> a) {
+__device__ __forceinline__ void vpart_block(const NmfArgs<R>& a, const int bx, const int by, const int bz) {
   constexpr int KT = kMaxK / 16;
   constexpr int KS = kMaxK / 4;
   __shared__ R red[2][KT][4][64];
   const int T = a.T, K = a.K, F = a.F;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
-  const int n = blockIdx.z, ch = blockIdx.y, t0 = blockIdx.x * 16;
+  const int n = bz, ch = by, t0 = bx * 16;
   const int f1 = min(F, ch * a.fchunk + a.fchunk);
   const int fs = ch * a.fchunk + 16 * wave;  // this wave's 16-bin sub-tile
   const int nkt = (K + 15) / 16, nks = (K + 3) / 4;
@@ -292,15 +299,18 @@ __global__ void __launch_bounds__(256) k_vpart(NmfArgs<R> a) {
   }
 }
 
+template <typename R>
+__global__ void __launch_bounds__(256) k_vpart(NmfArgs<R> a) { vpart_block<R>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
+
 // v <- max(v sqrt(num / (C' den)), floor) with the chunk partials summed in
 // chunk order; C' = #{l < L_n : t + l < T} (ALL_TAPS) or 1 (PAPER_TAP0).
 // The last Mb workgroups compute mu_r = sqrt(sum_f musq[r][f] / (F T)), Eq. (19).
 template <typename R>
-__global__ void __launch_bounds__(256) k_vfinal(NmfArgs<R> a, int nvblocks) {
+__device__ __forceinline__ void vfinal_block(const NmfArgs<R>& a, const int nvblocks, const int bx) {
   const int T = a.T, K = a.K, N = a.rm.N;
-  if ((int)blockIdx.x >= nvblocks) {
+  if (bx >= nvblocks) {
     __shared__ R red[256];
-    const int r = blockIdx.x - nvblocks, F = a.F;
+    const int r = bx - nvblocks, F = a.F;
     R acc = 0;
     for (int f = threadIdx.x; f < F; f += blockDim.x) acc += a.musq[(size_t)r * F + f];
     red[threadIdx.x] = acc;
@@ -316,7 +326,7 @@ __global__ void __launch_bounds__(256) k_vfinal(NmfArgs<R> a, int nvblocks) {
     }
     return;
   }
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= N * K * T) return;
   const int n = i / (K * T), k = (i / T) % K, t = i % T;
   R num = 0, den = 0;
@@ -330,6 +340,58 @@ __global__ void __launch_bounds__(256) k_vfinal(NmfArgs<R> a, int nvblocks) {
   R v = a.V[i] * sqrt(num / (c * den));
   latch_wave(a.status, !isfinite(v), kFaultMu);
   a.V[i] = v > a.floor ? v : a.floor;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_vfinal(NmfArgs<R> a, int nvblocks) { vfinal_block<R>(a, nvblocks, blockIdx.x); }
+
+// ------------------------------------------------------------------ batched
+// One grid over the workgroups of many problems (mixtures): a workgroup finds
+// its problem in start[] and runs that problem's workgroup (gx, gy: the
+// problem's own grid extents; z follows).  The work of each problem is the one
+// its single-problem launch does, in the same order.
+template <typename R>
+struct NmfDesc {
+  NmfArgs<R> a;
+  int gx, gy;
+  int extra;  // k_nmf_b: waves sharing the frames; k_vfinal: activation workgroups
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_lambda_batch(const NmfDesc<R>* d, const int* start, int nprob, int* zero,
+                                                      int nzero) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < nzero) zero[threadIdx.x] = 0;  // bin counters of the next launch
+  const int m = find_problem(start, nprob, blockIdx.x);
+  const NmfDesc<R>& D = d[m];
+  int b = blockIdx.x - start[m];
+  const int bx = b % D.gx;
+  b /= D.gx;
+  lambda_block<R>(D.a, bx, b % D.gy, b / D.gy);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(1024) k_nmf_b_batch(const NmfDesc<R>* d, const int* start, int nprob) {
+  const int m = find_problem(start, nprob, blockIdx.x);
+  const NmfDesc<R>& D = d[m];
+  const int b = blockIdx.x - start[m];
+  nmfb_block<R>(D.a, b % D.gx, b / D.gx, D.extra);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_vpart_batch(const NmfDesc<R>* d, const int* start, int nprob) {
+  const int m = find_problem(start, nprob, blockIdx.x);
+  const NmfDesc<R>& D = d[m];
+  int b = blockIdx.x - start[m];
+  const int bx = b % D.gx;
+  b /= D.gx;
+  vpart_block<R>(D.a, bx, b % D.gy, b / D.gy);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_vfinal_batch(const NmfDesc<R>* d, const int* start, int nprob) {
+  const int m = find_problem(start, nprob, blockIdx.x);
+  const NmfDesc<R>& D = d[m];
+  vfinal_block<R>(D.a, D.extra, blockIdx.x - start[m]);
 }
 
 // W row r /= mu_r and b_n /= mu_{(n,0)}^2, Eqs. (20)-(21) applied to W and b;

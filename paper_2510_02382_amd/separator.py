@@ -99,3 +99,79 @@ class Separator:
             self.close()
         except Exception:
             pass
+
+
+class BatchSeparator:
+    """CTF-MNMF separation of many mixtures of uneven shape on one GPU (ctfiss_batch_*).
+
+    shapes: list of (F, T, M, D, N, K, taps).  Mixture i takes tensors of the
+    shapes a Separator of shapes[i] takes.  Each iteration runs every mixture;
+    per launch shape the W update is one persistent launch over all bins of all
+    those mixtures, and each NMF step is one launch over all mixtures.
+    """
+
+    def __init__(self, shapes, precision="fp32", rule="iss", vrule="all_taps", floor=1e-8, device="cuda",
+                 stream=None):
+        self.shapes = [(int(F), int(T), int(M), int(D), int(N), int(K), tuple(int(x) for x in taps))
+                       for (F, T, M, D, N, K, taps) in shapes]
+        self.precision = precision
+        self.rdtype = torch.float32 if precision == "fp32" else torch.float64
+        self.cdtype = torch.complex64 if precision == "fp32" else torch.complex128
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._shapes = [b.make_shape(*sh) for sh in self.shapes]
+        nbytes = b.ctfiss_batch_workspace_size(self._shapes, _PREC[precision])
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace allocation is not 256-byte aligned")
+        self.batch = b.ctfiss_batch_create(self._shapes, _PREC[precision], _RULE[rule], _VRULE[vrule], floor,
+                                           self.workspace, self.stream)
+        self._X = None
+
+    def _check(self, ts, shape_fn, dtype, name):
+        if len(ts) != len(self.shapes):
+            raise ValueError(f"{name}: expected {len(self.shapes)} tensors, got {len(ts)}")
+        for i, (t, sh) in enumerate(zip(ts, self.shapes)):
+            want = shape_fn(*sh)
+            if t.device != self.device or t.dtype != dtype or tuple(t.shape) != want or not t.is_contiguous():
+                raise ValueError(f"{name}[{i}]: expected contiguous {dtype} {want} on {self.device}, got "
+                                 f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
+    def set_input(self, X) -> None:
+        self._check(X, lambda F, T, M, D, N, K, taps: (M, F, T), self.cdtype, "X")
+        self._X = list(X)
+        b.ctfiss_batch_set_input(self.batch, self._X)
+
+    def set_state(self, B, V, W=None) -> None:
+        self._check(B, lambda F, T, M, D, N, K, taps: (N, F, K), self.rdtype, "B")
+        self._check(V, lambda F, T, M, D, N, K, taps: (N, K, T), self.rdtype, "V")
+        if W is not None:
+            self._check(W, lambda F, T, M, D, N, K, taps: (F, M * D, M * D), self.cdtype, "W")
+        b.ctfiss_batch_set_state(self.batch, W, B, V)
+
+    def iterate(self, n_iter: int) -> None:
+        b.ctfiss_batch_iterate(self.batch, n_iter)
+
+    def source_images(self):
+        C = [torch.empty((N, M, F, T), dtype=self.cdtype, device=self.device)
+             for (F, T, M, D, N, K, taps) in self.shapes]
+        b.ctfiss_batch_source_images(self.batch, C)
+        return C
+
+    def status(self) -> tuple[int, int]:
+        """(mixture, code) of the first mixture with a latched device fault, or (-1, 0) (synchronises)."""
+        _, mix, code = b.ctfiss_batch_sync_status(self.batch)
+        return mix, code
+
+    def close(self) -> None:
+        if self.batch is not None:
+            b.ctfiss_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,107 @@
+"""Batches of uneven mixtures (ctfiss_batch_*) against single contexts.
+
+A batch runs, per mixture, the iteration a single context runs on the same
+launch shape (the W update per bin, the NMF steps per workgroup in the same
+order), so its images must equal the single-context images bit for bit.  The
+single-context path itself is checked against the FP64 oracle in
+test_gpu_parity.py.
+"""
+import numpy as np
+import pytest
+
+from datagen import random_problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (F, T, M, D, N, K, taps): several launch shapes, two mixtures of one shape
+SHAPES = [
+    (9, 40, 2, 2, 2, 3, (2, 2)),
+    (7, 100, 3, 1, 2, 2, (2, 1)),
+    (5, 313, 3, 4, 2, 4, (6, 6)),
+    (11, 70, 4, 2, 3, 3, (3, 3, 2)),
+    (9, 40, 2, 2, 2, 3, (2, 2)),
+    (4, 500, 2, 2, 2, 5, (2, 2)),
+]
+
+
+def _problems(precision, seed0=20):
+    rd = torch.float32 if precision == "fp32" else torch.float64
+    cd = torch.complex64 if precision == "fp32" else torch.complex128
+    out = []
+    for i, (F, T, M, D, N, K, taps) in enumerate(SHAPES):
+        X, B0, V0 = random_problem(F, T, M, N, K, seed0 + i, scale_spread=0.5)
+        out.append((torch.from_numpy(X).to("cuda", cd), torch.from_numpy(B0).to("cuda", rd),
+                    torch.from_numpy(V0).to("cuda", rd)))
+    return out
+
+
+def _single(precision, rule, probs, splits):
+    from paper_2510_02382_amd import Separator
+    imgs = []
+    for (F, T, M, D, N, K, taps), (X, B, V) in zip(SHAPES, probs):
+        sep = Separator(F, T, M, D, N, K, taps, precision=precision, rule=rule)
+        sep.set_input(X)
+        sep.set_state(B=B, V=V)
+        for n in splits:
+            sep.iterate(n)
+        imgs.append(sep.source_images())
+        assert sep.status() == 0
+        sep.close()
+    return imgs
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_equals_single_contexts(precision):
+    from paper_2510_02382_amd import BatchSeparator
+    probs = _problems(precision)
+    ref = _single(precision, "iss", probs, (4, 3))
+    bs = BatchSeparator(SHAPES, precision=precision)
+    bs.set_input([p[0] for p in probs])
+    bs.set_state(B=[p[1] for p in probs], V=[p[2] for p in probs])
+    bs.iterate(4)
+    bs.iterate(3)  # the carried demixed rows and the pending rescale cross calls as in a context
+    got = bs.source_images()
+    assert bs.status() == (-1, 0)
+    for i, (a, b) in enumerate(zip(got, ref)):
+        assert torch.equal(a, b), f"mixture {i}: max |diff| {float((a - b).abs().max())}"
+    bs.close()
+
+
+def test_batch_ip_rule_runs_per_mixture():
+    from paper_2510_02382_amd import BatchSeparator
+    probs = _problems("fp64", seed0=40)
+    ref = _single("fp64", "ip", probs, (3,))
+    bs = BatchSeparator(SHAPES, precision="fp64", rule="ip")
+    bs.set_input([p[0] for p in probs])
+    bs.set_state(B=[p[1] for p in probs], V=[p[2] for p in probs])
+    bs.iterate(3)
+    for a, b in zip(bs.source_images(), ref):
+        assert torch.equal(a, b)
+    bs.close()
+
+
+def test_batch_reports_the_faulting_mixture():
+    from paper_2510_02382_amd import BatchSeparator
+    probs = _problems("fp32", seed0=60)
+    X3 = probs[3][0].clone()
+    X3[0, 2, 5] = complex(float("nan"), 0.0)
+    bs = BatchSeparator(SHAPES, precision="fp32")
+    bs.set_input([p[0] if i != 3 else X3 for i, p in enumerate(probs)])
+    bs.set_state(B=[p[1] for p in probs], V=[p[2] for p in probs])
+    bs.iterate(1)
+    mix, code = bs.status()
+    assert mix == 3 and code != 0
+    bs.close()
+
+
+def test_batch_rejects_wrong_tensors():
+    from paper_2510_02382_amd import BatchSeparator
+    probs = _problems("fp32", seed0=80)
+    bs = BatchSeparator(SHAPES, precision="fp32")
+    with pytest.raises(ValueError):
+        bs.set_input([p[0] for p in probs][:-1])
+    with pytest.raises(ValueError):
+        bs.set_input([p[0].to(torch.complex128) for p in probs])
+    bs.close()
