@@ -94,6 +94,136 @@ def cpu_baseline(wl, X, B0, V0, n_iter=10):
                       f"in FP64 NumPy on 1 thread, {dt:.1f} s"}
 
 
+def batched_bench(args) -> int:
+    """256 uneven mixtures (3-12 s, N in {2, 3}, M = N + 1, D in {4, 8}, RT60 0.3-1.0 s, STFT
+    1024/256, K = 10, 50 iterations) separated as one batch in FP32, against the same
+    mixtures separated one context at a time (FP32 and FP64 ISS) and against FP64 IP (on a
+    subset, per unit of work).  value = sum of F*T*iterations / second of the batch."""
+    import torch
+
+    from datagen import batched_workloads, init_nmf, make_mixture
+    from paper_2510_02382_amd import BatchSeparator, Separator
+
+    wls = batched_workloads(args.batch, 7)
+    log(f"batched workload: {len(wls)} mixtures, T {min(w.T for w in wls)}-{max(w.T for w in wls)}, "
+        f"Mbar {sorted(set(w.mbar for w in wls))}; drawing mixtures")
+    dev = torch.device("cuda:0")
+    X32, X64, B32, B64, V32, V64, shapes = [], [], [], [], [], [], []
+    for i, w in enumerate(wls):
+        mix = make_mixture(w, 1000 + i)
+        B0, V0 = init_nmf(w.N, w.F, w.K, w.T, 1000 + i)
+        X64.append(torch.from_numpy(mix.X).to(dev))
+        X32.append(X64[-1].to(torch.complex64))
+        B64.append(torch.from_numpy(B0).to(dev))
+        B32.append(B64[-1].float())
+        V64.append(torch.from_numpy(V0).to(dev))
+        V32.append(V64[-1].float())
+        shapes.append((w.F, w.T, w.M, w.D, w.N, w.K, w.row_taps))
+        if (i + 1) % 64 == 0:
+            log(f"  {i + 1} mixtures drawn")
+    n_iter = wls[0].n_iter
+    units = sum(w.F * w.T for w in wls) * n_iter
+
+    bs = BatchSeparator(shapes, precision="fp32")
+    bs.set_input(X32)
+    for _ in range(args.warmup):
+        bs.set_state(B=B32, V=V32)
+        bs.iterate(n_iter)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bs.set_state(B=B32, V=V32)
+        bs.iterate(n_iter)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    C32 = bs.source_images()
+    st = bs.status()
+    bs.close()
+    value = units / dt
+    log(f"batched FP32 ISS: {dt * 1e3:.1f} ms per batch, {value:.4e} F*T*it/s, status {st}")
+
+    from paper_2510_02382_amd.binding import CtfissError
+
+    def single(precision, rule, idx):
+        """Separate mixtures idx one context at a time; mixtures whose shape this precision
+        does not support are skipped.  Returns (seconds, images by index, status, units run)."""
+        Xs, Bs, Vs = (X32, B32, V32) if precision == "fp32" else (X64, B64, V64)
+        seps, ran = [], []
+        for i in idx:
+            F, T, M, D, N, K, taps = shapes[i]
+            try:
+                sp = Separator(F, T, M, D, N, K, taps, precision=precision, rule=rule)
+            except CtfissError:
+                continue
+            sp.set_input(Xs[i])
+            seps.append(sp)
+            ran.append(i)
+        idx = ran
+        for i, sp in zip(idx, seps):  # warm-up
+            sp.set_state(B=Bs[i], V=Vs[i])
+            sp.iterate(1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i, sp in zip(idx, seps):
+            sp.set_state(B=Bs[i], V=Vs[i])
+            sp.iterate(n_iter)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        imgs = {i: sp.source_images() for i, sp in zip(idx, seps)}
+        stat = max(sp.status() for sp in seps)
+        for sp in seps:
+            sp.close()
+        return el, imgs, stat, sum(wls[i].F * wls[i].T for i in idx) * n_iter
+
+    allidx = list(range(len(wls)))
+    if args.no_side:
+        print(json.dumps({"metric": "F·T·iters/s of a batch of uneven mixtures (batched FP32 ISS)", "value": value,
+                          "unit": "F·T·iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": f"{len(wls)} uneven mixtures, 50 iterations"}}), flush=True)
+        return 0
+    dt32, _, st32, u32 = single("fp32", "iss", allidx)
+    log(f"single-context FP32 ISS: {dt32 * 1e3:.1f} ms, status {st32}")
+    dt64, C64, st64, u64 = single("fp64", "iss", allidx)
+    log(f"single-context FP64 ISS on {len(C64)} mixtures (the others exceed the FP64 kernel's limits): "
+        f"{dt64 * 1e3:.1f} ms, status {st64}")
+    sub = allidx[: min(32, len(allidx))]
+    dtip, _, stip, uip = single("fp64", "ip", sub)
+    log(f"single-context FP64 IP on the first {len(sub)} mixtures: {dtip * 1e3:.1f} ms, status {stip}")
+    rel = max(float(torch.linalg.norm((C32[i].to(torch.complex128) - C64[i]).flatten())
+                    / torch.linalg.norm(C64[i].flatten())) for i in C64)
+    out = {
+        "metric": "F·T·iters/s of a batch of uneven mixtures (batched FP32 ISS)",
+        "value": value,
+        "unit": "F·T·iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{len(wls)} mixtures: 3-12 s, N in {{2,3}}, M = N + 1, D in {{4,8}}, RT60 0.3-1.0 s, "
+                               "STFT 1024/256, K = 10, 50 iterations", "mixtures": len(wls),
+                   "sum_FT": sum(w.F * w.T for w in wls), "iterations": n_iter},
+        "side_by_side": {
+            "single_fp32_iss": {"value": u32 / dt32, "ms": dt32 * 1e3, "status": st32},
+            "single_fp64_iss": {"value": u64 / dt64, "ms": dt64 * 1e3, "mixtures": len(C64), "status": st64},
+            "single_fp64_ip": {"value": uip / dtip, "ms": dtip * 1e3, "mixtures": len(sub), "status": stip},
+            "speedup_vs_single_fp64_iss": value / (u64 / dt64),
+            "speedup_vs_single_fp32_iss": value / (u32 / dt32),
+            "speedup_vs_single_fp64_ip": value / (uip / dtip),
+            "batched_fp32_images_max_rel_err_vs_fp64_iss": rel,
+        },
+        "status": list(st),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +232,9 @@ def main() -> int:
     ap.add_argument("--side-steps", type=int, default=2, help="timed steps of the FP64 and IP paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="time only the FP32 ISS path")
+    ap.add_argument("--batched", action="store_true",
+                    help="time the batch of uneven mixtures instead of the single long mixture")
+    ap.add_argument("--batch", type=int, default=256, help="mixtures in --batched mode")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -112,6 +245,9 @@ def main() -> int:
         return 2
 
     import torch
+
+    if args.batched:
+        return batched_bench(args)
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
