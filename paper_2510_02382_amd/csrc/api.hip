@@ -57,14 +57,19 @@ bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
     list = prec == 0 ? kIp32 : kIp64;
     n = prec == 0 ? (int)(sizeof(kIp32) / sizeof(GR)) : (int)(sizeof(kIp64) / sizeof(GR));
   }
-  // FP32 ISS: 32-lane groups whenever the workgroup fits (Mbar <= 32).  Half
-  // the frames per lane of a 16-lane group: fewer registers (no spills up to
-  // 20 frames per lane), and for Mbar = 24 three waves per SIMD (a 16-lane
-  // group has 2 on two SIMDs and 1 on the others); at <= 10 frames per lane two
-  // such workgroups share a CU.
+  // FP32 ISS: 32-lane groups whenever the workgroup fits (Mbar <= 32) and
+  // needs at most 20 frames per lane (no spills); past that, 64-lane groups if
+  // they fit (Mbar <= 16), else 32-lane groups with more frames per lane.
+  // Against a 16-lane group: half the frames per lane (fewer registers), and
+  // for Mbar = 24 three waves per SIMD (a 16-lane group has 2 on two SIMDs and
+  // 1 on the others); at <= 10 frames per lane two such workgroups share a CU.
   if (rule == 0 && prec == 0) {
     Plan p;
-    if (plan_for(prec, rule, d, max_lds, 32, 1, 0, &p)) {
+    if (plan_for(prec, rule, d, max_lds, 32, 1, 0, &p) && p.CPL <= 20) {
+      *out = p;
+      return true;
+    }
+    if (plan_for(prec, rule, d, max_lds, 64, 1, 0, &p) || plan_for(prec, rule, d, max_lds, 32, 1, 0, &p)) {
       *out = p;
       return true;
     }

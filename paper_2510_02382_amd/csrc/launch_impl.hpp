@@ -59,6 +59,9 @@ template <typename R>
 WFn<R> pick(int rule, int G, int cpl, int rpl) {
   if (G == 16) return pick_rpl<R, 16>(rule, cpl, rpl);
   if (G == 32) return pick_rpl<R, 32>(rule, cpl, rpl);
+  if constexpr (sizeof(R) == 4) {
+    if (G == 64 && rpl == 1) return pick_cpl<R, 64, 1>(rule, cpl);  // long frames, Mbar <= 16
+  }
   if constexpr (sizeof(R) == 8) {
     if (G == 64) return pick_rpl<R, 64>(rule, cpl, rpl);
   }
@@ -235,8 +238,7 @@ WBFn<R> pickb(const Plan& p) {
   if (p.RPL == 1) {
     if (p.G == 16) return pickb_cpl<R, 16, 1>(p.CPL);
     if (p.G == 32) return pickb_cpl<R, 32, 1>(p.CPL);
-    if constexpr (sizeof(R) == 8)
-      if (p.G == 64) return pickb_cpl<R, 64, 1>(p.CPL);
+    if (p.G == 64) return pickb_cpl<R, 64, 1>(p.CPL);
   } else if (p.RPL == 2) {
     if (p.G == 16) return pickb_cpl<R, 16, 2>(p.CPL);
     if (p.G == 32) return pickb_cpl<R, 32, 2>(p.CPL);

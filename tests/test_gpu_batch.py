@@ -23,6 +23,7 @@ SHAPES = [
     (11, 70, 4, 2, 3, 3, (3, 3, 2)),
     (9, 40, 2, 2, 2, 3, (2, 2)),
     (4, 500, 2, 2, 2, 5, (2, 2)),
+    (3, 700, 2, 4, 2, 3, (4, 4)),
 ]
 
 

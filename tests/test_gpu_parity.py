@@ -28,6 +28,7 @@ pytestmark = pytest.mark.gpu
 CASES = {
     # name: (F, T, M, D, taps, K)
     "d1_tiny": (5, 37, 3, 1, (2, 1), 3),
+    "long_frames": (3, 700, 2, 4, (4, 4), 3),  # FP32 ISS on 64-lane row groups
     "single_row": (3, 50, 1, 1, (1,), 2),
     "ragged": (7, 100, 2, 3, (4, 2), 1),
     "three_src": (4, 150, 4, 2, (3, 3, 2), 4),
@@ -111,7 +112,7 @@ def oracle_run(X, D, taps, B0, V0, W0, n_iter, precision, rule="iss", vrule="all
 def test_one_iteration_matches_oracle(case, rule, precision):
     X, B0, V0, W0, D, taps = make_case(case)
     if case == "max_rows" and rule == "ip" and precision == "fp64":
-        # the per-bin IP working set (W, Q_r, [W Q_r | e_r] in FP64) exceeds one workgroup's LDS
+        # the per-bin IP working set in FP64 (W, its inverse, one inverse weighted covariance) exceeds LDS
         from paper_2510_02382_amd import binding as b
         with pytest.raises(b.CtfissError) as e:
             gpu_run(X, D, taps, B0, V0, W0, 1, precision, rule)
