@@ -224,6 +224,72 @@ def batched_bench(args) -> int:
     return 0
 
 
+def precision_bench(args) -> int:
+    """Long-signal workload with Mbar = 64: 60 s at 16 kHz, N=3, M=4, RT60 0.8 s, STFT 4096/1024
+    (F=2049, T=938), D=16 stacked frames (taps 22+21+21), K=30, 100 iterations.  A bin's 64 rows x
+    938 frames exceed one workgroup, so the W update runs as teams of workgroups splitting each
+    bin's frames.  The FP32 path is timed (value) and checked against the FP64 path on the same
+    mixture (the FP64 team path is checked against the CPU oracle by the test-suite)."""
+    import torch
+
+    from datagen import WORKLOADS, init_nmf, make_mixture
+    from paper_2510_02382_amd import Separator
+
+    wl = WORKLOADS["c3"]
+    log(f"workload c3: F={wl.F} T={wl.T} M={wl.M} D={wl.D} Mbar={wl.mbar} taps={wl.row_taps} K={wl.K} "
+        f"iters={wl.n_iter}")
+    mix = make_mixture(wl, 0)
+    B0n, V0n = init_nmf(wl.N, wl.F, wl.K, wl.T, 0)
+    dev = torch.device("cuda:0")
+    Xc = torch.from_numpy(mix.X).to(dev)
+    B0 = torch.from_numpy(B0n).to(dev)
+    V0 = torch.from_numpy(V0n).to(dev)
+    units = wl.F * wl.T * wl.n_iter
+    log("timing FP32 ISS")
+    dt, C32, st32, stats = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", args.steps, args.warmup,
+                                     profile=1)
+    value = units * args.steps / dt
+    n_iss, ms_iss = stats[0]
+    avg_iss_ms = ms_iss / max(n_iss, 1)
+    flops_launch = wl.F * wl.T * iss_flops_per_unit(wl.mbar, wl.n_iter)
+    achieved = flops_launch / (avg_iss_ms * 1e-3) / 1e12
+    _, _, _, allstats = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", 1, 0, profile=-1)
+    names = ["w_update_iss", "v_partial", "v_final_mu", "final_rescale", "images", "lambda", "basis_update"]
+    kernel_ms = {names[i]: allstats[i][1] / max(allstats[i][0], 1) for i in range(7)}
+    log(f"FP32 ISS: {dt / args.steps * 1e3:.3f} ms/step, {value:.4e} F·T·it/s, W update avg "
+        f"{avg_iss_ms * 1e3:.1f} us ({achieved:.1f} TFLOP/s), status {st32}")
+    side = {}
+    if not args.no_side:
+        log("timing FP64 ISS")
+        dt64, C64, st64, _ = time_path(torch, Separator, wl, Xc, B0, V0, "fp64", "iss", args.side_steps, 1)
+        rel = float(torch.linalg.norm((C32.to(torch.complex128) - C64).flatten()) / torch.linalg.norm(C64.flatten()))
+        per_src = [float(torch.linalg.norm((C32[n].to(torch.complex128) - C64[n]).flatten())
+                         / torch.linalg.norm(C64[n].flatten())) for n in range(wl.N)]
+        side["iss_fp64"] = {"value": units * args.side_steps / dt64, "ms_per_step": dt64 / args.side_steps * 1e3,
+                            "status": st64}
+        side["iss_fp32_images_rel_err_vs_fp64"] = rel
+        side["iss_fp32_images_rel_err_vs_fp64_per_source"] = per_src
+        side["speedup_iss_fp32_vs_fp64"] = value / side["iss_fp64"]["value"]
+        log(f"FP64 ISS: {dt64 / args.side_steps * 1e3:.3f} ms/step; FP32 vs FP64 images rel {rel:.2e}")
+    out = {
+        "metric": "F·T·iters/s ISS vs IP vs FP64-ISS at rel err ≤1e-4; HBM GB/s fraction",
+        "value": value, "unit": "F·T·iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c3 single mixture: 60 s, N=3, M=4, RT60 0.8 s, STFT 4096/1024, D=16 stacked frames "
+                               "(Mbar=64, taps 22+21+21), K=30, 100 iterations, CTF-MNMF-ISS, bins split over "
+                               "teams of workgroups",
+                   "F": wl.F, "T": wl.T, "Mbar": wl.mbar, "K": wl.K, "iterations": wl.n_iter},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+                     "kernel": "k_iss_team (W update, each bin's frames split over a team of workgroups)",
+                     "avg_launch_us": avg_iss_ms * 1e3, "flops_per_launch": flops_launch},
+        "kernel_avg_ms": kernel_ms, "status": st32, "side_by_side": side, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +301,8 @@ def main() -> int:
     ap.add_argument("--batched", action="store_true",
                     help="time the batch of uneven mixtures instead of the single long mixture")
     ap.add_argument("--batch", type=int, default=256, help="mixtures in --batched mode")
+    ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
+                    help="c3: the 60 s, Mbar = 64 mixture (team launches) instead of the 10 s, Mbar = 24 one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -248,6 +316,8 @@ def main() -> int:
 
     if args.batched:
         return batched_bench(args)
+    if args.workload == "c3":
+        return precision_bench(args)
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4

@@ -34,7 +34,9 @@
  * waiting, except where stated.  Numeric faults found on the device (a
  * non-positive or non-finite ISS denominator, a singular IP system, a singular
  * W_f in the output stage, a non-finite multiplicative update) are latched in
- * a device status word and reported by ctfiss_sync_status().  No exceptions
+ * a device status word and reported by ctfiss_sync_status(); so is a team of
+ * workgroups sharing a bin whose members did not all publish their partial
+ * sums within the wait bound (code 6; the launch still completes).  No exceptions
  * cross this interface.  One context per stream; calls on one context must
  * not overlap from several host threads.
  */
@@ -91,7 +93,12 @@ typedef struct ctfiss_ctx ctfiss_ctx;
  * powers, activation partial sums, row power sums, scales) and the demixed
  * rows Y = W xbar [F][Mbar][T], which the ISS rule carries from one iteration
  * to the next instead of recomputing (the sweep and the rescale apply the same
- * row operations to W and Y, so the two agree up to rounding). */
+ * row operations to W and Y, so the two agree up to rounding).  Shapes whose
+ * bins do not fit one workgroup (e.g. Mbar = 64 with T ~ 1000) split each bin's
+ * frames over a team of up to 8 workgroups; their workspace also holds the
+ * exchange words of the team's partial sums (F * team_words 64-bit words, a
+ * few percent of Y).  The size depends on CTFISS_PLAN in the environment, as
+ * the launch shape chosen at create does. */
 int ctfiss_workspace_size(const ctfiss_shape* shape, int precision, size_t* bytes);
 
 /* Create a context.  rule: ctfiss_rule; vrule: ctfiss_vrule; floor >= 0 is

@@ -45,6 +45,39 @@ bool plan_for(int prec, int rule, const Dims& d, size_t max_lds, int G, int RPL,
   }
   return false;
 }
+
+// Team plan (ISS): the frames of each bin split over P workgroups of S =
+// ceil(T / P) frames (fewer members if the last ones would be empty).  A
+// member's slice must cover the Lmax - 1 frames its predecessor's tap-aligned
+// powers read from it.
+bool plan_for_team(int prec, const Dims& d, size_t max_lds, int G, int RPL, int P, int cpl_req, Plan* out) {
+  if (P < 2 || P > kMaxTeam) return false;
+  const int S = (d.T + P - 1) / P;
+  const int Pe = (d.T + S - 1) / S;
+  if (Pe < 2 || S < d.lmax - 1) return false;
+  const int* cpls = prec == 0 ? kCpl32 : kCpl64;
+  const int ncpl = prec == 0 ? (int)(sizeof(kCpl32) / sizeof(int)) : (int)(sizeof(kCpl64) / sizeof(int));
+  const int rs = prec == 0 ? 4 : 8;
+  const int need = (S + G - 1) / G;
+  for (int ci = 0; ci < ncpl; ++ci) {
+    const int cpl = cpls[ci];
+    if (cpl < need || (cpl_req > 0 && cpl != cpl_req)) continue;
+    const bool ok = prec == 0 ? have_tkernel<float>(G, cpl, RPL) : have_tkernel<double>(G, cpl, RPL);
+    if (!ok) continue;
+    const int groups = (d.Mb + RPL - 1) / RPL;
+    const int threads = (groups * G + 63) / 64 * 64;
+    if (threads > iter_max_threads(rs, cpl, RPL)) return false;
+    const size_t lds = iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, G, cpl, rs, false, Pe, S).total;
+    if (lds > max_lds) return false;
+    *out = Plan{G, cpl, RPL, threads, lds, 0, Pe, S};
+    return true;
+  }
+  return false;
+}
+
+// Team shapes tried in order, each with the fewest members that fit.
+constexpr GR kTeam32[] = {{16, 1}, {16, 2}, {32, 2}};
+constexpr GR kTeam64[] = {{16, 1}, {16, 2}};
 }  // namespace
 
 bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
@@ -76,14 +109,33 @@ bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
   }
   for (int i = 0; i < n; ++i)
     if (plan_for(prec, rule, d, max_lds, list[i].G, list[i].RPL, 0, out)) return true;
+  // ISS bins too long for one workgroup: teams of workgroups
+  if (rule == 0) {
+    const GR* tl = prec == 0 ? kTeam32 : kTeam64;
+    const int tn = prec == 0 ? (int)(sizeof(kTeam32) / sizeof(GR)) : (int)(sizeof(kTeam64) / sizeof(GR));
+    for (int P = 2; P <= kMaxTeam; ++P)
+      for (int i = 0; i < tn; ++i)
+        if (plan_for_team(prec, d, max_lds, tl[i].G, tl[i].RPL, P, 0, out)) return true;
+  }
   return false;
 }
 
-// "G,CPL,RPL" (used to tune launch shapes; CTFISS_PLAN in the environment).
+// "G,CPL,RPL" or "G,CPL,RPL,P" with P > 1 for a team of P workgroups per bin
+// (used to tune launch shapes; CTFISS_PLAN in the environment).
 bool plan_from_string(const char* spec, int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
-  int G = 0, cpl = 0, rpl = 0;
-  if (!spec || std::sscanf(spec, "%d,%d,%d", &G, &cpl, &rpl) != 3) return false;
+  int G = 0, cpl = 0, rpl = 0, P = 1;
+  if (!spec) return false;
+  const int n = std::sscanf(spec, "%d,%d,%d,%d", &G, &cpl, &rpl, &P);
+  if (n < 3) return false;
+  if (n == 4 && P > 1) return rule == 0 && plan_for_team(prec, d, max_lds, G, rpl, P, cpl, out);
   return plan_for(prec, rule, d, max_lds, G, rpl, cpl, out);
+}
+
+// Members per bin a plan string asks for (1 if none).
+int plan_string_team(const char* spec) {
+  int G = 0, cpl = 0, rpl = 0, P = 1;
+  if (!spec || std::sscanf(spec, "%d,%d,%d,%d", &G, &cpl, &rpl, &P) != 4) return 1;
+  return P > 1 ? (P < kMaxTeam ? P : kMaxTeam) : 1;
 }
 
 // Split of the bins for the activation partial sums: chunks of 64 bins (four
@@ -113,7 +165,8 @@ constexpr size_t kAlign = 256;
 constexpr int kClasses = 7;
 
 struct Layout {
-  size_t W, B, V, ilam, P, P0, musq, mu, vnum, vden, nllpart, status, work, Y, total;
+  size_t W, B, V, ilam, P, P0, musq, mu, vnum, vden, nllpart, status, work, Y, xch, total;
+  int team;  // members per bin the exchange words are sized for (0: none)
 };
 
 struct TimedLaunch {
@@ -184,6 +237,14 @@ Layout make_layout(const Dims& d, int precision) {
   L.status = take(kAlign);
   L.work = take(kAlign);
   L.Y = take((size_t)d.F * d.Mb * d.T * cs);
+  // Exchange words for team launches: sized for the plan an ISS context of
+  // this shape takes on gfx950 (or the one CTFISS_PLAN asks for).
+  Plan p;
+  L.team = 0;
+  if (choose_plan(precision, CTFISS_RULE_ISS, d, kMaxLdsBytes, &p) && p.team > 1) L.team = p.team;
+  const int forced = plan_string_team(std::getenv("CTFISS_PLAN"));
+  if (forced > 1 && forced > L.team) L.team = forced;
+  L.xch = L.team > 1 ? take((size_t)d.F * team_words(d.Mb, d.lmax, L.team, (int)rs) * 8) : 0;
   L.total = off;
   return L;
 }
@@ -202,6 +263,7 @@ struct ctfiss_ctx {
   VSplit vs;
   bool have_input, have_state;
   bool y_valid;  // the carried Y holds W xbar of the current W (ISS)
+  unsigned epoch;  // tag base of the last team launch's exchange words
   int prof;  // bit mask of timed kernel classes
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> pool;
@@ -287,6 +349,7 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
     return CTFISS_E_UNSUPPORTED;
   }
   if (images_lds(d) > (size_t)max_lds || nll_lds(d) > (size_t)max_lds) return CTFISS_E_UNSUPPORTED;
+  if (plan.team > 1 && plan.team > lay.team) return CTFISS_E_UNSUPPORTED;
   // Persistent W-update workgroups: as many as fit on the device at once
   // (CTFISS_WBLOCKS in the environment overrides it, for tuning); any count
   // >= 1 gives the same result, since the workgroups share out the bins.
@@ -322,13 +385,20 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   c->ptr.status = reinterpret_cast<int*>(c->ws + lay.status);
   c->ptr.work = reinterpret_cast<int*>(c->ws + lay.work);
   c->ptr.Y = c->ws + lay.Y;
+  c->ptr.xch = plan.team > 1 ? static_cast<void*>(c->ws + lay.xch) : nullptr;
   c->have_input = c->have_state = c->y_valid = false;
+  c->epoch = 0;
   c->prof = 0;
   for (int i = 0; i < kClasses; ++i) {
     c->launches[i] = 0;
     c->ms[i] = 0.0;
   }
-  if (launch_zero_status(c->ptr.status, c->stream) != hipSuccess) {
+  hipError_t ze = launch_zero_status(c->ptr.status, c->stream);
+  // exchange words start untagged (every launch's tags are nonzero)
+  if (ze == hipSuccess && c->ptr.xch)
+    ze = hipMemsetAsync(c->ptr.xch, 0, (size_t)d.F * team_words(d.Mb, d.lmax, plan.team, precision == CTFISS_FP32 ? 4 : 8) * 8,
+                        c->stream);
+  if (ze != hipSuccess) {
     delete c;
     return CTFISS_E_HIP;
   }
@@ -375,10 +445,11 @@ int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
   for (int it = 0; it < n_iter; ++it) {
     const bool mu = it > 0;  // the previous iteration's scale is still to be applied
     hipError_t e = timed(c, 5, [&] { return f32 ? lambda_t<float>(d, p, mu, s) : lambda_t<double>(d, p, mu, s); });
+    c->epoch = c->epoch % 0x1FFFFFFu + 1u;  // tags epoch * 128 + step stay within 32 bits
     if (e == hipSuccess)
       e = timed(c, 0, [&] {
-        return f32 ? wupdate_t<float>(c->rule, c->plan, d, p, mu, c->y_valid, s)
-                   : wupdate_t<double>(c->rule, c->plan, d, p, mu, c->y_valid, s);
+        return f32 ? wupdate_t<float>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, s)
+                   : wupdate_t<double>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, s);
       });
     if (e == hipSuccess && c->rule == CTFISS_RULE_ISS) c->y_valid = true;
     if (e == hipSuccess)
@@ -588,6 +659,10 @@ int ctfiss_batch_create(const ctfiss_shape* shapes, int32_t n, int precision, in
     }
     b->ctx.push_back(c);
     off = align_up(off + wb, kAlign);
+    if (c->plan.team > 1) {  // batched launches take one workgroup per bin
+      ctfiss_batch_destroy(b);
+      return CTFISS_E_UNSUPPORTED;
+    }
   }
   b->wsz = desc_w_bytes(precision);
   b->nsz = desc_n_bytes(precision);

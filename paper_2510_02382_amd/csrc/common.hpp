@@ -10,6 +10,7 @@ namespace ctfiss {
 constexpr int kMaxRows = 64;   // Mbar
 constexpr int kMaxSrc = 8;     // N
 constexpr int kMaxK = 64;      // K
+constexpr int kMaxTeam = 8;    // workgroups sharing the frames of one bin
 
 // Device fault codes latched in the status word (first one wins).
 enum Fault : int {
@@ -19,6 +20,7 @@ enum Fault : int {
   kFaultMu = 3,              // multiplicative update produced a non-finite factor
   kFaultOutSingular = 4,     // W_f singular in the source-image stage
   kFaultScale = 5,           // zero or non-finite row power in the rescale
+  kFaultTeamWait = 6,        // the workgroups of a bin did not all publish their sums in time
 };
 
 template <typename R>
@@ -150,10 +152,26 @@ __device__ __forceinline__ int find_problem(const int* start, int nprob, int ite
 // During the sweep: x, w, phi, yb, wb (+ q, aug, u, fac for IP).  After it the
 // per-row powers |y|^2, a[Mb][TP], reuse the same bytes from offset 0.
 struct IterLds {
-  size_t x, w, phi, yb, wb, q, aug, u, fac, a, misc, total;
+  size_t x, w, phi, yb, wb, q, aug, u, fac, a, xv, misc, total;
   int lx, lp, tp, lmax;
-  int rc;  // IP: rows whose inverse weighted covariances are held at once
+  int rc;     // IP: rows whose inverse weighted covariances are held at once
+  int team;   // workgroups per bin (1: a bin is one workgroup)
+  int slice;  // frames per team member (T for a single workgroup)
+  int ta;     // row stride of a (TP, plus the Lmax - 1 frames of the next member in a team)
 };
+
+// Exchange words of one bin in a team launch (64-bit words, one 32-bit
+// payload each, so an FP64 value takes two): the partial frame sums of the
+// ISS steps, [2 (step parity)][Mb][3][P][wpv]; the |y|^2 of the first Lmax - 1
+// frames of every member, [P][Mb][Lmax - 1][wpv]; the partial row powers,
+// [Mb][P][wpv].
+__host__ __device__ constexpr int team_step_words(int Mb, int P, int rsize) { return 2 * Mb * 3 * P * (rsize / 4); }
+__host__ __device__ constexpr int team_halo_words(int Mb, int lmax, int P, int rsize) {
+  return P * Mb * (lmax - 1) * (rsize / 4);
+}
+__host__ __device__ constexpr int team_words(int Mb, int lmax, int P, int rsize) {
+  return team_step_words(Mb, P, rsize) + team_halo_words(Mb, lmax, P, rsize) + Mb * P * (rsize / 4);
+}
 
 // LDS one workgroup may use on gfx950.
 constexpr size_t kMaxLdsBytes = 163840;
@@ -163,15 +181,19 @@ __host__ __device__ constexpr int ip_max_chunk(int rsize) { return rsize == 8 ? 
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// team > 1: the bin's frames are split over `team` workgroups of `slice`
+// frames each (slice <= G * cpl); the layout is that of one member.
 __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, int N, int lmax, int G, int cpl,
-                                                   int rsize, bool ip) {
+                                                   int rsize, bool ip, int team = 1, int slice = 0) {
   IterLds L{};
   const size_t cs = 2 * (size_t)rsize;
   L.tp = G * cpl;
   L.lx = D - 1 + L.tp;
   L.lp = lmax - 1 + L.tp;
   L.lmax = lmax;
-  (void)T;
+  L.team = team > 1 ? team : 1;
+  L.slice = team > 1 ? slice : T;
+  L.ta = team > 1 ? L.tp + lmax - 1 : L.tp;
   size_t off = 0;
   L.x = off; off += align_up((size_t)M * L.lx * cs, 16);
   L.w = off; off += align_up((size_t)Mb * Mb * cs, 16);
@@ -203,8 +225,12 @@ __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, 
     L.rc = 0;
   }
   L.a = 0;
-  const size_t asz = align_up((size_t)Mb * L.tp * rsize, 16);
+  const size_t asz = align_up((size_t)Mb * L.ta * rsize, 16);
   if (asz > off) off = asz;
+  // team: 32-bit payloads of the exchange words a wave gathers (one step's
+  // partial sums of every row; also the row powers of the epilogue)
+  L.xv = off;
+  if (L.team > 1) off += align_up((size_t)Mb * 3 * L.team * (rsize / 4) * 4, 16);
   L.misc = off; off += 64;
   L.total = off;
   return L;

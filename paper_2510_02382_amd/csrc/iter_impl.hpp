@@ -37,6 +37,8 @@ struct IterArgs {
   int* work;        // bin counter of the persistent workgroups (zeroed before the launch)
   Cx<R>* Y;         // [F][Mb][T] demixed rows carried between iterations (ISS), or null
   int yload;        // 1: start from the carried Y (rows scaled by the pending mu), 0: Y = W xbar
+  unsigned long long* xch;  // team launches: [F][team_words] exchange words, else null
+  unsigned epoch;           // team launches: tag base of this launch's exchange words
   int F, T, M, D, K;
   RowMap rm;
 };
@@ -52,7 +54,8 @@ struct BinLds {
   Cx<R>* aug;  // [Mb][Mb+1] (IP)
   Cx<R>* u;    // [Mb] (IP)
   Cx<R>* fac;  // [Mb+1] (IP)
-  R* a;        // [Mb][TP] |y|^2 after the sweep (reuses the bytes above)
+  R* a;        // [Mb][TA] |y|^2 after the sweep (reuses the bytes above)
+  unsigned* xv;  // team: gathered exchange payloads
   int* misc;
 };
 
@@ -69,6 +72,7 @@ __device__ __forceinline__ BinLds<R> carve(unsigned char* base, const IterLds& L
   s.u = reinterpret_cast<Cx<R>*>(base + L.u);
   s.fac = reinterpret_cast<Cx<R>*>(base + L.fac);
   s.a = reinterpret_cast<R*>(base + L.a);
+  s.xv = reinterpret_cast<unsigned*>(base + L.xv);
   s.misc = reinterpret_cast<int*>(base + L.misc);
   return s;
 }
@@ -97,9 +101,10 @@ __device__ __forceinline__ int per_bin(int v) {
 }
 
 // Stage 1: scaled W_f, zero-padded observation block and inverse variances into LDS.
+// The frames staged start at t0 (a team member's first frame; 0 otherwise).
 template <typename R>
 __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid,
-                         bool need_x) {
+                         bool need_x, int t0 = 0) {
   const int nthr = blockDim.x;
   const int T = a.T, M = a.M, F = a.F, Mb = per_bin(a.rm.Mb), N = a.rm.N;
   const int LX = per_bin(L.lx), LP = per_bin(L.lp), Dm1 = a.D - 1, Lm1 = L.lmax - 1;
@@ -114,11 +119,11 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
     s.w[i] = w;
   }
   for (int i = tid; i < (need_x ? M * LX : 0); i += nthr) {
-    const int m = i / LX, t = i - m * LX - Dm1;
+    const int m = i / LX, t = i - m * LX - Dm1 + t0;
     s.x[i] = (t >= 0 && t < T) ? a.X[((size_t)m * F + f) * T + t] : Cx<R>{R(0), R(0)};
   }
   for (int i = tid; i < N * LP; i += nthr) {
-    const int n = i / LP, t = i - n * LP - Lm1;
+    const int n = i / LP, t = i - n * LP - Lm1 + t0;
     s.phi[i] = (t >= 0 && t < T) ? a.ilam[((size_t)n * F + f) * T + t] : R(0);
   }
   __syncthreads();
@@ -127,7 +132,7 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
 // Stage 2: y_p[t] = sum_c W[p][c] xbar_c[t] for the lane's rows and frames.
 template <typename R, int G, int CPL, int RPL>
 __device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int g,
-                                           int q, Cx<R> (&y)[RPL][CPL]) {
+                                           int q, Cx<R> (&y)[RPL][CPL], int nloc) {
   const int M = per_bin(a.M), D = a.D, Mb = a.rm.Mb, LX = L.lx, Dm1 = D - 1;
 #pragma unroll
   for (int i = 0; i < RPL; ++i)
@@ -153,12 +158,12 @@ __device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>
       for (int i = 0; i < RPL; ++i) y[i][j] = cfma(w[i], xv, y[i][j]);
     }
   }
-  // Padded frames t >= T: a delayed block still reads real frames there
-  // (x[t - d] with t - d < T), so clear them; the rank-1 updates keep them zero
-  // and they add nothing to the frame sums.
+  // Padded frames (past T, or past a team member's slice): a delayed block
+  // still reads real frames there, so clear them; the rank-1 updates keep them
+  // zero and they add nothing to the frame sums.
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
-    if (q + G * j >= a.T) {
+    if (q + G * j >= nloc) {
 #pragma unroll
       for (int i = 0; i < RPL; ++i) y[i][j] = Cx<R>{R(0), R(0)};
     }
@@ -168,17 +173,18 @@ __device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>
 // Stage 2 (carried): the lane's rows and frames of the stored Y, divided by the
 // pending row scale exactly as W is in load_bin; zero for t >= T.
 template <typename R, int G, int CPL, int RPL>
-__device__ __forceinline__ void load_rows(const IterArgs<R>& a, int f, int g, int q, Cx<R> (&y)[RPL][CPL]) {
+__device__ __forceinline__ void load_rows(const IterArgs<R>& a, int f, int g, int q, Cx<R> (&y)[RPL][CPL],
+                                          int t0, int nloc) {
   const int T = a.T, Mb = a.rm.Mb;
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int p = g * RPL + i;
     const bool ok = p < Mb;
     const R m = (ok && a.mu) ? a.mu[p] : R(1);
-    const Cx<R>* yr = a.Y + ((size_t)f * Mb + (ok ? p : 0)) * T + q;
+    const Cx<R>* yr = a.Y + ((size_t)f * Mb + (ok ? p : 0)) * T + t0 + q;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
-      Cx<R> v = (ok && q + G * j < T) ? yr[G * j] : Cx<R>{R(0), R(0)};
+      Cx<R> v = (ok && q + G * j < nloc) ? yr[G * j] : Cx<R>{R(0), R(0)};
       if (a.mu) {
         v.x = v.x / m;
         v.y = v.y / m;
@@ -224,15 +230,234 @@ __device__ void epilogue(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
   }
 }
 
-// ------------------------------------------------------------------ ISS
+// Orders the LDS accesses of one wave (its lanes then see each other's writes).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------------ teams
+// A bin whose Mbar rows x T frames do not fit the registers of one workgroup
+// is split by frames over a team of P workgroups: member j holds frames
+// [j S, min(T, (j + 1) S)) of every row and its own copy of W_f.  The frame
+// sums of an ISS step are then partial per member: each member publishes the
+// partial sums of its rows in exchange words of its bin and gathers those of
+// all members, adding them in member order, so that every member takes the
+// same steps bit for bit.  An exchange word holds a 32-bit tag (launch epoch
+// and step) and a 32-bit payload, stored and loaded as one relaxed
+// device-scope 64-bit atomic: a reader that sees the expected tag has the
+// matching payload, and no fences are needed.  The words of consecutive steps
+// alternate between two slots; no member gets two steps ahead of another,
+// since it waits for that member's sums of the step in between.
+//
+// Members claim (bin, member) items in order from the work counter, so the
+// members of a bin are all running once P workgroups are resident, and every
+// wait ends.  Each wait is bounded all the same: past kTeamSpin polls, or once
+// another fault is latched, it stops and the launch completes with
+// kFaultTeamWait latched.
+constexpr int kTeamSpin = 1 << 20;
+
+__device__ __forceinline__ void xput(unsigned long long* w, unsigned tag, unsigned payload) {
+  __hip_atomic_store(w, ((unsigned long long)tag << 32) | payload, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename R>
+__device__ __forceinline__ void xput_val(unsigned long long* w, unsigned tag, R v) {
+  if constexpr (sizeof(R) == 4) {
+    xput(w, tag, __float_as_uint(v));
+  } else {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    xput(w, tag, (unsigned)b);
+    xput(w + 1, tag, (unsigned)(b >> 32));
+  }
+}
+// Value k of gathered payloads (an FP64 value spans two words, low half first).
+template <typename R>
+__device__ __forceinline__ R xval(const unsigned* v, int k) {
+  if constexpr (sizeof(R) == 4)
+    return __uint_as_float(v[k]);
+  else
+    return __hiloint2double((int)v[2 * k + 1], (int)v[2 * k]);
+}
+
+// Wave-wide wait: word k (< KW) of a lane is src[idx[k]] (idx < 0: none);
+// once it carries `tag`, its payload goes to *dst[k].  Every lane of the wave
+// must call it.  Returns false if it stopped before all words arrived.
+template <int KW>
+__device__ bool xgather(const unsigned long long* src, const int (&idx)[KW], unsigned* const (&dst)[KW],
+                        unsigned tag, const int* status) {
+  unsigned pend = 0;
+#pragma unroll
+  for (int k = 0; k < KW; ++k)
+    if (idx[k] >= 0) pend |= 1u << k;
+  for (int spin = 0;; ++spin) {
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      if (pend & (1u << k)) {
+        const unsigned long long w = __hip_atomic_load(src + idx[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((unsigned)(w >> 32) == tag) {
+          *dst[k] = (unsigned)w;
+          pend &= ~(1u << k);
+        }
+      }
+    }
+    if (!__any(pend != 0)) return true;
+    if (spin >= kTeamSpin) return false;
+    if ((spin & 63) == 63 && __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// One ISS step's exchange: publish this member's partial (a_p, d_p) of the
+// group's rows, gather every member's and replace the partials by the totals.
+template <typename R, int G, int RPL>
+__device__ __forceinline__ bool team_step_sums(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L,
+                                               unsigned long long* xb, int mem, int r, int g, int q, R (&ar)[RPL],
+                                               R (&ai)[RPL], R (&dd)[RPL]) {
+  constexpr int WPV = sizeof(R) / 4;
+  constexpr int KW = (RPL * 3 * kMaxTeam * WPV + G - 1) / G;
+  const int Mb = a.rm.Mb, P = L.team;
+  const unsigned tag = a.epoch * 128u + (unsigned)r;
+  unsigned long long* xs = xb + (size_t)(r & 1) * (team_step_words(Mb, P, sizeof(R)) / 2);
+  if (q < 3 * RPL) {
+    const int i = q / 3, c = q - 3 * i;
+    R v = R(0);
+#pragma unroll
+    for (int ii = 0; ii < RPL; ++ii)
+      if (ii == i) v = c == 0 ? ar[ii] : (c == 1 ? ai[ii] : dd[ii]);
+    const int p = g * RPL + i;
+    if (p < Mb) xput_val<R>(xs + ((size_t)(p * 3 + c) * P + mem) * WPV, tag, v);
+  }
+  const int per_row = 3 * P * WPV, w0 = g * RPL * per_row;
+  int idx[KW];
+  unsigned* dst[KW];
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int e = q + G * k;
+    const bool ok = e < RPL * per_row && g * RPL + e / per_row < Mb;
+    idx[k] = ok ? w0 + e : -1;
+    dst[k] = s.xv + (ok ? w0 + e : 0);
+  }
+  const bool ok = xgather<KW>(xs, idx, dst, tag, a.status);
+  wave_sync();  // a group's lanes lie in one wave
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int p = g * RPL + i;
+    R t[3] = {R(0), R(0), R(0)};
+    if (p < Mb) {
+      for (int c = 0; c < 3; ++c)
+        for (int m = 0; m < P; ++m) t[c] += xval<R>(s.xv, (p * 3 + c) * P + m);
+    }
+    ar[i] = t[0];
+    ai[i] = t[1];
+    dd[i] = t[2];
+  }
+  return ok;
+}
+
+// Stage 4 of a team member: as epilogue(), with the tap-aligned powers of the
+// member's last frames taking |y|^2 of the next member's first Lmax - 1 frames
+// (exchanged), and the row powers summed over members in member order (by
+// member 0).
 template <typename R, int G, int CPL, int RPL>
-__device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f) {
+__device__ bool epilogue_team(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int mem, int t0,
+                              int nloc, int tid, int g, int q, const Cx<R> (&y)[RPL][CPL], unsigned long long* xb) {
+  constexpr int WPV = sizeof(R) / 4;
+  constexpr int KW = 4;
+  const int T = per_bin(a.T), Mb = a.rm.Mb, N = a.rm.N, F = a.F, TA = L.ta, P = L.team, S = L.slice;
+  const int H = L.lmax - 1, nthr = blockDim.x;
+  const unsigned tag = a.epoch * 128u + 127u;
+  unsigned long long* xh = xb + team_step_words(Mb, P, sizeof(R));
+  unsigned long long* xm = xh + team_halo_words(Mb, L.lmax, P, sizeof(R));
+  bool ok = true;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int p = g * RPL + i;
+    R rs = 0;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const R v = cabs2(y[i][j]);
+      rs += v;
+      if (p < Mb) s.a[p * TA + q + G * j] = v;
+    }
+    rs = group_sum<G>(rs);
+    if (p < Mb && q == 0) xput_val<R>(xm + ((size_t)p * P + mem) * WPV, tag, rs);
+  }
+  __syncthreads();
+  if (mem > 0) {  // my first H frames: the halo of the previous member
+    for (int e = tid; e < Mb * H; e += nthr) {
+      const int p = e / H, h = e - p * H;
+      xput_val<R>(xh + ((size_t)(mem * Mb + p) * H + h) * WPV, tag, s.a[p * TA + h]);
+    }
+  }
+  if (mem + 1 < P) {  // the next member's first H frames follow my S frames
+    const int nw = Mb * H * WPV;
+    const unsigned long long* src = xh + (size_t)(mem + 1) * Mb * H * WPV;
+    for (int e0 = 0; e0 < nw; e0 += nthr * KW) {
+      int idx[KW];
+      unsigned* dst[KW];
+#pragma unroll
+      for (int k = 0; k < KW; ++k) {
+        const int e = e0 + tid + nthr * k;
+        const bool in = e < nw;
+        const int v = e / WPV, half = e - v * WPV, p = v / (H > 0 ? H : 1), h = v - p * H;
+        idx[k] = in ? e : -1;
+        dst[k] = reinterpret_cast<unsigned*>(s.a + (in ? p * TA + S + h : 0)) + (in ? half : 0);
+      }
+      ok &= xgather<KW>(src, idx, dst, tag, a.status);
+    }
+  }
+  if (mem == 0) {  // every member's row powers
+    const int nw = Mb * P * WPV;
+    for (int e0 = 0; e0 < nw; e0 += nthr * KW) {
+      int idx[KW];
+      unsigned* dst[KW];
+#pragma unroll
+      for (int k = 0; k < KW; ++k) {
+        const int e = e0 + tid + nthr * k;
+        idx[k] = e < nw ? e : -1;
+        dst[k] = s.xv + (e < nw ? e : 0);
+      }
+      ok &= xgather<KW>(xm, idx, dst, tag, a.status);
+    }
+  }
+  __syncthreads();
+  if (mem == 0) {
+    for (int p = tid; p < Mb; p += nthr) {
+      R acc = 0;
+      for (int m = 0; m < P; ++m) acc += xval<R>(s.xv, p * P + m);
+      a.musq[(size_t)p * F + f] = acc;
+    }
+  }
+  for (int i = tid; i < N * nloc; i += nthr) {
+    const int n = i / nloc, tl = i - n * nloc, t = t0 + tl;
+    const int r0 = a.rm.r0[n], Ln = a.rm.L[n];
+    const R* ar = s.a + r0 * TA + tl;
+    R acc = 0;
+    for (int l = 0; l < Ln && t + l < T; ++l) acc += ar[l * TA + l];
+    const size_t o = ((size_t)n * F + f) * T + t;
+    a.P[o] = acc;
+    if (a.P0) a.P0[o] = ar[0];
+  }
+  return ok;
+}
+
+// ------------------------------------------------------------------ ISS
+// TEAM: the workgroup is member `mem` of the bin's team (frames
+// [t0, t0 + nloc)); otherwise it holds all T frames.
+template <typename R, int G, int CPL, int RPL, bool TEAM = false>
+__device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int mem = 0) {
   const int tid = lane_tid();
   const int g = tid / G, q = tid - g * G;
   const int T = a.T, Mb = a.rm.Mb, TP = L.tp, LP = L.lp, Lm1 = L.lmax - 1;
   constexpr int WPL = (kMaxRows + G - 1) / G;
+  const int t0 = TEAM ? mem * L.slice : 0;
+  const int nloc = TEAM ? (T - t0 < L.slice ? T - t0 : L.slice) : T;
+  unsigned long long* xb = TEAM ? a.xch + (size_t)f * team_words(Mb, L.lmax, L.team, sizeof(R)) : nullptr;
+  bool wait_ok = true;
 
-  load_bin(a, s, L, f, tid, !a.yload);
+  load_bin(a, s, L, f, tid, !a.yload, t0);
 
   // Y = W xbar equals the previous iteration's Y with rows divided by mu: the
   // sweep applies the same rank-1 steps to W and Y, and the rescale divides the
@@ -240,9 +465,9 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
   // MACs per frame) by one read and one write of Y.
   Cx<R> y[RPL][CPL];
   if (a.yload)
-    load_rows<R, G, CPL, RPL>(a, f, g, q, y);
+    load_rows<R, G, CPL, RPL>(a, f, g, q, y, t0, nloc);
   else
-    demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y);
+    demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y, nloc);
 
   Cx<R> wreg[RPL][WPL];
   R ph[RPL][CPL];  // weights of the lane's rows and frames, phi[n][t - l]
@@ -305,22 +530,30 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
         dd[i] += ty * yr[j].y;
       }
     }
+    // z_p from the row's frame sums
+    auto coef = [&](int i) {
+      const int p = g * RPL + i;
+      if (p == r) {
+        const R dr = dd[i] * invT;
+        bad |= !finite_pos(dr);
+        return Cx<R>{R(1) - fast_rsqrt(dr), R(0)};
+      }
+      bad |= p < Mb && !finite_pos(dd[i]);
+      const R inv = fast_rcp(dd[i]);
+      return Cx<R>{ar[i] * inv, ai[i] * inv};
+    };
     Cx<R> z[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       ar[i] = group_sum<G>(ar[i]);
       ai[i] = group_sum<G>(ai[i]);
       dd[i] = group_sum<G>(dd[i]);
-      const int p = g * RPL + i;
-      if (p == r) {
-        const R dr = dd[i] * invT;
-        bad |= !finite_pos(dr);
-        z[i] = Cx<R>{R(1) - fast_rsqrt(dr), R(0)};
-      } else {
-        bad |= p < Mb && !finite_pos(dd[i]);
-        const R inv = fast_rcp(dd[i]);
-        z[i] = Cx<R>{ar[i] * inv, ai[i] * inv};
-      }
+      if constexpr (!TEAM) z[i] = coef(i);
+    }
+    if constexpr (TEAM) {  // the partial sums of every member, added in member order
+      wait_ok &= team_step_sums<R, G, RPL>(a, s, L, xb, mem, r, g, q, ar, ai, dd);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) z[i] = coef(i);
     }
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
@@ -345,16 +578,21 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
 #pragma unroll
     for (int k = 0; k < WPL; ++k) {
       const int c = q + G * k;
-      if (p < Mb && c < Mb) a.W[((size_t)f * Mb + p) * Mb + c] = wreg[i][k];
+      if (p < Mb && c < Mb && (!TEAM || mem == 0)) a.W[((size_t)f * Mb + p) * Mb + c] = wreg[i][k];
     }
     if (a.Y && p < Mb) {
-      Cx<R>* yr = a.Y + ((size_t)f * Mb + p) * T + q;
+      Cx<R>* yr = a.Y + ((size_t)f * Mb + p) * T + t0 + q;
 #pragma unroll
       for (int j = 0; j < CPL; ++j)
-        if (q + G * j < T) yr[G * j] = y[i][j];
+        if (q + G * j < nloc) yr[G * j] = y[i][j];
     }
   }
-  epilogue<R, G, CPL, RPL>(a, s, L, f, tid, g, q, y);
+  if constexpr (TEAM) {
+    wait_ok &= epilogue_team<R, G, CPL, RPL>(a, s, L, f, mem, t0, nloc, tid, g, q, y, xb);
+    latch_wave(a.status, !wait_ok, kFaultTeamWait);
+  } else {
+    epilogue<R, G, CPL, RPL>(a, s, L, f, tid, g, q, y);
+  }
 }
 
 // Persistent workgroups: each pulls bins from a.work until all F are taken,
@@ -374,6 +612,19 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_mi
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
   for (int f = next_bin(a, s); f < a.F; f = next_bin(a, s)) iss_bin<R, G, CPL, RPL>(a, s, L, f);
+}
+
+// Team launch: the persistent workgroups take (bin, member) items in order,
+// item = bin * P + member.
+template <typename R, int G, int CPL, int RPL>
+__global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss_team(IterArgs<R> a, IterLds L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BinLds<R> s = carve<R>(smem, L);
+  const int P = L.team;
+  for (int it = next_bin(a, s); it < a.F * P; it = next_bin(a, s)) {
+    const int f = it / P;
+    iss_bin<R, G, CPL, RPL, true>(a, s, L, f, it - f * P);
+  }
 }
 
 // Batched ISS: the persistent workgroups take (problem, bin) items from one
@@ -412,12 +663,6 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_mi
 // W^{-1} is inverted once per bin and kept current across the sweep by the
 // Sherman-Morrison update for a changed row of W.
 
-// Orders the LDS accesses of one wave (its lanes then see each other's writes).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <typename R>
 __device__ __forceinline__ Cx<R> crecip(Cx<R> v) {
@@ -693,7 +938,7 @@ __device__ void ip_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& 
   // W_f out, then y = W xbar of the final W for the shared epilogue.
   for (int i = tid; i < Mb * Mb; i += nthr) a.W[(size_t)f * Mb * Mb + i] = s.w[i];
   Cx<R> y[RPL][CPL];
-  demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y);
+  demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y, a.T);
   epilogue<R, G, CPL, RPL>(a, s, L, f, tid, g, q, y);
 }
 

@@ -13,11 +13,14 @@ struct Dims {
 };
 
 // Launch shape of the W-update kernels: groups of G lanes, CPL frames per lane,
-// RPL rows per lane.
+// RPL rows per lane; team > 1: each bin's frames are split over `team`
+// workgroups of `slice` frames (ISS only).
 struct Plan {
   int G, CPL, RPL, threads;
   size_t lds;
-  int blocks;  // persistent workgroups launched (resident ones; at most F)
+  int blocks;  // persistent workgroups launched (resident ones; at most F items)
+  int team = 1;
+  int slice = 0;
 };
 
 // Type-erased device pointers of one context.
@@ -37,6 +40,7 @@ struct Ptrs {
   int* status;
   int* work;
   void* Y;  // [F][Mb][T] carried demixed rows (ISS)
+  void* xch;  // [F][team_words] exchange words of team launches, or null
 };
 
 struct VSplit {
@@ -48,12 +52,14 @@ constexpr int kCpl32[] = {4, 8, 10, 12, 16, 20, 24, 28, 32};
 constexpr int kCpl64[] = {4, 6, 8, 10, 12, 16};
 
 bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out);
+int plan_string_team(const char* spec);
 bool plan_from_string(const char* spec, int prec, int rule, const Dims& d, size_t max_lds, Plan* out);
 VSplit choose_vsplit(const Dims& d);
 
 // Typed launchers, defined once per precision.
 template <typename R>
-hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload, hipStream_t s);
+hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload,
+                     unsigned epoch, hipStream_t s);
 template <typename R>
 hipError_t lambda_t(const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s);
 template <typename R>
@@ -72,6 +78,8 @@ template <typename R>
 hipError_t identity_t(const Dims& d, void* W, hipStream_t s);
 template <typename R>
 bool have_wkernel(int rule, int G, int cpl, int rpl);
+template <typename R>
+bool have_tkernel(int G, int cpl, int rpl);
 template <typename R>
 int resident_wblocks(int rule, const Plan& p, const Dims& d);
 

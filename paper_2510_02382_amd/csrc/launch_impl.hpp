@@ -73,10 +73,37 @@ bool have_wkernel(int rule, int G, int cpl, int rpl) {
   return pick<R>(rule, G, cpl, rpl) != nullptr;
 }
 
+// Team (frame-split) ISS kernels: Mbar up to 64 with long signals.
+template <typename R>
+WFn<R> pickt(int G, int cpl, int rpl) {
+  if constexpr (sizeof(R) == 4) {
+    if (G == 16 && rpl == 1 && cpl == 16) return &k_iss_team<R, 16, 16, 1>;
+    if (G == 16 && rpl == 1 && cpl == 8) return &k_iss_team<R, 16, 8, 1>;
+    if (G == 16 && rpl == 2 && cpl == 8) return &k_iss_team<R, 16, 8, 2>;
+    if (G == 32 && rpl == 2 && cpl == 8) return &k_iss_team<R, 32, 8, 2>;
+    if (G == 32 && rpl == 2 && cpl == 4) return &k_iss_team<R, 32, 4, 2>;
+  } else {
+    if (G == 16 && rpl == 1 && cpl == 8) return &k_iss_team<R, 16, 8, 1>;
+    if (G == 16 && rpl == 1 && cpl == 4) return &k_iss_team<R, 16, 4, 1>;
+    if (G == 16 && rpl == 2 && cpl == 4) return &k_iss_team<R, 16, 4, 2>;
+  }
+  return nullptr;
+}
+
+template <typename R>
+bool have_tkernel(int G, int cpl, int rpl) {
+  return pickt<R>(G, cpl, rpl) != nullptr;
+}
+
+template <typename R>
+WFn<R> pick_plan(int rule, const Plan& p) {
+  return p.team > 1 ? (rule == 0 ? pickt<R>(p.G, p.CPL, p.RPL) : nullptr) : pick<R>(rule, p.G, p.CPL, p.RPL);
+}
+
 // Workgroups of the W-update kernel that fit on the device at once.
 template <typename R>
 int resident_wblocks(int rule, const Plan& p, const Dims& d) {
-  WFn<R> fn = pick<R>(rule, p.G, p.CPL, p.RPL);
+  WFn<R> fn = pick_plan<R>(rule, p);
   int dev = 0, cus = 0, per_cu = 0;
   if (!fn || hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
@@ -84,8 +111,8 @@ int resident_wblocks(int rule, const Plan& p, const Dims& d) {
       hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, p.threads, p.lds) != hipSuccess) return 0;
-  const long long n = (long long)per_cu * cus;
-  return n < 1 ? 0 : (int)(n < d.F ? n : d.F);
+  const long long n = (long long)per_cu * cus, items = (long long)d.F * (p.team > 1 ? p.team : 1);
+  return n < 1 ? 0 : (int)(n < items ? n : items);
 }
 
 template <typename R>
@@ -102,6 +129,8 @@ IterArgs<R> make_iargs(int rule, const Dims& d, const Ptrs& ptr, bool apply_mu, 
   a.work = ptr.work;
   a.Y = rule == 0 ? static_cast<Cx<R>*>(ptr.Y) : nullptr;
   a.yload = (rule == 0 && yload) ? 1 : 0;
+  a.xch = static_cast<unsigned long long*>(ptr.xch);
+  a.epoch = 0;
   a.F = d.F;
   a.T = d.T;
   a.M = d.M;
@@ -112,20 +141,23 @@ IterArgs<R> make_iargs(int rule, const Dims& d, const Ptrs& ptr, bool apply_mu, 
 }
 
 inline IterLds wlayout(int rule, const Plan& p, const Dims& d, int rsize) {
-  return iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, rsize, rule != 0);
+  return iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, rsize, rule != 0, p.team, p.slice);
 }
 
 template <typename R>
-hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload, hipStream_t s) {
-  WFn<R> fn = pick<R>(rule, p.G, p.CPL, p.RPL);
-  if (!fn) return hipErrorInvalidValue;
-  const IterArgs<R> a = make_iargs<R>(rule, d, ptr, apply_mu, yload);
+hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload,
+                     unsigned epoch, hipStream_t s) {
+  WFn<R> fn = pick_plan<R>(rule, p);
+  if (!fn || (p.team > 1 && !ptr.xch)) return hipErrorInvalidValue;
+  IterArgs<R> a = make_iargs<R>(rule, d, ptr, apply_mu, yload);
+  a.epoch = epoch;
   const IterLds L = wlayout(rule, p, d, (int)sizeof(R));
   if (L.total > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, dim3(p.blocks > 0 ? p.blocks : d.F), dim3(p.threads), L.total, s, a, L);
+  const int items = d.F * (p.team > 1 ? p.team : 1);
+  hipLaunchKernelGGL(fn, dim3(p.blocks > 0 ? p.blocks : items), dim3(p.threads), L.total, s, a, L);
   return hipGetLastError();
 }
 
@@ -255,6 +287,7 @@ template <typename R>
 void fill_wdesc(void* dst, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload) {
   WDesc<R> w;
   w.a = make_iargs<R>(0, d, ptr, apply_mu, yload);
+  w.a.xch = nullptr;
   w.L = wlayout(0, p, d, (int)sizeof(R));
   std::memcpy(dst, &w, sizeof(w));
 }
@@ -410,10 +443,11 @@ hipError_t identity_t(const Dims& d, void* W, hipStream_t s) {
 }
 
 #define CTFISS_INSTANTIATE(R)                                                                                  \
-  template hipError_t wupdate_t<R>(int, const Plan&, const Dims&, const Ptrs&, bool, bool, hipStream_t);       \
+  template hipError_t wupdate_t<R>(int, const Plan&, const Dims&, const Ptrs&, bool, bool, unsigned, hipStream_t); \
   template hipError_t lambda_t<R>(const Dims&, const Ptrs&, bool, hipStream_t);                               \
   template hipError_t nmfb_t<R>(const Dims&, const Ptrs&, double, bool, hipStream_t);                         \
   template bool have_wkernel<R>(int, int, int, int);                                                          \
+  template bool have_tkernel<R>(int, int, int);                                                               \
   template int resident_wblocks<R>(int, const Plan&, const Dims&);                                            \
   template hipError_t vpart_t<R>(const Dims&, const VSplit&, const Ptrs&, bool, hipStream_t);                 \
   template hipError_t vfinal_t<R>(const Dims&, const VSplit&, const Ptrs&, double, bool, hipStream_t);        \
