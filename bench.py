@@ -60,8 +60,8 @@ def run_config(sep, X, B0, V0, n_iter):
 
 def time_path(torch, Separator, wl, Xc, B0, V0, precision, rule, steps, warmup, profile=0):
     sep = Separator(wl.F, wl.T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision=precision, rule=rule)
-    rd = torch.float32 if precision == "fp32" else torch.float64
-    cd = torch.complex64 if precision == "fp32" else torch.complex128
+    rd = torch.float64 if precision == "fp64" else torch.float32
+    cd = torch.complex128 if precision == "fp64" else torch.complex64
     X = Xc.to(cd).contiguous()
     B = B0.to(rd).contiguous()
     V = V0.to(rd).contiguous()
@@ -228,8 +228,10 @@ def precision_bench(args) -> int:
     """Long-signal workload with Mbar = 64: 60 s at 16 kHz, N=3, M=4, RT60 0.8 s, STFT 4096/1024
     (F=2049, T=938), D=16 stacked frames (taps 22+21+21), K=30, 100 iterations.  A bin's 64 rows x
     938 frames exceed one workgroup, so the W update runs as teams of workgroups splitting each
-    bin's frames.  The FP32 path is timed (value) and checked against the FP64 path on the same
-    mixture (the FP64 team path is checked against the CPU oracle by the test-suite)."""
+    bin's frames.  The mixed-precision path (FP32 data and frame sums, FP64 W rows) is timed
+    (value); the FP32 and FP64 paths run alongside on the same mixture, and the images of both
+    FP32-data paths are compared with the FP64 path's (which the test-suite checks against the
+    CPU oracle)."""
     import torch
 
     from datagen import WORKLOADS, init_nmf, make_mixture
@@ -245,46 +247,56 @@ def precision_bench(args) -> int:
     B0 = torch.from_numpy(B0n).to(dev)
     V0 = torch.from_numpy(V0n).to(dev)
     units = wl.F * wl.T * wl.n_iter
-    log("timing FP32 ISS")
-    dt, C32, st32, stats = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", args.steps, args.warmup,
-                                     profile=1)
+    log("timing mixed-precision ISS (FP32 data and sums, FP64 W rows)")
+    dt, Cm, stm, stats = time_path(torch, Separator, wl, Xc, B0, V0, "mixed", "iss", args.steps, args.warmup,
+                                   profile=1)
     value = units * args.steps / dt
     n_iss, ms_iss = stats[0]
     avg_iss_ms = ms_iss / max(n_iss, 1)
     flops_launch = wl.F * wl.T * iss_flops_per_unit(wl.mbar, wl.n_iter)
     achieved = flops_launch / (avg_iss_ms * 1e-3) / 1e12
-    _, _, _, allstats = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", 1, 0, profile=-1)
+    _, _, _, allstats = time_path(torch, Separator, wl, Xc, B0, V0, "mixed", "iss", 1, 0, profile=-1)
     names = ["w_update_iss", "v_partial", "v_final_mu", "final_rescale", "images", "lambda", "basis_update"]
     kernel_ms = {names[i]: allstats[i][1] / max(allstats[i][0], 1) for i in range(7)}
-    log(f"FP32 ISS: {dt / args.steps * 1e3:.3f} ms/step, {value:.4e} F·T·it/s, W update avg "
-        f"{avg_iss_ms * 1e3:.1f} us ({achieved:.1f} TFLOP/s), status {st32}")
+    log(f"mixed ISS: {dt / args.steps * 1e3:.3f} ms/step, {value:.4e} F·T·it/s, W update avg "
+        f"{avg_iss_ms * 1e3:.1f} us ({achieved:.1f} TFLOP/s), status {stm}")
     side = {}
     if not args.no_side:
+        def errs(C, ref):
+            tot = float(torch.linalg.norm((C.to(torch.complex128) - ref).flatten()) / torch.linalg.norm(ref.flatten()))
+            per = [float(torch.linalg.norm((C[n].to(torch.complex128) - ref[n]).flatten())
+                         / torch.linalg.norm(ref[n].flatten())) for n in range(wl.N)]
+            return tot, per
+        log("timing FP32 ISS")
+        dt32, C32, st32, _ = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", args.side_steps, 1)
         log("timing FP64 ISS")
         dt64, C64, st64, _ = time_path(torch, Separator, wl, Xc, B0, V0, "fp64", "iss", args.side_steps, 1)
-        rel = float(torch.linalg.norm((C32.to(torch.complex128) - C64).flatten()) / torch.linalg.norm(C64.flatten()))
-        per_src = [float(torch.linalg.norm((C32[n].to(torch.complex128) - C64[n]).flatten())
-                         / torch.linalg.norm(C64[n].flatten())) for n in range(wl.N)]
+        em, em_src = errs(Cm, C64)
+        e32, e32_src = errs(C32, C64)
+        side["iss_fp32"] = {"value": units * args.side_steps / dt32, "ms_per_step": dt32 / args.side_steps * 1e3,
+                            "status": st32, "images_rel_err_vs_fp64": e32, "per_source": e32_src}
         side["iss_fp64"] = {"value": units * args.side_steps / dt64, "ms_per_step": dt64 / args.side_steps * 1e3,
                             "status": st64}
-        side["iss_fp32_images_rel_err_vs_fp64"] = rel
-        side["iss_fp32_images_rel_err_vs_fp64_per_source"] = per_src
-        side["speedup_iss_fp32_vs_fp64"] = value / side["iss_fp64"]["value"]
-        log(f"FP64 ISS: {dt64 / args.side_steps * 1e3:.3f} ms/step; FP32 vs FP64 images rel {rel:.2e}")
+        side["iss_mixed_images_rel_err_vs_fp64"] = em
+        side["iss_mixed_images_rel_err_vs_fp64_per_source"] = em_src
+        side["speedup_iss_mixed_vs_fp64"] = value / side["iss_fp64"]["value"]
+        log(f"FP32 ISS: {dt32 / args.side_steps * 1e3:.3f} ms/step, images rel {e32:.2e} vs FP64; "
+            f"FP64 ISS: {dt64 / args.side_steps * 1e3:.3f} ms/step; mixed images rel {em:.2e} vs FP64")
     out = {
         "metric": "F·T·iters/s ISS vs IP vs FP64-ISS at rel err ≤1e-4; HBM GB/s fraction",
         "value": value, "unit": "F·T·iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f32 (W rows f64)", "data": "synthetic",
         "config": {"workload": "c3 single mixture: 60 s, N=3, M=4, RT60 0.8 s, STFT 4096/1024, D=16 stacked frames "
                                "(Mbar=64, taps 22+21+21), K=30, 100 iterations, CTF-MNMF-ISS, bins split over "
                                "teams of workgroups",
                    "F": wl.F, "T": wl.T, "Mbar": wl.mbar, "K": wl.K, "iterations": wl.n_iter},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": None,
-                     "kernel": "k_iss_team (W update, each bin's frames split over a team of workgroups)",
+                     "kernel": "k_iss_team (mixed precision W update, each bin's frames split over a team of "
+                               "workgroups)",
                      "avg_launch_us": avg_iss_ms * 1e3, "flops_per_launch": flops_launch},
-        "kernel_avg_ms": kernel_ms, "status": st32, "side_by_side": side, "cpu_baseline": None,
+        "kernel_avg_ms": kernel_ms, "status": stm, "side_by_side": side, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -374,6 +386,12 @@ def main() -> int:
                             "status": st64}
         side["iss_fp32_images_rel_err_vs_fp64"] = rel
         log(f"FP64 ISS: {dt64 / args.side_steps * 1e3:.3f} ms/step; FP32 vs FP64 images rel {rel:.2e}")
+        log("timing mixed-precision ISS")
+        dtm, Cm, stm, _ = time_path(torch, Separator, wl, Xc, B0, V0, "mixed", "iss", args.side_steps, 1)
+        relm = float(torch.linalg.norm((Cm.to(torch.complex128) - C64).flatten()) / torch.linalg.norm(C64.flatten()))
+        side["iss_mixed"] = {"value": units * args.side_steps / dtm, "ms_per_step": dtm / args.side_steps * 1e3,
+                             "status": stm, "images_rel_err_vs_fp64": relm}
+        log(f"mixed ISS: {dtm / args.side_steps * 1e3:.3f} ms/step; images rel {relm:.2e} vs FP64")
         log("timing FP64 IP")
         dtip, Cip, stip, _ = time_path(torch, Separator, wl, Xc, B0, V0, "fp64", "ip", args.side_steps, 1)
         side["ip_fp64"] = {"value": units * args.side_steps / dtip, "ms_per_step": dtip / args.side_steps * 1e3,

@@ -16,7 +16,12 @@
  *   V  [N][K][T]       NMF activations v_{n,k,t} (real)
  *   C  [N][M][F][T]    source images (complex)
  * Scalar type: precision CTFISS_FP32 uses complex64 / float32 for every
- * buffer above, CTFISS_FP64 uses complex128 / float64.
+ * buffer above, CTFISS_FP64 uses complex128 / float64.  CTFISS_MIXED (ISS
+ * rule only, single contexts) takes the FP32 buffers and kernels, except that
+ * the ISS sweep updates the rows of W in FP64 registers (each row of W_f gets
+ * Mbar rank-one updates per iteration; holding them in FP64 leaves one FP32
+ * rounding of W per iteration instead of Mbar).  Same layout and workspace as
+ * CTFISS_FP32.
  *
  * Rows of W: r = L_0 + ... + L_{n-1} + l is tap l of source n (source-major,
  * tap-minor, the flattened index of Sec. III-A-1).  The observation may stack
@@ -65,7 +70,7 @@ extern "C" {
 #define CTFISS_MAX_SOURCES 8       /* N                                             */
 #define CTFISS_MAX_BASES 64        /* K                                             */
 
-typedef enum { CTFISS_FP32 = 0, CTFISS_FP64 = 1 } ctfiss_precision;
+typedef enum { CTFISS_FP32 = 0, CTFISS_FP64 = 1, CTFISS_MIXED = 2 } ctfiss_precision;
 
 /* Demixing-matrix update: ISS rank-1 steering, Eqs. (11) and (16), or the
  * iterative-projection baseline, Eqs. (9) and (10). */

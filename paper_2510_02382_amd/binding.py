@@ -23,7 +23,7 @@ CTFISS_E_ORDER = -5
 CTFISS_E_HIP = -6
 CTFISS_E_NUMERIC = -7
 
-CTFISS_FP32, CTFISS_FP64 = 0, 1
+CTFISS_FP32, CTFISS_FP64, CTFISS_MIXED = 0, 1, 2
 CTFISS_RULE_ISS, CTFISS_RULE_IP = 0, 1
 CTFISS_VRULE_ALL_TAPS, CTFISS_VRULE_PAPER_TAP0 = 0, 1
 

@@ -25,10 +25,22 @@ constexpr GR kIss64[] = {{32, 1}, {64, 1}, {16, 1}, {16, 2}, {32, 2}};
 constexpr GR kIp32[] = {{16, 1}, {32, 1}};
 constexpr GR kIp64[] = {{32, 1}, {64, 1}, {16, 1}};
 
+// Precision codes: CTFISS_FP32 (0), CTFISS_FP64 (1), CTFISS_MIXED (2: FP32 data and
+// kernels, FP64 W rows in the ISS sweep).
+bool have_w(int prec, int rule, int G, int cpl, int rpl) {
+  if (prec == CTFISS_MIXED) return have_wkernel<float, true>(rule, G, cpl, rpl);
+  return prec == CTFISS_FP32 ? have_wkernel<float>(rule, G, cpl, rpl) : have_wkernel<double>(rule, G, cpl, rpl);
+}
+bool have_t(int prec, int G, int cpl, int rpl) {
+  if (prec == CTFISS_MIXED) return have_tkernel<float, true>(G, cpl, rpl);
+  return prec == CTFISS_FP32 ? have_tkernel<float>(G, cpl, rpl) : have_tkernel<double>(G, cpl, rpl);
+}
+
 bool plan_for(int prec, int rule, const Dims& d, size_t max_lds, int G, int RPL, int cpl_req, Plan* out) {
-  const int* cpls = prec == 0 ? kCpl32 : kCpl64;
-  const int ncpl = prec == 0 ? (int)(sizeof(kCpl32) / sizeof(int)) : (int)(sizeof(kCpl64) / sizeof(int));
-  const int rs = prec == 0 ? 4 : 8;
+  const bool f32 = prec != CTFISS_FP64;
+  const int* cpls = f32 ? kCpl32 : kCpl64;
+  const int ncpl = f32 ? (int)(sizeof(kCpl32) / sizeof(int)) : (int)(sizeof(kCpl64) / sizeof(int));
+  const int rs = f32 ? 4 : 8;
   const int need = (d.T + G - 1) / G;
   for (int ci = 0; ci < ncpl; ++ci) {
     const int cpl = cpls[ci];
@@ -36,7 +48,7 @@ bool plan_for(int prec, int rule, const Dims& d, size_t max_lds, int G, int RPL,
     const int groups = (d.Mb + RPL - 1) / RPL;
     const int threads = (groups * G + 63) / 64 * 64;
     if (threads > iter_max_threads(rs, cpl, RPL)) return false;
-    const bool ok = prec == 0 ? have_wkernel<float>(rule, G, cpl, RPL) : have_wkernel<double>(rule, G, cpl, RPL);
+    const bool ok = have_w(prec, rule, G, cpl, RPL);
     if (!ok) return false;
     const size_t lds = iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, G, cpl, rs, rule != 0).total;
     if (lds > max_lds) return false;
@@ -55,14 +67,15 @@ bool plan_for_team(int prec, const Dims& d, size_t max_lds, int G, int RPL, int 
   const int S = (d.T + P - 1) / P;
   const int Pe = (d.T + S - 1) / S;
   if (Pe < 2 || S < d.lmax - 1) return false;
-  const int* cpls = prec == 0 ? kCpl32 : kCpl64;
-  const int ncpl = prec == 0 ? (int)(sizeof(kCpl32) / sizeof(int)) : (int)(sizeof(kCpl64) / sizeof(int));
-  const int rs = prec == 0 ? 4 : 8;
+  const bool f32 = prec != CTFISS_FP64;
+  const int* cpls = f32 ? kCpl32 : kCpl64;
+  const int ncpl = f32 ? (int)(sizeof(kCpl32) / sizeof(int)) : (int)(sizeof(kCpl64) / sizeof(int));
+  const int rs = f32 ? 4 : 8;
   const int need = (S + G - 1) / G;
   for (int ci = 0; ci < ncpl; ++ci) {
     const int cpl = cpls[ci];
     if (cpl < need || (cpl_req > 0 && cpl != cpl_req)) continue;
-    const bool ok = prec == 0 ? have_tkernel<float>(G, cpl, RPL) : have_tkernel<double>(G, cpl, RPL);
+    const bool ok = have_t(prec, G, cpl, RPL);
     if (!ok) continue;
     const int groups = (d.Mb + RPL - 1) / RPL;
     const int threads = (groups * G + 63) / 64 * 64;
@@ -83,12 +96,14 @@ constexpr GR kTeam64[] = {{16, 1}, {16, 2}};
 bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
   const GR* list;
   int n;
+  const bool f32 = prec != CTFISS_FP64;
   if (rule == 0) {
-    list = prec == 0 ? kIss32 : kIss64;
-    n = prec == 0 ? (int)(sizeof(kIss32) / sizeof(GR)) : (int)(sizeof(kIss64) / sizeof(GR));
+    list = f32 ? kIss32 : kIss64;
+    n = f32 ? (int)(sizeof(kIss32) / sizeof(GR)) : (int)(sizeof(kIss64) / sizeof(GR));
   } else {
-    list = prec == 0 ? kIp32 : kIp64;
-    n = prec == 0 ? (int)(sizeof(kIp32) / sizeof(GR)) : (int)(sizeof(kIp64) / sizeof(GR));
+    if (prec == CTFISS_MIXED) return false;  // the mixed path is an ISS path
+    list = f32 ? kIp32 : kIp64;
+    n = f32 ? (int)(sizeof(kIp32) / sizeof(GR)) : (int)(sizeof(kIp64) / sizeof(GR));
   }
   // FP32 ISS: 32-lane groups whenever the workgroup fits (Mbar <= 32) and
   // needs at most 20 frames per lane (no spills); past that, 64-lane groups if
@@ -96,7 +111,7 @@ bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
   // Against a 16-lane group: half the frames per lane (fewer registers), and
   // for Mbar = 24 three waves per SIMD (a 16-lane group has 2 on two SIMDs and
   // 1 on the others); at <= 10 frames per lane two such workgroups share a CU.
-  if (rule == 0 && prec == 0) {
+  if (rule == 0 && f32) {
     Plan p;
     if (plan_for(prec, rule, d, max_lds, 32, 1, 0, &p) && p.CPL <= 20) {
       *out = p;
@@ -111,8 +126,8 @@ bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
     if (plan_for(prec, rule, d, max_lds, list[i].G, list[i].RPL, 0, out)) return true;
   // ISS bins too long for one workgroup: teams of workgroups
   if (rule == 0) {
-    const GR* tl = prec == 0 ? kTeam32 : kTeam64;
-    const int tn = prec == 0 ? (int)(sizeof(kTeam32) / sizeof(GR)) : (int)(sizeof(kTeam64) / sizeof(GR));
+    const GR* tl = f32 ? kTeam32 : kTeam64;
+    const int tn = f32 ? (int)(sizeof(kTeam32) / sizeof(GR)) : (int)(sizeof(kTeam64) / sizeof(GR));
     for (int P = 2; P <= kMaxTeam; ++P)
       for (int i = 0; i < tn; ++i)
         if (plan_for_team(prec, d, max_lds, tl[i].G, tl[i].RPL, P, 0, out)) return true;
@@ -176,7 +191,7 @@ struct TimedLaunch {
 
 int validate_shape(const ctfiss_shape* sh, int precision, Dims* d) {
   if (!sh || !d) return CTFISS_E_ARG;
-  if (precision != CTFISS_FP32 && precision != CTFISS_FP64) return CTFISS_E_ARG;
+  if (precision != CTFISS_FP32 && precision != CTFISS_FP64 && precision != CTFISS_MIXED) return CTFISS_E_ARG;
   if (sh->F < 1 || sh->T < 1 || sh->M < 1 || sh->D < 1 || sh->N < 1 || sh->K < 1) return CTFISS_E_SHAPE;
   if (!sh->taps) return CTFISS_E_ARG;
   if (sh->N > CTFISS_MAX_SOURCES || sh->K > CTFISS_MAX_BASES) return CTFISS_E_UNSUPPORTED;
@@ -214,7 +229,7 @@ int validate_shape(const ctfiss_shape* sh, int precision, Dims* d) {
 }
 
 Layout make_layout(const Dims& d, int precision) {
-  const size_t rs = precision == CTFISS_FP32 ? 4 : 8, cs = 2 * rs;
+  const size_t rs = precision != CTFISS_FP64 ? 4 : 8, cs = 2 * rs;
   const VSplit vs = choose_vsplit(d);
   Layout L{};
   size_t off = 0;
@@ -353,7 +368,9 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   // Persistent W-update workgroups: as many as fit on the device at once
   // (CTFISS_WBLOCKS in the environment overrides it, for tuning); any count
   // >= 1 gives the same result, since the workgroups share out the bins.
-  plan.blocks = precision == CTFISS_FP32 ? resident_wblocks<float>(rule, plan, d) : resident_wblocks<double>(rule, plan, d);
+  plan.blocks = precision == CTFISS_MIXED ? resident_wblocks<float, true>(rule, plan, d)
+                : precision == CTFISS_FP32 ? resident_wblocks<float>(rule, plan, d)
+                                           : resident_wblocks<double>(rule, plan, d);
   if (const char* wb = std::getenv("CTFISS_WBLOCKS")) {
     const int n = std::atoi(wb);
     if (n > 0) plan.blocks = n < d.F ? n : d.F;
@@ -396,7 +413,7 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   hipError_t ze = launch_zero_status(c->ptr.status, c->stream);
   // exchange words start untagged (every launch's tags are nonzero)
   if (ze == hipSuccess && c->ptr.xch)
-    ze = hipMemsetAsync(c->ptr.xch, 0, (size_t)d.F * team_words(d.Mb, d.lmax, plan.team, precision == CTFISS_FP32 ? 4 : 8) * 8,
+    ze = hipMemsetAsync(c->ptr.xch, 0, (size_t)d.F * team_words(d.Mb, d.lmax, plan.team, precision != CTFISS_FP64 ? 4 : 8) * 8,
                         c->stream);
   if (ze != hipSuccess) {
     delete c;
@@ -417,12 +434,12 @@ int ctfiss_set_input(ctfiss_ctx* c, const void* X) {
 int ctfiss_set_state(ctfiss_ctx* c, const void* W, const void* B, const void* V) {
   if (!c || !B || !V) return CTFISS_E_ARG;
   const Dims& d = c->d;
-  const size_t rs = c->prec == CTFISS_FP32 ? 4 : 8;
+  const size_t rs = c->prec != CTFISS_FP64 ? 4 : 8;
   hipError_t e;
   if (W)
     e = hipMemcpyAsync(c->ptr.W, W, (size_t)d.F * d.Mb * d.Mb * 2 * rs, hipMemcpyDeviceToDevice, c->stream);
   else
-    e = c->prec == CTFISS_FP32 ? identity_t<float>(d, c->ptr.W, c->stream) : identity_t<double>(d, c->ptr.W, c->stream);
+    e = c->prec != CTFISS_FP64 ? identity_t<float>(d, c->ptr.W, c->stream) : identity_t<double>(d, c->ptr.W, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->ptr.B, B, (size_t)d.N * d.F * d.K * rs, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess)
@@ -438,7 +455,7 @@ int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
   if (!c || n_iter < 0) return CTFISS_E_ARG;
   if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
   const bool tap0 = c->vrule == CTFISS_VRULE_PAPER_TAP0;
-  const bool f32 = c->prec == CTFISS_FP32;
+  const bool f32 = c->prec != CTFISS_FP64;
   const Dims& d = c->d;
   const Ptrs& p = c->ptr;
   hipStream_t s = c->stream;
@@ -448,6 +465,7 @@ int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
     c->epoch = c->epoch % 0x1FFFFFFu + 1u;  // tags epoch * 128 + step stay within 32 bits
     if (e == hipSuccess)
       e = timed(c, 0, [&] {
+        if (c->prec == CTFISS_MIXED) return wupdate_t<float, true>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, s);
         return f32 ? wupdate_t<float>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, s)
                    : wupdate_t<double>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, s);
       });
@@ -476,7 +494,7 @@ int ctfiss_get_state(ctfiss_ctx* c, void* W, void* B, void* V) {
   if (!c) return CTFISS_E_ARG;
   if (!c->have_state) return CTFISS_E_ORDER;
   const Dims& d = c->d;
-  const size_t rs = c->prec == CTFISS_FP32 ? 4 : 8;
+  const size_t rs = c->prec != CTFISS_FP64 ? 4 : 8;
   hipError_t e = hipSuccess;
   if (W) e = hipMemcpyAsync(W, c->ptr.W, (size_t)d.F * d.Mb * d.Mb * 2 * rs, hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess && B)
@@ -490,7 +508,7 @@ int ctfiss_source_images(ctfiss_ctx* c, void* C) {
   if (!c || !C) return CTFISS_E_ARG;
   if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
   hipError_t e = timed(c, 4, [&] {
-    return c->prec == CTFISS_FP32 ? images_t<float>(c->d, c->ptr, C, c->stream) : images_t<double>(c->d, c->ptr, C, c->stream);
+    return c->prec != CTFISS_FP64 ? images_t<float>(c->d, c->ptr, C, c->stream) : images_t<double>(c->d, c->ptr, C, c->stream);
   });
   return e == hipSuccess ? CTFISS_OK : CTFISS_E_HIP;
 }
@@ -499,7 +517,7 @@ int ctfiss_nll(ctfiss_ctx* c, double* out) {
   if (!c || !out) return CTFISS_E_ARG;
   if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
   std::vector<double> part((size_t)c->d.F);
-  hipError_t e = c->prec == CTFISS_FP32 ? nll_t<float>(c->d, c->ptr, c->stream) : nll_t<double>(c->d, c->ptr, c->stream);
+  hipError_t e = c->prec != CTFISS_FP64 ? nll_t<float>(c->d, c->ptr, c->stream) : nll_t<double>(c->d, c->ptr, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(part.data(), c->ptr.nllpart, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -604,8 +622,8 @@ size_t batch_tables_bytes(int n, size_t wsz, size_t nsz) {
   return b;
 }
 
-size_t desc_w_bytes(int prec) { return prec == CTFISS_FP32 ? wdesc_bytes<float>() : wdesc_bytes<double>(); }
-size_t desc_n_bytes(int prec) { return prec == CTFISS_FP32 ? ndesc_bytes<float>() : ndesc_bytes<double>(); }
+size_t desc_w_bytes(int prec) { return prec != CTFISS_FP64 ? wdesc_bytes<float>() : wdesc_bytes<double>(); }
+size_t desc_n_bytes(int prec) { return prec != CTFISS_FP64 ? ndesc_bytes<float>() : ndesc_bytes<double>(); }
 
 }  // namespace
 
@@ -639,6 +657,7 @@ int ctfiss_batch_create(const ctfiss_shape* shapes, int32_t n, int precision, in
   int st = ctfiss_batch_workspace_size(shapes, n, precision, &need);
   if (st != CTFISS_OK) return st;
   if (workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return CTFISS_E_WORKSPACE;
+  if (precision == CTFISS_MIXED) return CTFISS_E_UNSUPPORTED;  // batched W updates run FP32 or FP64 rows
   ctfiss_batch* b = new (std::nothrow) ctfiss_batch();
   if (!b) return CTFISS_E_ARG;
   b->n = n;
@@ -686,7 +705,7 @@ int ctfiss_batch_create(const ctfiss_shape* shapes, int32_t n, int precision, in
     bk->mix.push_back(i);
     const size_t lds = iter_lds_layout(b->ctx[i]->d.M, b->ctx[i]->d.T, b->ctx[i]->d.D, b->ctx[i]->d.Mb,
                                        b->ctx[i]->d.N, b->ctx[i]->d.lmax, p.G, p.CPL,
-                                       precision == CTFISS_FP32 ? 4 : 8, rule != 0)
+                                       precision != CTFISS_FP64 ? 4 : 8, rule != 0)
                            .total;
     if (lds > bk->lds) bk->lds = lds;
   }
@@ -701,7 +720,7 @@ int ctfiss_batch_create(const ctfiss_shape* shapes, int32_t n, int precision, in
     sbase += (int)bk.mix.size() + 1;
     int bins = 0;
     for (int i : bk.mix) bins += b->ctx[i]->d.F;
-    const int res = rule == CTFISS_RULE_ISS ? (precision == CTFISS_FP32 ? resident_wblocks_batch<float>(bk.plan, bk.lds)
+    const int res = rule == CTFISS_RULE_ISS ? (precision != CTFISS_FP64 ? resident_wblocks_batch<float>(bk.plan, bk.lds)
                                                                         : resident_wblocks_batch<double>(bk.plan, bk.lds))
                                             : 1;
     if (res < 1) {
@@ -721,7 +740,7 @@ int ctfiss_batch_set_input(ctfiss_batch* b, const void* const* X) {
     const int st = ctfiss_set_input(b->ctx[i], X[i]);
     if (st != CTFISS_OK) return st;
   }
-  const bool f32 = b->prec == CTFISS_FP32;
+  const bool f32 = b->prec != CTFISS_FP64;
   unsigned char* h = b->host.data();
   auto at = [&](size_t off) { return h + (off - b->off_w); };
   // W-update tables: per bucket, variants (no pending scale, demix), (pending scale, carried Y),
@@ -794,7 +813,7 @@ int ctfiss_batch_iterate(ctfiss_batch* b, int32_t n_iter) {
     }
     return CTFISS_OK;
   }
-  const bool f32 = b->prec == CTFISS_FP32;
+  const bool f32 = b->prec != CTFISS_FP64;
   char* w = b->ws;
   const int* nst = reinterpret_cast<const int*>(w + b->off_ns);
   int* cnt = reinterpret_cast<int*>(w + b->off_cnt);

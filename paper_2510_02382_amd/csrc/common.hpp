@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ctfiss {
 
 constexpr int kMaxRows = 64;   // Mbar
@@ -198,9 +200,9 @@ __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, 
   L.x = off; off += align_up((size_t)M * L.lx * cs, 16);
   L.w = off; off += align_up((size_t)Mb * Mb * cs, 16);
   L.phi = off; off += align_up((size_t)N * L.lp * rsize, 16);
-  if (!ip) {  // the ISS broadcasts of y_r and w_r
+  if (!ip) {  // the ISS broadcasts of y_r and w_r (w_r held in FP64 by the mixed-precision sweep)
     L.yb = off; off += align_up((size_t)2 * L.tp * cs, 16);
-    L.wb = off; off += align_up((size_t)2 * Mb * cs, 16);
+    L.wb = off; off += align_up((size_t)2 * Mb * 16, 16);
   } else {
     L.yb = L.wb = 0;
   }

@@ -446,8 +446,12 @@ __device__ bool epilogue_team(const IterArgs<R>& a, const BinLds<R>& s, const It
 // ------------------------------------------------------------------ ISS
 // TEAM: the workgroup is member `mem` of the bin's team (frames
 // [t0, t0 + nloc)); otherwise it holds all T frames.
-template <typename R, int G, int CPL, int RPL, bool TEAM = false>
+// WX: the rows of W are updated in FP64 registers during the sweep (R =
+// float): its 64 rank-1 updates per iteration then add no FP32 rounding to W,
+// which is loaded from and stored to the FP32 state once per iteration.
+template <typename R, int G, int CPL, int RPL, bool TEAM = false, bool WX = false>
 __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int mem = 0) {
+  using WR = typename std::conditional<WX, double, R>::type;
   const int tid = lane_tid();
   const int g = tid / G, q = tid - g * G;
   const int T = a.T, Mb = a.rm.Mb, TP = L.tp, LP = L.lp, Lm1 = L.lmax - 1;
@@ -469,7 +473,7 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
   else
     demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y, nloc);
 
-  Cx<R> wreg[RPL][WPL];
+  Cx<WR> wreg[RPL][WPL];
   R ph[RPL][CPL];  // weights of the lane's rows and frames, phi[n][t - l]
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
@@ -481,7 +485,8 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
 #pragma unroll
     for (int k = 0; k < WPL; ++k) {
       const int c = q + G * k;
-      wreg[i][k] = (ok && c < Mb) ? s.w[p * Mb + c] : Cx<R>{R(0), R(0)};
+      const Cx<R> w0 = (ok && c < Mb) ? s.w[p * Mb + c] : Cx<R>{R(0), R(0)};
+      wreg[i][k] = Cx<WR>{WR(w0.x), WR(w0.y)};
     }
   }
 
@@ -492,7 +497,7 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
   bool bad = false;
   for (int r = 0; r < Mb; ++r) {
     Cx<R>* yb = s.yb + (r & 1) * TP;
-    Cx<R>* wb = s.wb + (r & 1) * Mb;
+    Cx<WR>* wb = reinterpret_cast<Cx<WR>*>(s.wb) + (r & 1) * Mb;
     if (g == r / RPL) {
       const int io = r - g * RPL;
 #pragma unroll
@@ -564,9 +569,9 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
     for (int k = 0; k < WPL; ++k) {
       const int c = q + G * k;
       if (c < Mb) {
-        const Cx<R> wr = wb[c];
+        const Cx<WR> wr = wb[c];
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) wreg[i][k] = cfms(z[i], wr, wreg[i][k]);
+        for (int i = 0; i < RPL; ++i) wreg[i][k] = cfms(Cx<WR>{WR(z[i].x), WR(z[i].y)}, wr, wreg[i][k]);
       }
     }
   }
@@ -578,7 +583,8 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
 #pragma unroll
     for (int k = 0; k < WPL; ++k) {
       const int c = q + G * k;
-      if (p < Mb && c < Mb && (!TEAM || mem == 0)) a.W[((size_t)f * Mb + p) * Mb + c] = wreg[i][k];
+      if (p < Mb && c < Mb && (!TEAM || mem == 0))
+        a.W[((size_t)f * Mb + p) * Mb + c] = Cx<R>{R(wreg[i][k].x), R(wreg[i][k].y)};
     }
     if (a.Y && p < Mb) {
       Cx<R>* yr = a.Y + ((size_t)f * Mb + p) * T + t0 + q;
@@ -606,24 +612,24 @@ __device__ __forceinline__ int next_bin(const IterArgs<R>& a, const BinLds<R>& s
   return __builtin_amdgcn_readfirstlane(s.misc[0]);  // uniform: bin addressing stays scalar
 }
 
-template <typename R, int G, int CPL, int RPL>
+template <typename R, int G, int CPL, int RPL, bool WX = false>
 __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_min_waves(sizeof(R), CPL, RPL))
     k_iss(IterArgs<R> a, IterLds L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
-  for (int f = next_bin(a, s); f < a.F; f = next_bin(a, s)) iss_bin<R, G, CPL, RPL>(a, s, L, f);
+  for (int f = next_bin(a, s); f < a.F; f = next_bin(a, s)) iss_bin<R, G, CPL, RPL, false, WX>(a, s, L, f);
 }
 
 // Team launch: the persistent workgroups take (bin, member) items in order,
 // item = bin * P + member.
-template <typename R, int G, int CPL, int RPL>
+template <typename R, int G, int CPL, int RPL, bool WX = false>
 __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL)) k_iss_team(IterArgs<R> a, IterLds L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
   const int P = L.team;
   for (int it = next_bin(a, s); it < a.F * P; it = next_bin(a, s)) {
     const int f = it / P;
-    iss_bin<R, G, CPL, RPL, true>(a, s, L, f, it - f * P);
+    iss_bin<R, G, CPL, RPL, true, WX>(a, s, L, f, it - f * P);
   }
 }
 

@@ -56,8 +56,9 @@ int plan_string_team(const char* spec);
 bool plan_from_string(const char* spec, int prec, int rule, const Dims& d, size_t max_lds, Plan* out);
 VSplit choose_vsplit(const Dims& d);
 
-// Typed launchers, defined once per precision.
-template <typename R>
+// Typed launchers, defined once per precision.  WX (R = float only): the
+// ISS sweep updates the rows of W in FP64 registers (mixed precision).
+template <typename R, bool WX = false>
 hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload,
                      unsigned epoch, hipStream_t s);
 template <typename R>
@@ -76,11 +77,11 @@ template <typename R>
 hipError_t nll_t(const Dims& d, const Ptrs& ptr, hipStream_t s);
 template <typename R>
 hipError_t identity_t(const Dims& d, void* W, hipStream_t s);
-template <typename R>
+template <typename R, bool WX = false>
 bool have_wkernel(int rule, int G, int cpl, int rpl);
-template <typename R>
+template <typename R, bool WX = false>
 bool have_tkernel(int G, int cpl, int rpl);
-template <typename R>
+template <typename R, bool WX = false>
 int resident_wblocks(int rule, const Plan& p, const Dims& d);
 
 // Batched launches (many problems of one launch shape per W-update launch).

@@ -13,76 +13,78 @@ namespace ctfiss {
 template <typename R>
 using WFn = void (*)(IterArgs<R>, IterLds);
 
-template <typename R, int G, int CPL, int RPL>
+// WX: ISS kernels with FP64 W rows (mixed precision, R = float; no IP kernels).
+template <typename R, bool WX, int G, int CPL, int RPL>
 WFn<R> wfn(int rule) {
-  if (rule == 0) return &k_iss<R, G, CPL, RPL>;
-  if constexpr (RPL == 1) return &k_ip<R, G, CPL, 1>;
+  if (rule == 0) return &k_iss<R, G, CPL, RPL, WX>;
+  if constexpr (RPL == 1 && !WX) return &k_ip<R, G, CPL, 1>;
   return nullptr;
 }
 
-template <typename R, int G, int RPL>
+template <typename R, bool WX, int G, int RPL>
 WFn<R> pick_cpl(int rule, int cpl) {
   if constexpr (sizeof(R) == 4) {
     switch (cpl) {
-      case 4: return wfn<R, G, 4, RPL>(rule);
-      case 8: return wfn<R, G, 8, RPL>(rule);
-      case 10: return wfn<R, G, 10, RPL>(rule);
-      case 12: return wfn<R, G, 12, RPL>(rule);
-      case 16: return wfn<R, G, 16, RPL>(rule);
-      case 20: return wfn<R, G, 20, RPL>(rule);
-      case 24: return wfn<R, G, 24, RPL>(rule);
-      case 28: return wfn<R, G, 28, RPL>(rule);
-      case 32: return wfn<R, G, 32, RPL>(rule);
+      case 4: return wfn<R, WX, G, 4, RPL>(rule);
+      case 8: return wfn<R, WX, G, 8, RPL>(rule);
+      case 10: return wfn<R, WX, G, 10, RPL>(rule);
+      case 12: return wfn<R, WX, G, 12, RPL>(rule);
+      case 16: return wfn<R, WX, G, 16, RPL>(rule);
+      case 20: return wfn<R, WX, G, 20, RPL>(rule);
+      case 24: return wfn<R, WX, G, 24, RPL>(rule);
+      case 28: return wfn<R, WX, G, 28, RPL>(rule);
+      case 32: return wfn<R, WX, G, 32, RPL>(rule);
       default: return nullptr;
     }
   } else {
     switch (cpl) {
-      case 4: return wfn<R, G, 4, RPL>(rule);
-      case 6: return wfn<R, G, 6, RPL>(rule);
-      case 8: return wfn<R, G, 8, RPL>(rule);
-      case 10: return wfn<R, G, 10, RPL>(rule);
-      case 12: return wfn<R, G, 12, RPL>(rule);
-      case 16: return wfn<R, G, 16, RPL>(rule);
+      case 4: return wfn<R, WX, G, 4, RPL>(rule);
+      case 6: return wfn<R, WX, G, 6, RPL>(rule);
+      case 8: return wfn<R, WX, G, 8, RPL>(rule);
+      case 10: return wfn<R, WX, G, 10, RPL>(rule);
+      case 12: return wfn<R, WX, G, 12, RPL>(rule);
+      case 16: return wfn<R, WX, G, 16, RPL>(rule);
       default: return nullptr;
     }
   }
 }
 
-template <typename R, int G>
+template <typename R, bool WX, int G>
 WFn<R> pick_rpl(int rule, int cpl, int rpl) {
-  if (rpl == 1) return pick_cpl<R, G, 1>(rule, cpl);
-  if (rpl == 2) return pick_cpl<R, G, 2>(rule, cpl);
+  if (rpl == 1) return pick_cpl<R, WX, G, 1>(rule, cpl);
+  if (rpl == 2) return pick_cpl<R, WX, G, 2>(rule, cpl);
   return nullptr;
 }
 
-template <typename R>
+template <typename R, bool WX>
 WFn<R> pick(int rule, int G, int cpl, int rpl) {
-  if (G == 16) return pick_rpl<R, 16>(rule, cpl, rpl);
-  if (G == 32) return pick_rpl<R, 32>(rule, cpl, rpl);
+  if constexpr (WX && sizeof(R) != 4) return nullptr;
+  if (G == 16) return pick_rpl<R, WX, 16>(rule, cpl, rpl);
+  if (G == 32) return pick_rpl<R, WX, 32>(rule, cpl, rpl);
   if constexpr (sizeof(R) == 4) {
-    if (G == 64 && rpl == 1) return pick_cpl<R, 64, 1>(rule, cpl);  // long frames, Mbar <= 16
+    if (G == 64 && rpl == 1) return pick_cpl<R, WX, 64, 1>(rule, cpl);  // long frames, Mbar <= 16
   }
   if constexpr (sizeof(R) == 8) {
-    if (G == 64) return pick_rpl<R, 64>(rule, cpl, rpl);
+    if (G == 64) return pick_rpl<R, WX, 64>(rule, cpl, rpl);
   }
   return nullptr;
 }
 
-template <typename R>
+template <typename R, bool WX>
 bool have_wkernel(int rule, int G, int cpl, int rpl) {
-  return pick<R>(rule, G, cpl, rpl) != nullptr;
+  return pick<R, WX>(rule, G, cpl, rpl) != nullptr;
 }
 
 // Team (frame-split) ISS kernels: Mbar up to 64 with long signals.
-template <typename R>
+template <typename R, bool WX>
 WFn<R> pickt(int G, int cpl, int rpl) {
   if constexpr (sizeof(R) == 4) {
-    if (G == 16 && rpl == 1 && cpl == 16) return &k_iss_team<R, 16, 16, 1>;
-    if (G == 16 && rpl == 1 && cpl == 8) return &k_iss_team<R, 16, 8, 1>;
-    if (G == 16 && rpl == 2 && cpl == 8) return &k_iss_team<R, 16, 8, 2>;
-    if (G == 32 && rpl == 2 && cpl == 8) return &k_iss_team<R, 32, 8, 2>;
-    if (G == 32 && rpl == 2 && cpl == 4) return &k_iss_team<R, 32, 4, 2>;
-  } else {
+    if (G == 16 && rpl == 1 && cpl == 16) return &k_iss_team<R, 16, 16, 1, WX>;
+    if (G == 16 && rpl == 1 && cpl == 8) return &k_iss_team<R, 16, 8, 1, WX>;
+    if (G == 16 && rpl == 2 && cpl == 8) return &k_iss_team<R, 16, 8, 2, WX>;
+    if (G == 32 && rpl == 2 && cpl == 8) return &k_iss_team<R, 32, 8, 2, WX>;
+    if (G == 32 && rpl == 2 && cpl == 4) return &k_iss_team<R, 32, 4, 2, WX>;
+  } else if constexpr (!WX) {
     if (G == 16 && rpl == 1 && cpl == 8) return &k_iss_team<R, 16, 8, 1>;
     if (G == 16 && rpl == 1 && cpl == 4) return &k_iss_team<R, 16, 4, 1>;
     if (G == 16 && rpl == 2 && cpl == 4) return &k_iss_team<R, 16, 4, 2>;
@@ -90,20 +92,20 @@ WFn<R> pickt(int G, int cpl, int rpl) {
   return nullptr;
 }
 
-template <typename R>
+template <typename R, bool WX>
 bool have_tkernel(int G, int cpl, int rpl) {
-  return pickt<R>(G, cpl, rpl) != nullptr;
+  return pickt<R, WX>(G, cpl, rpl) != nullptr;
 }
 
-template <typename R>
+template <typename R, bool WX>
 WFn<R> pick_plan(int rule, const Plan& p) {
-  return p.team > 1 ? (rule == 0 ? pickt<R>(p.G, p.CPL, p.RPL) : nullptr) : pick<R>(rule, p.G, p.CPL, p.RPL);
+  return p.team > 1 ? (rule == 0 ? pickt<R, WX>(p.G, p.CPL, p.RPL) : nullptr) : pick<R, WX>(rule, p.G, p.CPL, p.RPL);
 }
 
 // Workgroups of the W-update kernel that fit on the device at once.
-template <typename R>
+template <typename R, bool WX>
 int resident_wblocks(int rule, const Plan& p, const Dims& d) {
-  WFn<R> fn = pick_plan<R>(rule, p);
+  WFn<R> fn = pick_plan<R, WX>(rule, p);
   int dev = 0, cus = 0, per_cu = 0;
   if (!fn || hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
@@ -144,10 +146,10 @@ inline IterLds wlayout(int rule, const Plan& p, const Dims& d, int rsize) {
   return iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, rsize, rule != 0, p.team, p.slice);
 }
 
-template <typename R>
+template <typename R, bool WX>
 hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload,
                      unsigned epoch, hipStream_t s) {
-  WFn<R> fn = pick_plan<R>(rule, p);
+  WFn<R> fn = pick_plan<R, WX>(rule, p);
   if (!fn || (p.team > 1 && !ptr.xch)) return hipErrorInvalidValue;
   IterArgs<R> a = make_iargs<R>(rule, d, ptr, apply_mu, yload);
   a.epoch = epoch;
@@ -442,13 +444,18 @@ hipError_t identity_t(const Dims& d, void* W, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The launchers of the W update for one arithmetic of the W rows (WX).
+#define CTFISS_INSTANTIATE_W(R, WX)                                                                            \
+  template hipError_t wupdate_t<R, WX>(int, const Plan&, const Dims&, const Ptrs&, bool, bool, unsigned,       \
+                                       hipStream_t);                                                           \
+  template bool have_wkernel<R, WX>(int, int, int, int);                                                      \
+  template bool have_tkernel<R, WX>(int, int, int);                                                           \
+  template int resident_wblocks<R, WX>(int, const Plan&, const Dims&);
+
 #define CTFISS_INSTANTIATE(R)                                                                                  \
-  template hipError_t wupdate_t<R>(int, const Plan&, const Dims&, const Ptrs&, bool, bool, unsigned, hipStream_t); \
+  CTFISS_INSTANTIATE_W(R, false)                                                                              \
   template hipError_t lambda_t<R>(const Dims&, const Ptrs&, bool, hipStream_t);                               \
   template hipError_t nmfb_t<R>(const Dims&, const Ptrs&, double, bool, hipStream_t);                         \
-  template bool have_wkernel<R>(int, int, int, int);                                                          \
-  template bool have_tkernel<R>(int, int, int);                                                               \
-  template int resident_wblocks<R>(int, const Plan&, const Dims&);                                            \
   template hipError_t vpart_t<R>(const Dims&, const VSplit&, const Ptrs&, bool, hipStream_t);                 \
   template hipError_t vfinal_t<R>(const Dims&, const VSplit&, const Ptrs&, double, bool, hipStream_t);        \
   template hipError_t apply_mu_t<R>(const Dims&, const Ptrs&, bool, hipStream_t);                            \

@@ -5,7 +5,7 @@ import torch
 
 from . import binding as b
 
-_PREC = {"fp32": b.CTFISS_FP32, "fp64": b.CTFISS_FP64}
+_PREC = {"fp32": b.CTFISS_FP32, "fp64": b.CTFISS_FP64, "mixed": b.CTFISS_MIXED}
 _RULE = {"iss": b.CTFISS_RULE_ISS, "ip": b.CTFISS_RULE_IP}
 _VRULE = {"all_taps": b.CTFISS_VRULE_ALL_TAPS, "paper_tap0": b.CTFISS_VRULE_PAPER_TAP0}
 
@@ -13,7 +13,7 @@ _VRULE = {"all_taps": b.CTFISS_VRULE_ALL_TAPS, "paper_tap0": b.CTFISS_VRULE_PAPE
 class Separator:
     """CTF-MNMF separation of one mixture on one GPU.
 
-    X [M, F, T] complex (complex64 for fp32, complex128 for fp64) on the device;
+    X [M, F, T] complex (complex64 for fp32 and mixed, complex128 for fp64) on the device;
     W [F, Mbar, Mbar] complex, B [N, F, K] and V [N, K, T] real.  All work is
     enqueued on `stream` (default: torch's current stream when the object is made).
     """
@@ -24,8 +24,8 @@ class Separator:
         self.taps = tuple(int(x) for x in taps)
         self.Mbar = self.M * self.D
         self.precision = precision
-        self.rdtype = torch.float32 if precision == "fp32" else torch.float64
-        self.cdtype = torch.complex64 if precision == "fp32" else torch.complex128
+        self.rdtype = torch.float64 if precision == "fp64" else torch.float32
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device(self.device.type, torch.cuda.current_device())
@@ -115,8 +115,8 @@ class BatchSeparator:
         self.shapes = [(int(F), int(T), int(M), int(D), int(N), int(K), tuple(int(x) for x in taps))
                        for (F, T, M, D, N, K, taps) in shapes]
         self.precision = precision
-        self.rdtype = torch.float32 if precision == "fp32" else torch.float64
-        self.cdtype = torch.complex64 if precision == "fp32" else torch.complex128
+        self.rdtype = torch.float64 if precision == "fp64" else torch.float32
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device(self.device.type, torch.cuda.current_device())

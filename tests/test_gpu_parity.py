@@ -50,9 +50,9 @@ def rel(a, b):
 
 def as_device(x, precision):
     if np.iscomplexobj(x):
-        dt = torch.complex64 if precision == "fp32" else torch.complex128
+        dt = torch.complex128 if precision == "fp64" else torch.complex64
     else:
-        dt = torch.float32 if precision == "fp32" else torch.float64
+        dt = torch.float64 if precision == "fp64" else torch.float32
     return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dt).contiguous()
 
 
