@@ -143,6 +143,26 @@ int ctfiss_source_images(ctfiss_ctx* ctx, void* C);
  * written to *out.  Computed on the device in FP64; synchronises the stream. */
 int ctfiss_nll(ctfiss_ctx* ctx, double* out);
 
+/* Reverse mode (gradients) of the unrolled separation: the forward is W = I
+ * (Sec. V-A), B = B0, V = V0, n_iter iterations as in ctfiss_iterate, then
+ * the source images C = ctfiss_source_images (Eq. (24) by projection back).
+ * Given gC = dL/dC for a real loss L (complex [N][M][F][T], gradient
+ * convention dL/dRe + i dL/dIm), writes gX = dL/dX [M][F][T] (the bound
+ * input), gB0 = dL/dB0 [N][F][K] and gV0 = dL/dV0 [N][K][T] (either may be
+ * NULL).  The factor floor is treated as a clamp: where a factor is clamped,
+ * its update passes no gradient.  The forward is run again inside the call
+ * with the state saved before every iteration; each iteration is then
+ * reversed from its saved state (hand-written adjoint kernels of the rescale,
+ * activation and basis updates, the ISS sweep row by row and the demix).
+ * FP64 ISS contexts with the all-taps activation rule and Mbar <= 32 only
+ * (else CTFISS_E_UNSUPPORTED).  aws: device workspace of
+ * ctfiss_adjoint_workspace_size() bytes (256-byte aligned), scratch for the
+ * call.  The context ends in the forward's final state, as after
+ * ctfiss_iterate.  Enqueued on the context's stream. */
+int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int32_t n_iter, size_t* bytes);
+int ctfiss_backward(ctfiss_ctx* ctx, int32_t n_iter, const void* B0, const void* V0, const void* gC, void* gX,
+                    void* gB0, void* gV0, void* aws, size_t aws_bytes);
+
 /* Synchronise the stream and return CTFISS_E_NUMERIC if a device fault was
  * latched since the last set_state, CTFISS_E_HIP on a HIP error, else 0.
  * *fault_code (nullable) receives the raw device code (0 = none). */

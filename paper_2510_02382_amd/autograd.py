@@ -1,0 +1,46 @@
+"""torch.autograd.Function over the unrolled separation (forward and reverse on the GPU).
+
+    C = separate(X, B0, V0, D, taps, n_iter)
+
+runs W = I, (B0, V0), n_iter CTF-MNMF-ISS iterations and the source images
+through the C ABI (FP64 contexts), and its backward calls ctfiss_backward,
+whose hand-written adjoint kernels re-run the forward with the state saved per
+iteration and reverse it.  Gradients flow to X (complex [M, F, T]), B0 and V0.
+"""
+from __future__ import annotations
+
+import torch
+
+from .separator import Separator
+
+
+class _Separate(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, X, B0, V0, D, taps, n_iter, floor):
+        M, F, T = X.shape
+        N, _, K = B0.shape
+        sep = Separator(F, T, M, D, N, K, taps, precision="fp64", floor=floor, device=X.device)
+        Xc, Bc, Vc = X.detach().contiguous(), B0.detach().contiguous(), V0.detach().contiguous()
+        sep.set_input(Xc)
+        sep.set_state(B=Bc, V=Vc)
+        sep.iterate(n_iter)
+        C = sep.source_images()
+        ctx.sep = sep
+        ctx.n_iter = n_iter
+        ctx.save_for_backward(Xc, Bc, Vc)
+        return C
+
+    @staticmethod
+    def backward(ctx, gC):
+        Xc, Bc, Vc = ctx.saved_tensors
+        sep = ctx.sep
+        sep.set_input(Xc)
+        gX, gB0, gV0 = sep.backward(ctx.n_iter, Bc, Vc, gC.contiguous())
+        sep.close()
+        return gX, gB0, gV0, None, None, None, None
+
+
+def separate(X: torch.Tensor, B0: torch.Tensor, V0: torch.Tensor, D: int, taps, n_iter: int,
+             floor: float = 1e-8) -> torch.Tensor:
+    """Source images [N, M, F, T] (complex128) after n_iter iterations, differentiable in X, B0, V0."""
+    return _Separate.apply(X, B0, V0, int(D), tuple(int(t) for t in taps), int(n_iter), float(floor))

@@ -33,6 +33,7 @@ EXPORTS = (
     "ctfiss_status_string", "ctfiss_set_profiling", "ctfiss_kernel_stats",
     "ctfiss_batch_workspace_size", "ctfiss_batch_create", "ctfiss_batch_set_input", "ctfiss_batch_set_state",
     "ctfiss_batch_iterate", "ctfiss_batch_source_images", "ctfiss_batch_sync_status", "ctfiss_batch_destroy",
+    "ctfiss_adjoint_workspace_size", "ctfiss_backward",
 )
 
 
@@ -76,6 +77,8 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "ctfiss_batch_source_images": ([vp, ctypes.POINTER(vp)], i32),
         "ctfiss_batch_sync_status": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "ctfiss_batch_destroy": ([vp], i32),
+        "ctfiss_adjoint_workspace_size": ([ctypes.POINTER(Shape), i32, ctypes.POINTER(sz)], i32),
+        "ctfiss_backward": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, sz], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -176,6 +179,18 @@ def ctfiss_kernel_stats(ctx, which: int) -> tuple[int, float]:
     ms = ctypes.c_double(0.0)
     _check(_lib.ctfiss_kernel_stats(ctx, int(which), ctypes.byref(n), ctypes.byref(ms)), "ctfiss_kernel_stats")
     return int(n.value), float(ms.value)
+
+
+def ctfiss_adjoint_workspace_size(shape: Shape, n_iter: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.ctfiss_adjoint_workspace_size(ctypes.byref(shape), int(n_iter), ctypes.byref(out)),
+           "ctfiss_adjoint_workspace_size")
+    return int(out.value)
+
+
+def ctfiss_backward(ctx, n_iter: int, B0, V0, gC, gX, gB0, gV0, aws: torch.Tensor) -> None:
+    _check(_lib.ctfiss_backward(ctx, int(n_iter), _ptr(B0), _ptr(V0), _ptr(gC), _ptr(gX), _ptr(gB0), _ptr(gV0),
+                                _ptr(aws), aws.numel() * aws.element_size()), "ctfiss_backward")
 
 
 # ------------------------------------------------------------------ batches

@@ -1,0 +1,669 @@
+// Reverse mode (adjoint) of the unrolled CTF-MNMF-ISS iterations followed by
+// the source images, FP64.  Gradients follow the real-calculus convention
+// g = dL/dRe + i dL/dIm for complex variables (L real), so that for w = u v,
+// g_u += conj(v) g_w, and for s = |u|^2, g_u += 2 u g_s.
+//
+// Per iteration (state W, B, V -> W', B', V'), the forward is
+//   lambda = B V, phi_(n,l)[t] = 1 / lambda[n, t - l];  ISS sweep on W and
+//   Y = W xbar (Eqs. (11), (16));  P[n, s] = sum_l |y_(n,l)[s + l]|^2;
+//   B^ = max(B sqrt(sum_s P v / lambda^2 / sum_s c v / lambda), floor)  (Eq. (17));
+//   V^ = max(V sqrt(sum_f B^ P / lambda^2 / sum_f B^ c / lambda), floor) with
+//   lambda = B^ V (all taps of a source, c[n, s] = #{l : s + l < T});
+//   mu_r = sqrt(sum_{f,t} |y_r|^2 / (F T)), W' = W^s / mu, B' = B^ / mu_first^2,
+//   V' = V^  (Eqs. (19)-(21)),
+// and the images are c_n = H[:M, rows(n)] y_rows(n) with H = W^{-1} (Eq. (24)).
+// The kernels below take these steps backwards, one launch per step and
+// index space; the ISS sweep is reversed row by row, reconstructing the rows
+// before each rank-one step from the ones after it (the step is invertible:
+// 1 - z_r = d_r^{-1/2} > 0) with the coefficients recorded by a forward sweep
+// in the same kernel.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace ctfiss {
+namespace {
+
+using Cd = Cx<double>;
+
+__device__ __forceinline__ Cd cconj(Cd a) { return {a.x, -a.y}; }
+__device__ __forceinline__ Cd cscale(Cd a, double s) { return {a.x * s, a.y * s}; }
+
+struct AdjArgs {
+  // forward quantities of the iteration being reversed
+  const Cd* X;       // [M][F][T]
+  const Cd* Wk;      // [F][Mb][Mb] state at the start of the iteration
+  const double* Bk;  // [N][F][K]
+  const double* Vk;  // [N][K][T]
+  const Cd* Ws;      // [F][Mb][Mb] after the sweep, before the rescale
+  const double* Bh;  // [N][F][K] after the basis update, before the rescale
+  const double* Vh;  // [N][K][T] after the activation update
+  const double* ilam;  // [N][F][T] 1 / (Bk Vk)
+  const double* P;     // [N][F][T] tap-aligned powers of the swept rows
+  const double* mu;    // [Mb]
+  // adjoints
+  Cd* gW;       // [F][Mb][Mb] in: of W', out: of Wk
+  double* gB;   // [N][F][K]   in: of B', out: of Bk
+  double* gV;   // [N][K][T]   in: of V', out: of Vk
+  double* gBh;  // [N][F][K]
+  double* gVh;  // [N][K][T]
+  double* gP;   // [N][F][T]
+  double* glam;   // [N][F][T] of lambda = Bk Vk
+  double* glamh;  // [N][F][T] of lambda = B^ Vk
+  double* lamh;   // [N][F][T] B^ Vk
+  double* G1;     // [N][K][T] adjoint of the activation update's numerator sum
+  double* G2;     // [N][K][T] ... denominator sum
+  double* H1;     // [N][F][K] adjoint of the basis update's numerator sum
+  double* H2;     // [N][F][K] ... denominator sum
+  double* part;   // [F][Mb + N] rescale partial sums
+  double* gS;     // [Mb] adjoint of the row power sums
+  Cd* gX;         // [M][F][T] accumulated
+  int* status;
+  // per-bin scratch of the sweep
+  Cd* Y;        // [F][Mb][T]
+  Cd* gY;       // [F][Mb][T]
+  double* gphi; // [F][Mb][T]
+  Cd* ztape;    // [F][Mb][Mb] z of row r's step, [f][r][p]
+  double* dtape;  // [F][Mb][Mb] d_p of row r's step
+  double floor;
+  int F, T, M, D, N, K, Mb;
+  RowMap rm;
+};
+
+__device__ __forceinline__ double tapc(const RowMap& rm, int n, int s, int T) {
+  const int c = T - s;
+  return (double)(c < rm.L[n] ? c : rm.L[n]);
+}
+
+// xbar_c[t] = x[m][f][t - d] for c = d M + m (zero before frame 0)
+__device__ __forceinline__ Cd xbar(const AdjArgs& a, int f, int c, int t) {
+  const int d = c / a.M, m = c - d * a.M;
+  return t - d >= 0 ? a.X[((size_t)m * a.F + f) * a.T + t - d] : Cd{0.0, 0.0};
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ images
+// gC [N][M][F][T]: H = W^{-1} (Gauss-Jordan, partial pivoting), then
+// g_H = g_C Y^H, g_Y = H^H g_C (rows of each source), g_W = -H^H g_H H^H + g_Y xbar^H,
+// g_xbar = W^H g_Y.  Writes gW and gX (the first contributions).
+__global__ void __launch_bounds__(256) k_adj_images(AdjArgs a, const Cd* __restrict__ W, const Cd* __restrict__ gC) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int f = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int Mb = a.Mb, M = a.M, T = a.T, F = a.F;
+  Cd* Wl = reinterpret_cast<Cd*>(smem);     // [Mb][Mb]
+  Cd* aug = Wl + Mb * Mb;                   // [Mb][2 Mb]
+  Cd* gH = aug + 2 * Mb * Mb;               // [M][Mb]
+  Cd* A = gH + M * Mb;                      // [M][Mb]  gH H^H
+  Cd* colk = A + M * Mb;                    // [Mb] pivot column
+  int* piv = reinterpret_cast<int*>(colk + Mb);
+  const Cd* Wf = W + (size_t)f * Mb * Mb;
+  for (int i = tid; i < Mb * Mb; i += nt) {
+    Wl[i] = Wf[i];
+    const int r = i / Mb, c = i - r * Mb;
+    aug[r * 2 * Mb + c] = Wf[i];
+    aug[r * 2 * Mb + Mb + c] = Cd{r == c ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  for (int k = 0; k < Mb; ++k) {
+    if (tid == 0) {
+      int best = k;
+      double bv = cabs2(aug[k * 2 * Mb + k]);
+      for (int i = k + 1; i < Mb; ++i) {
+        const double v = cabs2(aug[i * 2 * Mb + k]);
+        if (v > bv) { bv = v; best = i; }
+      }
+      piv[0] = best;
+      if (!(bv > 0.0)) latch(a.status, kFaultOutSingular);
+    }
+    __syncthreads();
+    const int pr = piv[0];
+    if (pr != k)
+      for (int j = tid; j < 2 * Mb; j += nt) {
+        const Cd t0 = aug[k * 2 * Mb + j];
+        aug[k * 2 * Mb + j] = aug[pr * 2 * Mb + j];
+        aug[pr * 2 * Mb + j] = t0;
+      }
+    __syncthreads();
+    const Cd p = aug[k * 2 * Mb + k];
+    const double den = cabs2(p);
+    const Cd pinv{p.x / den, -p.y / den};
+    __syncthreads();
+    for (int j = tid; j < 2 * Mb; j += nt) aug[k * 2 * Mb + j] = cmul(aug[k * 2 * Mb + j], pinv);
+    for (int i = tid; i < Mb; i += nt) colk[i] = aug[i * 2 * Mb + k];
+    __syncthreads();
+    for (int e = tid; e < Mb * 2 * Mb; e += nt) {
+      const int i = e / (2 * Mb), j = e - i * 2 * Mb;
+      if (i != k) aug[e] = cfms(colk[i], aug[k * 2 * Mb + j], aug[e]);
+    }
+    __syncthreads();
+  }
+  // H[i][j] = aug[i][Mb + j]
+  auto H = [&](int i, int j) { return aug[i * 2 * Mb + Mb + j]; };
+  auto yv = [&](int r, int t) {
+    Cd s{0.0, 0.0};
+    for (int c = 0; c < Mb; ++c) s = cfma(Wl[r * Mb + c], xbar(a, f, c, t), s);
+    return s;
+  };
+  auto gc = [&](int r, int m, int t) { return gC[(((size_t)a.rm.src[r] * M + m) * F + f) * T + t]; };
+  // gH[m][r] = sum_t gC[n(r)][m][t] conj(y_r[t])
+  for (int e = tid; e < M * Mb; e += nt) {
+    const int m = e / Mb, r = e - m * Mb;
+    Cd s{0.0, 0.0};
+    for (int t = 0; t < T; ++t) s = cfma(gc(r, m, t), cconj(yv(r, t)), s);
+    gH[e] = s;
+  }
+  // gY[r][t] = sum_m conj(H[m][r]) gC[n(r)][m][t]  (into the sweep scratch)
+  Cd* gY = a.gY + (size_t)f * Mb * T;
+  for (int e = tid; e < Mb * T; e += nt) {
+    const int r = e / T, t = e - r * T;
+    Cd s{0.0, 0.0};
+    for (int m = 0; m < M; ++m) s = cfma(cconj(H(m, r)), gc(r, m, t), s);
+    gY[e] = s;
+  }
+  __syncthreads();
+  // A = gH H^H: A[m][c] = sum_r gH[m][r] conj(H[c][r])
+  for (int e = tid; e < M * Mb; e += nt) {
+    const int m = e / Mb, c = e - m * Mb;
+    Cd s{0.0, 0.0};
+    for (int r = 0; r < Mb; ++r) s = cfma(gH[m * Mb + r], cconj(H(c, r)), s);
+    A[e] = s;
+  }
+  __syncthreads();
+  // gW[r][c] = -sum_m conj(H[m][r]) A[m][c] + sum_t gY[r][t] conj(xbar_c[t])
+  for (int e = tid; e < Mb * Mb; e += nt) {
+    const int r = e / Mb, c = e - r * Mb;
+    Cd s{0.0, 0.0};
+    for (int m = 0; m < M; ++m) s = cfms(cconj(H(m, r)), A[m * Mb + c], s);
+    for (int t = 0; t < T; ++t) s = cfma(gY[r * T + t], cconj(xbar(a, f, c, t)), s);
+    a.gW[(size_t)f * Mb * Mb + e] = s;
+  }
+  // gX[m][f][t] = sum_d sum_r conj(W[r][d M + m]) gY[r][t + d]
+  for (int e = tid; e < M * T; e += nt) {
+    const int m = e / T, t = e - m * T;
+    Cd s{0.0, 0.0};
+    for (int d = 0; d < a.D && t + d < T; ++d)
+      for (int r = 0; r < Mb; ++r) s = cfma(cconj(Wl[r * Mb + d * M + m]), gY[r * T + t + d], s);
+    a.gX[((size_t)m * F + f) * T + t] = s;
+  }
+}
+
+// ------------------------------------------------------------------ rescale
+// part[f][r] = sum_c Re(conj(W'[r][c]) gW'[r][c]) with W' = W^s / mu_r;
+// part[f][Mb + n] = sum_k gB'[n][f][k] B'[n][f][k] with B' = B^ / mu_first(n)^2.
+__global__ void __launch_bounds__(256) k_adj_rescale_part(AdjArgs a) {
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const int Mb = a.Mb;
+  if (tid < Mb) {
+    const int r = tid;
+    double s = 0.0;
+    for (int c = 0; c < Mb; ++c) {
+      const size_t o = ((size_t)f * Mb + r) * Mb + c;
+      const Cd w = a.Ws[o], g = a.gW[o];
+      s += (w.x * g.x + w.y * g.y) / a.mu[r];
+    }
+    a.part[(size_t)f * (Mb + a.N) + r] = s;
+  } else if (tid < Mb + a.N) {
+    const int n = tid - Mb;
+    const double m0 = a.mu[a.rm.r0[n]];
+    double s = 0.0;
+    for (int k = 0; k < a.K; ++k) {
+      const size_t o = ((size_t)n * a.F + f) * a.K + k;
+      s += a.gB[o] * a.Bh[o] / (m0 * m0);
+    }
+    a.part[(size_t)f * (Mb + a.N) + tid] = s;
+  }
+}
+
+// g_mu_r = -sum_f part[f][r] / mu_r - [r first row of n] 2 sum_f part[f][Mb + n] / mu_r;
+// gS_r = g_mu_r / (2 mu_r F T).
+__global__ void __launch_bounds__(64) k_adj_rescale_final(AdjArgs a) {
+  const int r = threadIdx.x;
+  if (r >= a.Mb) return;
+  const int W = a.Mb + a.N;
+  double s = 0.0;
+  for (int f = 0; f < a.F; ++f) s += a.part[(size_t)f * W + r];
+  double g = -s / a.mu[r];
+  const int n = a.rm.src[r];
+  if (a.rm.r0[n] == r) {
+    double sb = 0.0;
+    for (int f = 0; f < a.F; ++f) sb += a.part[(size_t)f * W + a.Mb + n];
+    g -= 2.0 * sb / a.mu[r];
+  }
+  a.gS[r] = g / (2.0 * a.mu[r] * (double)a.F * (double)a.T);
+}
+
+// gW^s = gW' / mu_r (in place), gB^ = gB' / mu_first^2, gV^ = gV'.
+__global__ void __launch_bounds__(256) k_adj_rescale_apply(AdjArgs a) {
+  const size_t nW = (size_t)a.F * a.Mb * a.Mb, nB = (size_t)a.N * a.F * a.K, nV = (size_t)a.N * a.K * a.T;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nW) {
+    const int r = (int)((i / a.Mb) % a.Mb);
+    a.gW[i] = cscale(a.gW[i], 1.0 / a.mu[r]);
+  } else if (i < nW + nB) {
+    const size_t j = i - nW;
+    const int n = (int)(j / ((size_t)a.F * a.K));
+    const double m0 = a.mu[a.rm.r0[n]];
+    a.gBh[j] = a.gB[j] / (m0 * m0);
+  } else if (i < nW + nB + nV) {
+    const size_t j = i - nW - nB;
+    a.gVh[j] = a.gV[j];
+  }
+}
+
+// ------------------------------------------------------------------ activation update
+// Per (n, k, s): num = sum_f B^ P / lamh^2, den = sum_f B^ c / lamh (lamh = B^ Vk);
+// where V^ was not clamped: gV[n][k][s] = gV^ sqrt(num / den), G1 = gV^ V^ / (2 num),
+// G2 = -gV^ V^ / (2 den); else all zero.
+__global__ void __launch_bounds__(256) k_adj_v1(AdjArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)a.N * a.K * a.T) return;
+  const int s = (int)(i % a.T), k = (int)((i / a.T) % a.K), n = (int)(i / ((size_t)a.K * a.T));
+  const double c = tapc(a.rm, n, s, a.T);
+  double num = 0.0, den = 0.0;
+  for (int f = 0; f < a.F; ++f) {
+    const double* b = a.Bh + ((size_t)n * a.F + f) * a.K;
+    double lam = 0.0;
+    for (int j = 0; j < a.K; ++j) lam += b[j] * a.Vk[((size_t)n * a.K + j) * a.T + s];
+    const double p = a.P[((size_t)n * a.F + f) * a.T + s];
+    num += b[k] * p / (lam * lam);
+    den += b[k] * c / lam;
+  }
+  const double ratio = sqrt(num / den);
+  const double val = a.Vk[i] * ratio;
+  const double g = a.gVh[i];
+  if (val >= a.floor) {
+    a.gV[i] = g * ratio;
+    a.G1[i] = g * val / (2.0 * num);
+    a.G2[i] = -g * val / (2.0 * den);
+  } else {
+    a.gV[i] = 0.0;
+    a.G1[i] = 0.0;
+    a.G2[i] = 0.0;
+  }
+}
+
+// Per (n, f, s): lamh = B^ Vk; gP = sum_k G1 B^ / lamh^2 (first contribution);
+// glamh = sum_k (-2 G1 B^ P / lamh^3 - G2 B^ c / lamh^2).
+__global__ void __launch_bounds__(256) k_adj_v2(AdjArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)a.N * a.F * a.T) return;
+  const int s = (int)(i % a.T), f = (int)((i / a.T) % a.F), n = (int)(i / ((size_t)a.F * a.T));
+  const double* b = a.Bh + ((size_t)n * a.F + f) * a.K;
+  double lam = 0.0;
+  for (int k = 0; k < a.K; ++k) lam += b[k] * a.Vk[((size_t)n * a.K + k) * a.T + s];
+  const double p = a.P[i], c = tapc(a.rm, n, s, a.T);
+  double gp = 0.0, gl = 0.0;
+  for (int k = 0; k < a.K; ++k) {
+    const size_t o = ((size_t)n * a.K + k) * a.T + s;
+    gp += a.G1[o] * b[k] / (lam * lam);
+    gl += -2.0 * a.G1[o] * b[k] * p / (lam * lam * lam) - a.G2[o] * b[k] * c / (lam * lam);
+  }
+  a.lamh[i] = lam;
+  a.gP[i] = gp;
+  a.glamh[i] = gl;
+}
+
+// ------------------------------------------------------------------ basis update
+// Per (n, f, k): first the rest of gB^ from the activation update,
+//   gB^ += sum_s (G1 P / lamh^2 + G2 c / lamh + glamh Vk);
+// then the basis update with lam = 1 / ilam: num = sum_s P Vk / lam^2,
+// den = sum_s c Vk / lam; where B^ was not clamped: gB = gB^ sqrt(num / den),
+// H1 = gB^ B^ / (2 num), H2 = -gB^ B^ / (2 den); else zero.
+__global__ void __launch_bounds__(256) k_adj_b1(AdjArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)a.N * a.F * a.K) return;
+  const int k = (int)(i % a.K), f = (int)((i / a.K) % a.F), n = (int)(i / ((size_t)a.F * a.K));
+  const size_t fo = ((size_t)n * a.F + f) * a.T;
+  const double* v = a.Vk + ((size_t)n * a.K + k) * a.T;
+  double gbh = a.gBh[i];
+  double num = 0.0, den = 0.0;
+  for (int s = 0; s < a.T; ++s) {
+    const double c = tapc(a.rm, n, s, a.T), p = a.P[fo + s];
+    const double lh = a.lamh[fo + s];
+    const size_t o = ((size_t)n * a.K + k) * a.T + s;
+    gbh += a.G1[o] * p / (lh * lh) + a.G2[o] * c / lh + a.glamh[fo + s] * v[s];
+    const double il = a.ilam[fo + s];
+    num += p * v[s] * il * il;
+    den += c * v[s] * il;
+  }
+  const double ratio = sqrt(num / den);
+  const double val = a.Bk[i] * ratio;
+  if (val >= a.floor) {
+    a.gB[i] = gbh * ratio;
+    a.H1[i] = gbh * val / (2.0 * num);
+    a.H2[i] = -gbh * val / (2.0 * den);
+  } else {
+    a.gB[i] = 0.0;
+    a.H1[i] = 0.0;
+    a.H2[i] = 0.0;
+  }
+}
+
+// Per (n, f, s): gP += sum_k H1 Vk / lam^2;  glam = sum_k (-2 H1 Vk P / lam^3 - H2 c Vk / lam^2).
+__global__ void __launch_bounds__(256) k_adj_b2(AdjArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)a.N * a.F * a.T) return;
+  const int s = (int)(i % a.T), f = (int)((i / a.T) % a.F), n = (int)(i / ((size_t)a.F * a.T));
+  const double il = a.ilam[i], p = a.P[i], c = tapc(a.rm, n, s, a.T);
+  double gp = 0.0, gl = 0.0;
+  for (int k = 0; k < a.K; ++k) {
+    const double v = a.Vk[((size_t)n * a.K + k) * a.T + s];
+    const size_t o = ((size_t)n * a.F + f) * a.K + k;
+    gp += a.H1[o] * v * il * il;
+    gl += -2.0 * a.H1[o] * v * p * il * il * il - a.H2[o] * c * v * il * il;
+  }
+  a.gP[i] += gp;
+  a.glam[i] = gl;
+}
+
+// ------------------------------------------------------------------ ISS sweep
+// One workgroup per bin.  Forward: Y = Wk xbar, the sweep with z and d_p
+// recorded.  Backward from gW^s and gY^s = 2 y (tap-aligned gP) + 2 gS_r y_r,
+// rows r = Mb-1 .. 0.  Then the demix (gW += gY xbar^H, gxbar = Wk^H gY) and
+// glam += -sum_l gphi_(n,l)[s + l] / lam^2.
+__global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int f = blockIdx.x, tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  const int Mb = a.Mb, T = a.T, F = a.F;
+  const double invT = 1.0 / T;
+  Cd* W = reinterpret_cast<Cd*>(smem);   // [Mb][Mb]
+  Cd* gWl = W + Mb * Mb;                 // [Mb][Mb]
+  Cd* zl = gWl + Mb * Mb;                // [Mb]
+  Cd* ga = zl + Mb;                      // [Mb] adjoint of a_p
+  Cd* wr = ga + Mb;                      // [Mb] row r of W
+  double* dl = reinterpret_cast<double*>(wr + Mb);  // [Mb]
+  double* gd = dl + Mb;                  // [Mb] adjoint of d_p
+  Cd* yr = reinterpret_cast<Cd*>(gd + Mb);  // [T]
+  Cd* Y = a.Y + (size_t)f * Mb * T;
+  Cd* gY = a.gY + (size_t)f * Mb * T;
+  double* gphi = a.gphi + (size_t)f * Mb * T;
+  Cd* zt = a.ztape + (size_t)f * Mb * Mb;
+  double* dt = a.dtape + (size_t)f * Mb * Mb;
+  auto phi = [&](int p, int t) {
+    const int l = a.rm.tap[p];
+    return t >= l ? a.ilam[((size_t)a.rm.src[p] * F + f) * T + t - l] : 0.0;
+  };
+  for (int i = tid; i < Mb * Mb; i += nt) W[i] = a.Wk[(size_t)f * Mb * Mb + i];
+  __syncthreads();
+  for (int e = tid; e < Mb * T; e += nt) {
+    const int r = e / T, t = e - r * T;
+    Cd s{0.0, 0.0};
+    for (int c = 0; c < Mb; ++c) s = cfma(W[r * Mb + c], xbar(a, f, c, t), s);
+    Y[e] = s;
+  }
+  __syncthreads();
+  // forward sweep, recording z and d
+  for (int r = 0; r < Mb; ++r) {
+    for (int t = tid; t < T; t += nt) yr[t] = Y[r * T + t];
+    if (tid < Mb) wr[tid] = W[r * Mb + tid];
+    __syncthreads();
+    for (int p = wave; p < Mb; p += nw) {
+      double d = 0.0, ax = 0.0, ay = 0.0;
+      for (int t = lane; t < T; t += 64) {
+        const double ph = phi(p, t);
+        const Cd y = yr[t], yp = Y[p * T + t];
+        d += ph * cabs2(y);
+        const Cd q = cmulc(yp, y);
+        ax += ph * q.x;
+        ay += ph * q.y;
+      }
+      d = wave_sum(d) * invT;
+      ax = wave_sum(ax) * invT;
+      ay = wave_sum(ay) * invT;
+      if (lane == 0) {
+        Cd z{ax / d, ay / d};
+        if (p == r) z = Cd{1.0 - 1.0 / sqrt(d), 0.0};
+        zl[p] = z;
+        dl[p] = d;
+        zt[r * Mb + p] = z;
+        dt[r * Mb + p] = d;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < Mb * T; e += nt) {
+      const int p = e / T, t = e - p * T;
+      Y[e] = cfms(zl[p], yr[t], Y[e]);
+    }
+    for (int e = tid; e < Mb * Mb; e += nt) {
+      const int p = e / Mb, c = e - p * Mb;
+      W[e] = cfms(zl[p], wr[c], W[e]);
+    }
+    __syncthreads();
+  }
+  // adjoint seeds
+  for (int i = tid; i < Mb * Mb; i += nt) gWl[i] = a.gW[(size_t)f * Mb * Mb + i];
+  for (int e = tid; e < Mb * T; e += nt) {
+    const int r = e / T, t = e - r * T;
+    const int n = a.rm.src[r], l = a.rm.tap[r];
+    double g = 2.0 * a.gS[r];
+    if (t >= l) g += 2.0 * a.gP[((size_t)n * F + f) * T + t - l];
+    gY[e] = cscale(Y[e], g);
+    gphi[e] = 0.0;
+  }
+  __syncthreads();
+  for (int r = Mb - 1; r >= 0; --r) {
+    const Cd zr = zt[r * Mb + r];
+    const double sc = 1.0 - zr.x;  // y_r' = sc y_r
+    // rows before the step: y_r = y_r' / sc (the other rows after the reductions)
+    for (int t = tid; t < T; t += nt) {
+      const Cd v = cscale(Y[r * T + t], 1.0 / sc);
+      Y[r * T + t] = v;
+      yr[t] = v;
+    }
+    if (tid < Mb) {
+      wr[tid] = cscale(W[r * Mb + tid], 1.0 / sc);
+      zl[tid] = zt[r * Mb + tid];
+      dl[tid] = dt[r * Mb + tid];
+    }
+    __syncthreads();
+    // g_z_p = -sum_c gW'[p][c] conj(w_r[c]) - sum_t gY'[p][t] conj(y_r[t])
+    for (int p = wave; p < Mb; p += nw) {
+      double gx = 0.0, gy = 0.0;
+      for (int t = lane; t < T; t += 64) {
+        const Cd q = cmulc(gY[p * T + t], yr[t]);
+        gx += q.x;
+        gy += q.y;
+      }
+      for (int c = lane; c < Mb; c += 64) {
+        const Cd q = cmulc(gWl[p * Mb + c], wr[c]);
+        gx += q.x;
+        gy += q.y;
+      }
+      gx = -wave_sum(gx);
+      gy = -wave_sum(gy);
+      if (lane == 0) {
+        const Cd gz{gx, gy};
+        const double d = dl[p];
+        if (p == r) {
+          ga[p] = Cd{0.0, 0.0};
+          gd[p] = 0.5 * pow(d, -1.5) * gz.x;
+        } else {
+          const Cd z = zl[p];
+          ga[p] = cscale(gz, 1.0 / d);
+          gd[p] = -(z.x * gz.x + z.y * gz.y) / d;
+        }
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < T; t += nt) {
+      const Cd y = yr[t];
+      const double y2 = cabs2(y);
+      Cd gyr = cscale(gY[r * T + t], sc);
+      for (int p = 0; p < Mb; ++p) {
+        const double ph = phi(p, t) * invT;
+        gyr = cfma(cscale(y, 2.0 * ph), Cd{gd[p], 0.0}, gyr);
+        gphi[p * T + t] += y2 * gd[p] * invT;
+        if (p == r) continue;
+        const Cd z = zl[p];
+        const Cd gp = gY[p * T + t];
+        gyr = cfms(cconj(z), gp, gyr);
+        const Cd yp = cfma(z, y, Y[p * T + t]);  // row p before the step
+        Y[p * T + t] = yp;
+        gyr = cfma(cscale(yp, ph), cconj(ga[p]), gyr);
+        gY[p * T + t] = cfma(cscale(y, ph), ga[p], gp);
+        gphi[p * T + t] += cmul(cconj(yp), cmul(y, ga[p])).x * invT;
+      }
+      gY[r * T + t] = gyr;
+    }
+    if (tid < Mb) {
+      const int c = tid;
+      Cd g = cscale(gWl[r * Mb + c], sc);
+      for (int p = 0; p < Mb; ++p) {
+        if (p == r) continue;
+        g = cfms(cconj(zl[p]), gWl[p * Mb + c], g);
+        W[p * Mb + c] = cfma(zl[p], wr[c], W[p * Mb + c]);
+      }
+      gWl[r * Mb + c] = g;
+      W[r * Mb + c] = wr[c];
+    }
+    __syncthreads();
+  }
+  // demix: gW = gWl + gY xbar^H; gxbar = Wk^H gY
+  const Cd* Wk = a.Wk + (size_t)f * Mb * Mb;
+  for (int e = tid; e < Mb * Mb; e += nt) {
+    const int r = e / Mb, c = e - r * Mb;
+    Cd s = gWl[e];
+    for (int t = 0; t < T; ++t) s = cfma(gY[r * T + t], cconj(xbar(a, f, c, t)), s);
+    a.gW[(size_t)f * Mb * Mb + e] = s;
+  }
+  for (int e = tid; e < a.M * T; e += nt) {
+    const int m = e / T, t = e - m * T;
+    Cd s{0.0, 0.0};
+    for (int d = 0; d < a.D && t + d < T; ++d)
+      for (int r = 0; r < Mb; ++r) s = cfma(cconj(Wk[r * Mb + d * a.M + m]), gY[r * T + t + d], s);
+    const size_t o = ((size_t)m * F + f) * T + t;
+    a.gX[o] = cadd(a.gX[o], s);
+  }
+  // phi_(n,l)[t] = 1 / lam[n][t - l]: glam[n][s] -= sum_l gphi_(n,l)[s + l] ilam[n][s]^2
+  for (int e = tid; e < a.N * T; e += nt) {
+    const int n = e / T, s = e - n * T;
+    const size_t o = ((size_t)n * F + f) * T + s;
+    const double il = a.ilam[o];
+    double g = 0.0;
+    for (int l = 0; l < a.rm.L[n] && s + l < T; ++l) g += gphi[(a.rm.r0[n] + l) * T + s + l];
+    a.glam[o] -= g * il * il;
+  }
+}
+
+// ------------------------------------------------------------------ lambda
+// Per (n, f, k): gB += sum_s glam Vk.
+__global__ void __launch_bounds__(256) k_adj_l1(AdjArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)a.N * a.F * a.K) return;
+  const int k = (int)(i % a.K), f = (int)((i / a.K) % a.F), n = (int)(i / ((size_t)a.F * a.K));
+  const double* g = a.glam + ((size_t)n * a.F + f) * a.T;
+  const double* v = a.Vk + ((size_t)n * a.K + k) * a.T;
+  double s = 0.0;
+  for (int t = 0; t < a.T; ++t) s += g[t] * v[t];
+  a.gB[i] += s;
+}
+
+// Per (n, k, s): gV += sum_f (B^ glamh + H1 P / lam^2 + H2 c / lam + Bk glam).
+__global__ void __launch_bounds__(256) k_adj_l2(AdjArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)a.N * a.K * a.T) return;
+  const int s = (int)(i % a.T), k = (int)((i / a.T) % a.K), n = (int)(i / ((size_t)a.K * a.T));
+  const double c = tapc(a.rm, n, s, a.T);
+  double acc = 0.0;
+  for (int f = 0; f < a.F; ++f) {
+    const size_t fk = ((size_t)n * a.F + f) * a.K + k, fs = ((size_t)n * a.F + f) * a.T + s;
+    const double il = a.ilam[fs];
+    acc += a.Bh[fk] * a.glamh[fs] + a.H1[fk] * a.P[fs] * il * il + a.H2[fk] * c * il + a.Bk[fk] * a.glam[fs];
+  }
+  a.gV[i] += acc;
+}
+
+}  // namespace
+
+size_t adj_images_lds(int Mb, int M) { return (size_t)(3 * Mb * Mb + 2 * M * Mb + Mb) * 16 + 64; }
+size_t adj_iss_lds(int Mb, int T) { return (size_t)(2 * Mb * Mb + 3 * Mb) * 16 + 2 * Mb * 8 + (size_t)T * 16; }
+
+namespace {
+AdjArgs make_adj(const AdjPtrs& p, const Dims& d, double floor) {
+  AdjArgs a{};
+  a.X = static_cast<const Cd*>(p.X);
+  a.Wk = static_cast<const Cd*>(p.Wk);
+  a.Bk = p.Bk;
+  a.Vk = p.Vk;
+  a.Ws = static_cast<const Cd*>(p.Ws);
+  a.Bh = p.Bh;
+  a.Vh = p.Vh;
+  a.ilam = p.ilam;
+  a.P = p.P;
+  a.mu = p.mu;
+  a.gW = static_cast<Cd*>(p.gW);
+  a.gB = p.gB;
+  a.gV = p.gV;
+  a.gBh = p.gBh;
+  a.gVh = p.gVh;
+  a.gP = p.gP;
+  a.glam = p.glam;
+  a.glamh = p.glamh;
+  a.lamh = p.lamh;
+  a.G1 = p.G1;
+  a.G2 = p.G2;
+  a.H1 = p.H1;
+  a.H2 = p.H2;
+  a.part = p.part;
+  a.gS = p.gS;
+  a.gX = static_cast<Cd*>(p.gX);
+  a.status = p.status;
+  a.Y = static_cast<Cd*>(p.Y);
+  a.gY = static_cast<Cd*>(p.gY);
+  a.gphi = p.gphi;
+  a.ztape = static_cast<Cd*>(p.ztape);
+  a.dtape = p.dtape;
+  a.floor = floor;
+  a.F = d.F;
+  a.T = d.T;
+  a.M = d.M;
+  a.D = d.D;
+  a.N = d.N;
+  a.K = d.K;
+  a.Mb = d.Mb;
+  a.rm = d.rm;
+  return a;
+}
+}  // namespace
+
+// Host side: the images stage and one reverse iteration; launches go to stream s.
+hipError_t adj_images(const AdjPtrs& p, const Dims& d, const void* W, const void* gC, hipStream_t s) {
+  const AdjArgs a = make_adj(p, d, 0.0);
+  const size_t lds = adj_images_lds(d.Mb, d.M);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_adj_images, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_adj_images, dim3(d.F), dim3(256), lds, s, a, static_cast<const Cd*>(W), static_cast<const Cd*>(gC));
+  return hipGetLastError();
+}
+
+hipError_t adj_iteration(const AdjPtrs& p, const Dims& d, double floor, hipStream_t s) {
+  const AdjArgs a = make_adj(p, d, floor);
+  auto blocks = [](size_t n) { return dim3((unsigned)((n + 255) / 256)); };
+  const size_t nkt = (size_t)d.N * d.K * d.T, nft = (size_t)d.N * d.F * d.T, nfk = (size_t)d.N * d.F * d.K;
+  const size_t napply = (size_t)d.F * d.Mb * d.Mb + nfk + nkt;
+  hipLaunchKernelGGL(k_adj_rescale_part, dim3(d.F), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_rescale_final, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_adj_rescale_apply, blocks(napply), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_v1, blocks(nkt), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_v2, blocks(nft), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_b1, blocks(nfk), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_b2, blocks(nft), dim3(256), 0, s, a);
+  const size_t lds = adj_iss_lds(d.Mb, d.T);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_adj_iss, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_adj_iss, dim3(d.F), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(k_adj_l1, blocks(nfk), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_l2, blocks(nkt), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ctfiss

@@ -103,6 +103,35 @@ template <typename R>
 hipError_t nmf_batch_t(int kind, const void* desc, const int* start, int nprob, int blocks, int threads, int* zero,
                        int nzero, hipStream_t s);
 hipError_t launch_zero_status(int* status, hipStream_t s);
+
+// Reverse mode of the unrolled iterations (FP64; see adjoint.hip).
+struct AdjPtrs {
+  const void* X;                     // [M][F][T]
+  const void* Wk;                    // state at the start of the iteration being reversed
+  const double* Bk;
+  const double* Vk;
+  const void* Ws;                    // W after the sweep (before the rescale)
+  const double* Bh;                  // B after the basis update (before the rescale)
+  const double* Vh;                  // V after the activation update
+  const double* ilam;                // 1 / (Bk Vk)
+  const double* P;                   // tap-aligned powers of the swept rows
+  const double* mu;                  // row scales of the iteration
+  void* gW;                          // adjoints of the state: in, of the next state; out, of this one
+  double* gB;
+  double* gV;
+  double *gBh, *gVh, *gP, *glam, *glamh, *lamh, *G1, *G2, *H1, *H2, *part, *gS;  // scratch
+  void* gX;                          // [M][F][T] accumulated
+  int* status;
+  void* Y;                           // [F][Mb][T] sweep scratch
+  void* gY;
+  double* gphi;
+  void* ztape;                       // [F][Mb][Mb]
+  double* dtape;
+};
+size_t adj_images_lds(int Mb, int M);
+size_t adj_iss_lds(int Mb, int T);
+hipError_t adj_images(const AdjPtrs& p, const Dims& d, const void* W, const void* gC, hipStream_t s);
+hipError_t adj_iteration(const AdjPtrs& p, const Dims& d, double floor, hipStream_t s);
 size_t images_lds(const Dims& d);
 size_t nll_lds(const Dims& d);
 

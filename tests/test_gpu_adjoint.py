@@ -1,0 +1,129 @@
+"""Reverse mode (ctfiss_backward, behind a torch.autograd.Function) against
+the FP64 PyTorch autograd reference and against central finite differences.
+
+The loss is the mean squared error between the source images after n
+iterations (from W = I and the given B0, V0) and a fixed random target.  Both
+sides are FP64; the gradients are held to 1e-8 relative (Frobenius norm) on
+short runs and 1e-6 over 20 iterations of a bin slice shaped like the
+differentiation workload (T = 375, M = 3, D = 4, taps 6 + 6, K = 10), where
+the fixed-point dynamics amplify summation-order differences.  The finite
+differences use h = 1e-3 along random directions of the GPU forward and hold
+the directional derivative to 1e-3.
+"""
+import numpy as np
+import pytest
+
+from datagen import random_problem, rng_for
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# name: (F, T, M, D, taps, K, iterations)
+CASES = {
+    "small": (3, 30, 2, 2, (2, 2), 3, 3),
+    "uneven_taps": (4, 41, 2, 3, (4, 2), 2, 4),
+    "three_sources": (3, 50, 3, 1, (1, 1, 1), 3, 3),
+    "c4_slice": (6, 375, 3, 4, (6, 6), 10, 20),
+}
+TOL = {"small": 1e-8, "uneven_taps": 1e-8, "three_sources": 1e-8, "c4_slice": 1e-6}
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def problem(name, seed=0):
+    F, T, M, D, taps, K, n = CASES[name]
+    X, B0, V0 = random_problem(F, T, M, len(taps), K, seed, scale_spread=0.5)
+    rng = rng_for(seed + 7)
+    target = 0.3 * (rng.standard_normal((len(taps), M, F, T)) + 1j * rng.standard_normal((len(taps), M, F, T)))
+    return X, B0, V0, target, D, taps, n
+
+
+def reference(X, B0, V0, target, D, taps, n):
+    from oracle import ctf_iss_torch as ot
+    Xt = torch.from_numpy(X).requires_grad_(True)
+    Bt = torch.from_numpy(B0).requires_grad_(True)
+    Vt = torch.from_numpy(V0).requires_grad_(True)
+    C = ot.forward(Xt, Bt, Vt, D, taps, n)[0]
+    ot.mse(C, torch.from_numpy(target)).backward()
+    return C.detach().numpy(), Xt.grad.numpy(), Bt.grad.numpy(), Vt.grad.numpy()
+
+
+def gpu(X, B0, V0, target, D, taps, n):
+    from paper_2510_02382_amd.autograd import separate
+    Xg = torch.from_numpy(X).cuda().requires_grad_(True)
+    Bg = torch.from_numpy(B0).cuda().requires_grad_(True)
+    Vg = torch.from_numpy(V0).cuda().requires_grad_(True)
+    C = separate(Xg, Bg, Vg, D, taps, n)
+    loss = ((C - torch.from_numpy(target).cuda()).abs() ** 2).mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    return C.detach().cpu().numpy(), Xg.grad.cpu().numpy(), Bg.grad.cpu().numpy(), Vg.grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_gradients_match_autograd_reference(case):
+    args = problem(case)
+    C, gX, gB, gV = gpu(*args)
+    Cr, gXr, gBr, gVr = reference(*args)
+    tol = TOL[case]
+    assert rel(C, Cr) < tol, rel(C, Cr)
+    assert rel(gX, gXr) < tol, rel(gX, gXr)
+    assert rel(gB, gBr) < tol, rel(gB, gBr)
+    assert rel(gV, gVr) < tol, rel(gV, gVr)
+
+
+@pytest.mark.parametrize("case", ["small", "c4_slice"])
+def test_gradients_match_central_differences(case):
+    from paper_2510_02382_amd import Separator
+    X, B0, V0, target, D, taps, n = problem(case, seed=3)
+    M, F, T = X.shape
+    N, _, K = B0.shape
+    tgt = torch.from_numpy(target).cuda()
+
+    def loss(Xn, Bn):
+        sep = Separator(F, T, M, D, N, K, taps, precision="fp64")
+        sep.set_input(torch.from_numpy(np.ascontiguousarray(Xn)).cuda())
+        sep.set_state(B=torch.from_numpy(np.ascontiguousarray(Bn)).cuda(), V=torch.from_numpy(V0).cuda())
+        sep.iterate(n)
+        C = sep.source_images()
+        out = float(((C - tgt).abs() ** 2).mean())
+        sep.close()
+        return out
+
+    _, gX, gB, _ = gpu(X, B0, V0, target, D, taps, n)
+    rng = rng_for(11)
+    h = 1e-3
+    for _ in range(2):
+        dX = rng.standard_normal(X.shape) + 1j * rng.standard_normal(X.shape)
+        dX *= np.abs(X)  # relative perturbation of every coefficient
+        fd = (loss(X + h * dX, B0) - loss(X - h * dX, B0)) / (2 * h)
+        an = float(np.sum(np.real(np.conj(gX) * dX)))
+        assert abs(an - fd) <= 1e-3 * abs(fd), (an, fd)
+        dB = rng.standard_normal(B0.shape) * B0
+        fd = (loss(X, B0 + h * dB) - loss(X, B0 - h * dB)) / (2 * h)
+        an = float(np.sum(gB * dB))
+        assert abs(an - fd) <= 1e-3 * abs(fd), (an, fd)
+
+
+def test_backward_is_fp64_all_taps_iss_only():
+    from paper_2510_02382_amd import Separator
+    from paper_2510_02382_amd import binding as b
+    X, B0, V0, target, D, taps, n = problem("small")
+    M, F, T = X.shape
+    N, _, K = B0.shape
+    gC = torch.zeros((N, M, F, T), dtype=torch.complex64, device="cuda")
+    sep = Separator(F, T, M, D, N, K, taps, precision="fp32")
+    sep.set_input(torch.from_numpy(X).cuda().to(torch.complex64))
+    with pytest.raises(b.CtfissError) as e:
+        sep.backward(n, torch.from_numpy(B0).cuda().float(), torch.from_numpy(V0).cuda().float(), gC)
+    assert e.value.status == b.CTFISS_E_UNSUPPORTED
+    sep.close()
+    sep = Separator(F, T, M, D, N, K, taps, precision="fp64", vrule="paper_tap0")
+    sep.set_input(torch.from_numpy(X).cuda())
+    with pytest.raises(b.CtfissError) as e:
+        sep.backward(n, torch.from_numpy(B0).cuda(), torch.from_numpy(V0).cuda(), gC.to(torch.complex128))
+    assert e.value.status == b.CTFISS_E_UNSUPPORTED
+    sep.close()
