@@ -302,6 +302,99 @@ def precision_bench(args) -> int:
     return 0
 
 
+def adjoint_bench(args) -> int:
+    """Differentiation workload: 32 mixtures of 6 s (N=2, M=3, STFT 1024/256: F=513, T=376, D=4
+    stacked frames: Mbar=12, taps 6+6, K=10), 20 unrolled iterations, loss = mean squared error of
+    the source images against the known synthetic images.  One step = forward and reverse pass
+    (ctfiss_backward) of all 32 mixtures, FP64, one context at a time.  Mixture 0's gradients are
+    checked against the FP64 PyTorch autograd reference on the host, which is also timed there as
+    the CPU baseline."""
+    import torch
+
+    from datagen import WORKLOADS, init_nmf, make_mixture
+    from paper_2510_02382_amd.autograd import separate
+
+    wl = WORKLOADS["c4"]
+    nmix = args.batch if args.batch != 256 else 32
+    log(f"workload c4: {nmix} mixtures, F={wl.F} T={wl.T} M={wl.M} D={wl.D} Mbar={wl.mbar} taps={wl.row_taps} "
+        f"K={wl.K} iters={wl.n_iter}")
+    dev = torch.device("cuda:0")
+    mixes = []
+    for i in range(nmix):
+        m = make_mixture(wl, 1000 + i, with_images=True)
+        B0, V0 = init_nmf(wl.N, wl.F, wl.K, wl.T, 1000 + i)
+        mixes.append((torch.from_numpy(m.X).to(dev), torch.from_numpy(B0).to(dev), torch.from_numpy(V0).to(dev),
+                      torch.from_numpy(m.images).to(dev)))
+
+    def step(sample=None):
+        out = None
+        for i, (X, B0, V0, img) in enumerate(mixes if sample is None else mixes[:sample]):
+            Xg = X.clone().requires_grad_(True)
+            Bg = B0.clone().requires_grad_(True)
+            C = separate(Xg, Bg, V0, wl.D, wl.row_taps, wl.n_iter)
+            loss = ((C - img).abs() ** 2).mean()
+            loss.backward()
+            if i == 0:
+                out = (float(loss), Xg.grad, Bg.grad)
+        return out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        first = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    units = nmix * wl.F * wl.T * wl.n_iter
+    value = units / dt
+    # forward alone, for the split
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        for X, B0, V0, img in mixes:
+            separate(X, B0, V0, wl.D, wl.row_taps, wl.n_iter)
+    torch.cuda.synchronize()
+    dt_fwd = time.perf_counter() - t0
+    log(f"forward + reverse: {dt * 1e3:.1f} ms per step of {nmix} mixtures ({value:.3e} F·T·it/s); "
+        f"forward alone {dt_fwd * 1e3:.1f} ms")
+    cpu = None
+    check = None
+    if not args.no_cpu_baseline:
+        from oracle import ctf_iss_torch as ot
+        X, B0, V0, img = mixes[0]
+        Xt = X.cpu().clone().requires_grad_(True)
+        Bt = B0.cpu().clone().requires_grad_(True)
+        nthreads = torch.get_num_threads()
+        t0 = time.perf_counter()
+        C = ot.forward(Xt, Bt, V0.cpu(), wl.D, wl.row_taps, wl.n_iter)[0]
+        loss = ot.mse(C, img.cpu())
+        loss.backward()
+        dtc = time.perf_counter() - t0
+        gx = first[1].cpu().numpy()
+        gb = first[2].cpu().numpy()
+        import numpy as np
+        check = {"mixture": 0, "loss": first[0], "loss_reference": float(loss),
+                 "gX_rel_err": float(np.linalg.norm(gx - Xt.grad.numpy()) / np.linalg.norm(Xt.grad.numpy())),
+                 "gB0_rel_err": float(np.linalg.norm(gb - Bt.grad.numpy()) / np.linalg.norm(Bt.grad.numpy()))}
+        cpu = {"value": wl.F * wl.T * wl.n_iter / dtc, "unit": "F·T·iters/s (forward + reverse)", "cores": nthreads,
+               "kind": "oracle", "sample": f"mixture 0 of the batch: FP64 PyTorch autograd forward and reverse on the "
+                                           f"host, {nthreads} threads, {dtc:.1f} s"}
+        log(f"autograd reference on the host: {dtc:.1f} s for one mixture; gradient errors {check}")
+    out = {
+        "metric": "F·T·iters/s ISS vs IP vs FP64-ISS at rel err ≤1e-4; HBM GB/s fraction",
+        "value": value, "unit": "F·T·iters/s (forward + reverse)", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"c4 differentiation: {nmix} mixtures of 6 s, N=2, M=3, STFT 1024/256, D=4 "
+                               f"(Mbar=12, taps 6+6), K=10, 20 unrolled iterations, image MSE loss, gradients "
+                               f"w.r.t. the mixture STFT and the initial bases",
+                   "F": wl.F, "T": wl.T, "Mbar": wl.mbar, "K": wl.K, "iterations": wl.n_iter, "mixtures": nmix},
+        "forward_ms_per_step": dt_fwd * 1e3, "gradient_check": check, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,8 +406,9 @@ def main() -> int:
     ap.add_argument("--batched", action="store_true",
                     help="time the batch of uneven mixtures instead of the single long mixture")
     ap.add_argument("--batch", type=int, default=256, help="mixtures in --batched mode")
-    ap.add_argument("--workload", choices=["c1", "c3"], default="c1",
-                    help="c3: the 60 s, Mbar = 64 mixture (team launches) instead of the 10 s, Mbar = 24 one")
+    ap.add_argument("--workload", choices=["c1", "c3", "c4"], default="c1",
+                    help="c3: the 60 s, Mbar = 64 mixture (team launches) instead of the 10 s, Mbar = 24 one; "
+                         "c4: forward and reverse pass of 32 mixtures (gradients)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -330,6 +424,8 @@ def main() -> int:
         return batched_bench(args)
     if args.workload == "c3":
         return precision_bench(args)
+    if args.workload == "c4":
+        return adjoint_bench(args)
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
