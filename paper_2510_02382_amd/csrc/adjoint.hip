@@ -52,6 +52,8 @@ struct AdjArgs {
   double* glam;   // [N][F][T] of lambda = Bk Vk
   double* glamh;  // [N][F][T] of lambda = B^ Vk
   double* lamh;   // [N][F][T] B^ Vk
+  double* q1;     // [N][F][T] P / lamh^2
+  double* q2;     // [N][F][T] c / lamh
   double* G1;     // [N][K][T] adjoint of the activation update's numerator sum
   double* G2;     // [N][K][T] ... denominator sum
   double* H1;     // [N][F][K] adjoint of the basis update's numerator sum
@@ -68,6 +70,7 @@ struct AdjArgs {
   double* dtape;  // [F][Mb][Mb] d_p of row r's step
   double floor;
   int F, T, M, D, N, K, Mb;
+  int sweep_lds;  // 1: the sweep keeps gY and gphi in LDS
   RowMap rm;
 };
 
@@ -219,22 +222,24 @@ __global__ void __launch_bounds__(256) k_adj_rescale_part(AdjArgs a) {
   }
 }
 
-// g_mu_r = -sum_f part[f][r] / mu_r - [r first row of n] 2 sum_f part[f][Mb + n] / mu_r;
+// One wave per row r (lanes over f): g_mu_r = -sum_f part[f][r] / mu_r, minus
+// 2 sum_f part[f][Mb + n] / mu_r for the first row of source n;
 // gS_r = g_mu_r / (2 mu_r F T).
 __global__ void __launch_bounds__(64) k_adj_rescale_final(AdjArgs a) {
-  const int r = threadIdx.x;
-  if (r >= a.Mb) return;
-  const int W = a.Mb + a.N;
-  double s = 0.0;
-  for (int f = 0; f < a.F; ++f) s += a.part[(size_t)f * W + r];
-  double g = -s / a.mu[r];
-  const int n = a.rm.src[r];
-  if (a.rm.r0[n] == r) {
-    double sb = 0.0;
-    for (int f = 0; f < a.F; ++f) sb += a.part[(size_t)f * W + a.Mb + n];
-    g -= 2.0 * sb / a.mu[r];
+  const int r = blockIdx.x, lane = threadIdx.x;
+  const int W = a.Mb + a.N, n = a.rm.src[r];
+  const bool first = a.rm.r0[n] == r;
+  double s = 0.0, sb = 0.0;
+  for (int f = lane; f < a.F; f += 64) {
+    s += a.part[(size_t)f * W + r];
+    if (first) sb += a.part[(size_t)f * W + a.Mb + n];
   }
-  a.gS[r] = g / (2.0 * a.mu[r] * (double)a.F * (double)a.T);
+  s = wave_sum(s);
+  sb = wave_sum(sb);
+  if (lane == 0) {
+    const double g = -(s + 2.0 * sb) / a.mu[r];
+    a.gS[r] = g / (2.0 * a.mu[r] * (double)a.F * (double)a.T);
+  }
 }
 
 // gW^s = gW' / mu_r (in place), gB^ = gB' / mu_first^2, gV^ = gV'.
@@ -256,23 +261,37 @@ __global__ void __launch_bounds__(256) k_adj_rescale_apply(AdjArgs a) {
 }
 
 // ------------------------------------------------------------------ activation update
-// Per (n, k, s): num = sum_f B^ P / lamh^2, den = sum_f B^ c / lamh (lamh = B^ Vk);
+// Per (n, f, s): lamh = B^ Vk, q1 = P / lamh^2, q2 = c / lamh.
+__global__ void __launch_bounds__(256) k_adj_v0(AdjArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)a.N * a.F * a.T) return;
+  const int s = (int)(i % a.T), f = (int)((i / a.T) % a.F), n = (int)(i / ((size_t)a.F * a.T));
+  const double* b = a.Bh + ((size_t)n * a.F + f) * a.K;
+  double lam = 0.0;
+  for (int k = 0; k < a.K; ++k) lam += b[k] * a.Vk[((size_t)n * a.K + k) * a.T + s];
+  a.lamh[i] = lam;
+  a.q1[i] = a.P[i] / (lam * lam);
+  a.q2[i] = tapc(a.rm, n, s, a.T) / lam;
+}
+
+// One wave per (n, k, s): num = sum_f B^ q1, den = sum_f B^ q2 (lanes over f);
 // where V^ was not clamped: gV[n][k][s] = gV^ sqrt(num / den), G1 = gV^ V^ / (2 num),
 // G2 = -gV^ V^ / (2 den); else all zero.
 __global__ void __launch_bounds__(256) k_adj_v1(AdjArgs a) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= (size_t)a.N * a.K * a.T) return;
   const int s = (int)(i % a.T), k = (int)((i / a.T) % a.K), n = (int)(i / ((size_t)a.K * a.T));
-  const double c = tapc(a.rm, n, s, a.T);
   double num = 0.0, den = 0.0;
-  for (int f = 0; f < a.F; ++f) {
-    const double* b = a.Bh + ((size_t)n * a.F + f) * a.K;
-    double lam = 0.0;
-    for (int j = 0; j < a.K; ++j) lam += b[j] * a.Vk[((size_t)n * a.K + j) * a.T + s];
-    const double p = a.P[((size_t)n * a.F + f) * a.T + s];
-    num += b[k] * p / (lam * lam);
-    den += b[k] * c / lam;
+  for (int f = lane; f < a.F; f += 64) {
+    const double b = a.Bh[((size_t)n * a.F + f) * a.K + k];
+    const size_t o = ((size_t)n * a.F + f) * a.T + s;
+    num += b * a.q1[o];
+    den += b * a.q2[o];
   }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if (lane != 0) return;
   const double ratio = sqrt(num / den);
   const double val = a.Vk[i] * ratio;
   const double g = a.gVh[i];
@@ -294,8 +313,7 @@ __global__ void __launch_bounds__(256) k_adj_v2(AdjArgs a) {
   if (i >= (size_t)a.N * a.F * a.T) return;
   const int s = (int)(i % a.T), f = (int)((i / a.T) % a.F), n = (int)(i / ((size_t)a.F * a.T));
   const double* b = a.Bh + ((size_t)n * a.F + f) * a.K;
-  double lam = 0.0;
-  for (int k = 0; k < a.K; ++k) lam += b[k] * a.Vk[((size_t)n * a.K + k) * a.T + s];
+  const double lam = a.lamh[i];
   const double p = a.P[i], c = tapc(a.rm, n, s, a.T);
   double gp = 0.0, gl = 0.0;
   for (int k = 0; k < a.K; ++k) {
@@ -303,34 +321,34 @@ __global__ void __launch_bounds__(256) k_adj_v2(AdjArgs a) {
     gp += a.G1[o] * b[k] / (lam * lam);
     gl += -2.0 * a.G1[o] * b[k] * p / (lam * lam * lam) - a.G2[o] * b[k] * c / (lam * lam);
   }
-  a.lamh[i] = lam;
   a.gP[i] = gp;
   a.glamh[i] = gl;
 }
 
 // ------------------------------------------------------------------ basis update
-// Per (n, f, k): first the rest of gB^ from the activation update,
-//   gB^ += sum_s (G1 P / lamh^2 + G2 c / lamh + glamh Vk);
-// then the basis update with lam = 1 / ilam: num = sum_s P Vk / lam^2,
-// den = sum_s c Vk / lam; where B^ was not clamped: gB = gB^ sqrt(num / den),
-// H1 = gB^ B^ / (2 num), H2 = -gB^ B^ / (2 den); else zero.
+// One wave per (n, f, k), lanes over s: first the rest of gB^ from the
+// activation update, gB^ += sum_s (G1 q1 + G2 q2 + glamh Vk); then the basis
+// update with lam = 1 / ilam: num = sum_s P Vk / lam^2, den = sum_s c Vk / lam;
+// where B^ was not clamped: gB = gB^ sqrt(num / den), H1 = gB^ B^ / (2 num),
+// H2 = -gB^ B^ / (2 den); else zero.
 __global__ void __launch_bounds__(256) k_adj_b1(AdjArgs a) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= (size_t)a.N * a.F * a.K) return;
   const int k = (int)(i % a.K), f = (int)((i / a.K) % a.F), n = (int)(i / ((size_t)a.F * a.K));
-  const size_t fo = ((size_t)n * a.F + f) * a.T;
-  const double* v = a.Vk + ((size_t)n * a.K + k) * a.T;
-  double gbh = a.gBh[i];
-  double num = 0.0, den = 0.0;
-  for (int s = 0; s < a.T; ++s) {
-    const double c = tapc(a.rm, n, s, a.T), p = a.P[fo + s];
-    const double lh = a.lamh[fo + s];
-    const size_t o = ((size_t)n * a.K + k) * a.T + s;
-    gbh += a.G1[o] * p / (lh * lh) + a.G2[o] * c / lh + a.glamh[fo + s] * v[s];
+  const size_t fo = ((size_t)n * a.F + f) * a.T, ko = ((size_t)n * a.K + k) * a.T;
+  double gbh = 0.0, num = 0.0, den = 0.0;
+  for (int s = lane; s < a.T; s += 64) {
+    const double c = tapc(a.rm, n, s, a.T), p = a.P[fo + s], v = a.Vk[ko + s];
+    gbh += a.G1[ko + s] * a.q1[fo + s] + a.G2[ko + s] * a.q2[fo + s] + a.glamh[fo + s] * v;
     const double il = a.ilam[fo + s];
-    num += p * v[s] * il * il;
-    den += c * v[s] * il;
+    num += p * v * il * il;
+    den += c * v * il;
   }
+  gbh = wave_sum(gbh) + a.gBh[i];
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if (lane != 0) return;
   const double ratio = sqrt(num / den);
   const double val = a.Bk[i] * ratio;
   if (val >= a.floor) {
@@ -379,9 +397,11 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
   double* dl = reinterpret_cast<double*>(wr + Mb);  // [Mb]
   double* gd = dl + Mb;                  // [Mb] adjoint of d_p
   Cd* yr = reinterpret_cast<Cd*>(gd + Mb);  // [T]
+  // the rows (read-mostly) stay in global memory; their adjoints and the
+  // weight adjoints go to LDS when they fit (every step reads and writes them)
   Cd* Y = a.Y + (size_t)f * Mb * T;
-  Cd* gY = a.gY + (size_t)f * Mb * T;
-  double* gphi = a.gphi + (size_t)f * Mb * T;
+  Cd* gY = a.sweep_lds ? yr + T : a.gY + (size_t)f * Mb * T;
+  double* gphi = a.sweep_lds ? reinterpret_cast<double*>(gY + (size_t)Mb * T) : a.gphi + (size_t)f * Mb * T;
   Cd* zt = a.ztape + (size_t)f * Mb * Mb;
   double* dt = a.dtape + (size_t)f * Mb * Mb;
   auto phi = [&](int p, int t) {
@@ -551,37 +571,49 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
 }
 
 // ------------------------------------------------------------------ lambda
-// Per (n, f, k): gB += sum_s glam Vk.
+// One wave per (n, f, k), lanes over s: gB += sum_s glam Vk.
 __global__ void __launch_bounds__(256) k_adj_l1(AdjArgs a) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= (size_t)a.N * a.F * a.K) return;
   const int k = (int)(i % a.K), f = (int)((i / a.K) % a.F), n = (int)(i / ((size_t)a.F * a.K));
   const double* g = a.glam + ((size_t)n * a.F + f) * a.T;
   const double* v = a.Vk + ((size_t)n * a.K + k) * a.T;
   double s = 0.0;
-  for (int t = 0; t < a.T; ++t) s += g[t] * v[t];
-  a.gB[i] += s;
+  for (int t = lane; t < a.T; t += 64) s += g[t] * v[t];
+  s = wave_sum(s);
+  if (lane == 0) a.gB[i] += s;
 }
 
-// Per (n, k, s): gV += sum_f (B^ glamh + H1 P / lam^2 + H2 c / lam + Bk glam).
+// One wave per (n, k, s), lanes over f:
+// gV += sum_f (B^ glamh + H1 P / lam^2 + H2 c / lam + Bk glam).
 __global__ void __launch_bounds__(256) k_adj_l2(AdjArgs a) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= (size_t)a.N * a.K * a.T) return;
   const int s = (int)(i % a.T), k = (int)((i / a.T) % a.K), n = (int)(i / ((size_t)a.K * a.T));
   const double c = tapc(a.rm, n, s, a.T);
   double acc = 0.0;
-  for (int f = 0; f < a.F; ++f) {
+  for (int f = lane; f < a.F; f += 64) {
     const size_t fk = ((size_t)n * a.F + f) * a.K + k, fs = ((size_t)n * a.F + f) * a.T + s;
     const double il = a.ilam[fs];
     acc += a.Bh[fk] * a.glamh[fs] + a.H1[fk] * a.P[fs] * il * il + a.H2[fk] * c * il + a.Bk[fk] * a.glam[fs];
   }
-  a.gV[i] += acc;
+  acc = wave_sum(acc);
+  if (lane == 0) a.gV[i] += acc;
 }
 
 }  // namespace
 
 size_t adj_images_lds(int Mb, int M) { return (size_t)(3 * Mb * Mb + 2 * M * Mb + Mb) * 16 + 64; }
-size_t adj_iss_lds(int Mb, int T) { return (size_t)(2 * Mb * Mb + 3 * Mb) * 16 + 2 * Mb * 8 + (size_t)T * 16; }
+size_t adj_iss_lds_base(int Mb, int T) { return (size_t)(2 * Mb * Mb + 3 * Mb) * 16 + 2 * Mb * 8 + (size_t)T * 16; }
+// gY and gphi in LDS only while three workgroups still fit a CU: a launch has
+// one workgroup per bin, and with fewer per CU the bins of a typical F (513)
+// need several rounds, which costs more than the global-memory traffic saved.
+bool adj_sweep_in_lds(int Mb, int T) { return adj_iss_lds_base(Mb, T) + (size_t)Mb * T * 24 <= kMaxLdsBytes / 3; }
+size_t adj_iss_lds(int Mb, int T) {
+  return adj_iss_lds_base(Mb, T) + (adj_sweep_in_lds(Mb, T) ? (size_t)Mb * T * 24 : 0);
+}
 
 namespace {
 AdjArgs make_adj(const AdjPtrs& p, const Dims& d, double floor) {
@@ -605,6 +637,8 @@ AdjArgs make_adj(const AdjPtrs& p, const Dims& d, double floor) {
   a.glam = p.glam;
   a.glamh = p.glamh;
   a.lamh = p.lamh;
+  a.q1 = p.q1;
+  a.q2 = p.q2;
   a.G1 = p.G1;
   a.G2 = p.G2;
   a.H1 = p.H1;
@@ -626,6 +660,7 @@ AdjArgs make_adj(const AdjPtrs& p, const Dims& d, double floor) {
   a.N = d.N;
   a.K = d.K;
   a.Mb = d.Mb;
+  a.sweep_lds = adj_sweep_in_lds(d.Mb, d.T) ? 1 : 0;
   a.rm = d.rm;
   return a;
 }
@@ -649,11 +684,12 @@ hipError_t adj_iteration(const AdjPtrs& p, const Dims& d, double floor, hipStrea
   const size_t nkt = (size_t)d.N * d.K * d.T, nft = (size_t)d.N * d.F * d.T, nfk = (size_t)d.N * d.F * d.K;
   const size_t napply = (size_t)d.F * d.Mb * d.Mb + nfk + nkt;
   hipLaunchKernelGGL(k_adj_rescale_part, dim3(d.F), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_rescale_final, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_adj_rescale_final, dim3(d.Mb), dim3(64), 0, s, a);
   hipLaunchKernelGGL(k_adj_rescale_apply, blocks(napply), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_v1, blocks(nkt), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_v0, blocks(nft), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_v1, blocks(nkt * 64), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_adj_v2, blocks(nft), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_b1, blocks(nfk), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_b1, blocks(nfk * 64), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_adj_b2, blocks(nft), dim3(256), 0, s, a);
   const size_t lds = adj_iss_lds(d.Mb, d.T);
   if (lds > 65536) {
@@ -661,8 +697,8 @@ hipError_t adj_iteration(const AdjPtrs& p, const Dims& d, double floor, hipStrea
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_adj_iss, dim3(d.F), dim3(256), lds, s, a);
-  hipLaunchKernelGGL(k_adj_l1, blocks(nfk), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_l2, blocks(nkt), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_l1, blocks(nfk * 64), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_l2, blocks(nkt * 64), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

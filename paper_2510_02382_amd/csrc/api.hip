@@ -570,8 +570,8 @@ const char* ctfiss_status_string(int status) {
 namespace {
 
 struct AdjLayout {
-  size_t ckW, ckB, ckV, gW, gB, gBh, gV, gVh, gP, glam, glamh, lamh, G1, G2, H1, H2, part, gS, Y, gY, gphi, zt, dt,
-      total;
+  size_t ckW, ckB, ckV, gW, gB, gBh, gV, gVh, gP, glam, glamh, lamh, q1, q2, G1, G2, H1, H2, part, gS, Y, gY, gphi,
+      zt, dt, total;
 };
 
 AdjLayout adj_layout(const Dims& d, int n_iter) {
@@ -596,6 +596,8 @@ AdjLayout adj_layout(const Dims& d, int n_iter) {
   L.glam = take(ft);
   L.glamh = take(ft);
   L.lamh = take(ft);
+  L.q1 = take(ft);
+  L.q2 = take(ft);
   L.G1 = take(v);
   L.G2 = take(v);
   L.H1 = take(b);
@@ -674,6 +676,8 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
   p.glam = reinterpret_cast<double*>(ws + L.glam);
   p.glamh = reinterpret_cast<double*>(ws + L.glamh);
   p.lamh = reinterpret_cast<double*>(ws + L.lamh);
+  p.q1 = reinterpret_cast<double*>(ws + L.q1);
+  p.q2 = reinterpret_cast<double*>(ws + L.q2);
   p.G1 = reinterpret_cast<double*>(ws + L.G1);
   p.G2 = reinterpret_cast<double*>(ws + L.G2);
   p.H1 = reinterpret_cast<double*>(ws + L.H1);

@@ -119,7 +119,7 @@ struct AdjPtrs {
   void* gW;                          // adjoints of the state: in, of the next state; out, of this one
   double* gB;
   double* gV;
-  double *gBh, *gVh, *gP, *glam, *glamh, *lamh, *G1, *G2, *H1, *H2, *part, *gS;  // scratch
+  double *gBh, *gVh, *gP, *glam, *glamh, *lamh, *q1, *q2, *G1, *G2, *H1, *H2, *part, *gS;  // scratch
   void* gX;                          // [M][F][T] accumulated
   int* status;
   void* Y;                           // [F][Mb][T] sweep scratch
