@@ -306,7 +306,7 @@ def adjoint_bench(args) -> int:
     """Differentiation workload: 32 mixtures of 6 s (N=2, M=3, STFT 1024/256: F=513, T=376, D=4
     stacked frames: Mbar=12, taps 6+6, K=10), 20 unrolled iterations, loss = mean squared error of
     the source images against the known synthetic images.  One step = forward and reverse pass
-    (ctfiss_backward) of all 32 mixtures, FP64, one context at a time.  Mixture 0's gradients are
+    (ctfiss_backward) of all 32 mixtures, FP64, one context per mixture, spread over --streams streams.  Mixture 0's gradients are
     checked against the FP64 PyTorch autograd reference on the host, which is also timed there as
     the CPU baseline."""
     import torch
@@ -326,17 +326,29 @@ def adjoint_bench(args) -> int:
         mixes.append((torch.from_numpy(m.X).to(dev), torch.from_numpy(B0).to(dev), torch.from_numpy(V0).to(dev),
                       torch.from_numpy(m.images).to(dev)))
 
+    # the mixtures are independent: round-robin over a few streams (default
+    # priority) so that their launches overlap; each backward runs on the
+    # stream of its forward
+    streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, args.streams))]
+
     def step(sample=None):
         out = None
+        cur = torch.cuda.current_stream(dev)
+        for st in streams:
+            st.wait_stream(cur)
         for i, (X, B0, V0, img) in enumerate(mixes if sample is None else mixes[:sample]):
-            Xg = X.clone().requires_grad_(True)
-            Bg = B0.clone().requires_grad_(True)
-            C = separate(Xg, Bg, V0, wl.D, wl.row_taps, wl.n_iter)
-            loss = ((C - img).abs() ** 2).mean()
-            loss.backward()
-            if i == 0:
-                out = (float(loss), Xg.grad, Bg.grad)
-        return out
+            st = streams[i % len(streams)]
+            with torch.cuda.stream(st):
+                Xg = X.clone().requires_grad_(True)
+                Bg = B0.clone().requires_grad_(True)
+                C = separate(Xg, Bg, V0, wl.D, wl.row_taps, wl.n_iter)
+                loss = ((C - img).abs() ** 2).mean()
+                loss.backward()
+                if i == 0:
+                    out = (loss, Xg.grad, Bg.grad)
+        for st in streams:
+            cur.wait_stream(st)
+        return (float(out[0]), out[1], out[2])
 
     for _ in range(args.warmup):
         step()
@@ -389,7 +401,7 @@ def adjoint_bench(args) -> int:
                                f"(Mbar=12, taps 6+6), K=10, 20 unrolled iterations, image MSE loss, gradients "
                                f"w.r.t. the mixture STFT and the initial bases",
                    "F": wl.F, "T": wl.T, "Mbar": wl.mbar, "K": wl.K, "iterations": wl.n_iter, "mixtures": nmix},
-        "forward_ms_per_step": dt_fwd * 1e3, "gradient_check": check, "cpu_baseline": cpu,
+        "forward_ms_per_step": dt_fwd * 1e3, "streams": len(streams), "gradient_check": check, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -406,6 +418,7 @@ def main() -> int:
     ap.add_argument("--batched", action="store_true",
                     help="time the batch of uneven mixtures instead of the single long mixture")
     ap.add_argument("--batch", type=int, default=256, help="mixtures in --batched mode")
+    ap.add_argument("--streams", type=int, default=8, help="c4: streams the mixtures are spread over")
     ap.add_argument("--workload", choices=["c1", "c3", "c4"], default="c1",
                     help="c3: the 60 s, Mbar = 64 mixture (team launches) instead of the 10 s, Mbar = 24 one; "
                          "c4: forward and reverse pass of 32 mixtures (gradients)")

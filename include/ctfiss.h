@@ -168,7 +168,11 @@ int ctfiss_backward(ctfiss_ctx* ctx, int32_t n_iter, const void* B0, const void*
  * *fault_code (nullable) receives the raw device code (0 = none). */
 int ctfiss_sync_status(ctfiss_ctx* ctx, int32_t* fault_code);
 
-/* Release the context (does not touch the workspace or any device buffer). */
+/* Release the context (does not touch the workspace or any device buffer).
+ * Does not wait for work already enqueued on the context's stream (unless
+ * profiling launches are pending): the workspace and the buffers the context
+ * used must stay allocated until that work has completed, e.g. freed in
+ * stream order or after a synchronisation. */
 int ctfiss_destroy(ctfiss_ctx* ctx);
 
 /* Static description of a status code. */

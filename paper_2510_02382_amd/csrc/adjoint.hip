@@ -19,6 +19,8 @@
 // in the same kernel.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -83,6 +85,13 @@ __device__ __forceinline__ double tapc(const RowMap& rm, int n, int s, int T) {
 __device__ __forceinline__ Cd xbar(const AdjArgs& a, int f, int c, int t) {
   const int d = c / a.M, m = c - d * a.M;
   return t - d >= 0 ? a.X[((size_t)m * a.F + f) * a.T + t - d] : Cd{0.0, 0.0};
+}
+
+// fn(integral_constant<int, R>) for R in the sequence, in order: every R is a
+// compile-time constant in fn's body.
+template <typename Fn, int... R>
+__device__ __forceinline__ void static_for(Fn&& fn, std::integer_sequence<int, R...>) {
+  (fn(std::integral_constant<int, R>{}), ...);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -570,6 +579,255 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
   }
 }
 
+// Register-column form of k_adj_iss for Mbar <= MB <= 12 and T <= 512: thread t
+// owns frame t and keeps that frame's column of the rows (y), of their
+// adjoints (gy), of the weight adjoints (gph) and of the weights (ph) in
+// registers, for every row; the row loops are unrolled over MB, so no register
+// array is indexed at run time.  Only the frame sums of each step cross
+// threads (wave sums, then LDS across waves).  The coefficients z and d_p of
+// the forward sweep stay in LDS.  Same arithmetic as k_adj_iss.
+template <int MB>
+__global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int f = blockIdx.x, tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  const int Mb = a.Mb, T = a.T, F = a.F, t = tid;
+  const bool own = t < T;
+  const double invT = 1.0 / T;
+  Cd* W = reinterpret_cast<Cd*>(smem);  // [Mb][Mb]
+  Cd* gWl = W + MB * MB;                // [Mb][Mb]
+  Cd* zt = gWl + MB * MB;               // [MB][MB] z of step r, [r][p]
+  Cd* ga = zt + MB * MB;                // [MB]
+  Cd* wr = ga + MB;                     // [MB]
+  double* dt = reinterpret_cast<double*>(wr + MB);  // [MB][MB]
+  double* gd = dt + MB * MB;                        // [MB]
+  double* red = gd + MB;                            // [nw][3 MB] partial frame sums
+  for (int i = tid; i < Mb * Mb; i += nt) {
+    const int r = i / Mb, c = i - r * Mb;
+    W[r * MB + c] = a.Wk[(size_t)f * Mb * Mb + i];
+  }
+  __syncthreads();
+  Cd y[MB], gy[MB];
+  double ph[MB], gph[MB];
+#pragma unroll
+  for (int p = 0; p < MB; ++p) {
+    Cd s{0.0, 0.0};
+    double w = 0.0;
+    if (p < Mb && own) {
+      for (int c = 0; c < Mb; ++c) s = cfma(W[p * MB + c], xbar(a, f, c, t), s);
+      const int l = a.rm.tap[p];
+      w = t >= l ? a.ilam[((size_t)a.rm.src[p] * F + f) * T + t - l] : 0.0;
+    }
+    y[p] = s;
+    ph[p] = w;
+    gph[p] = 0.0;
+  }
+  // frame sum v of this wave into its slot; then block_finish adds the waves' slots
+  auto wave_put = [&](int v, double x) {
+    const double s = group_sum<64>(x);  // DPP within rows of 16 lanes, two cross-row steps
+    if (lane == 0) red[wave * 3 * MB + v] = s;
+  };
+  auto block_finish = [&](int nv) {
+    __syncthreads();
+    if (tid < nv) {
+      double s = 0.0;
+      for (int w2 = 0; w2 < nw; ++w2) s += red[w2 * 3 * MB + tid];
+      red[tid] = s;  // wave 0's slot: every wave has read its partial above
+    }
+    __syncthreads();
+  };
+  // forward sweep: record z and d_p
+  auto fwd_step = [&](auto rc) {
+    constexpr int r = decltype(rc)::value;
+    if (r < Mb) {
+    const Cd yr = y[r];
+#pragma unroll
+    for (int p = 0; p < MB; ++p) {
+      if (p < Mb) {
+        const Cd q = cmulc(y[p], yr);
+        wave_put(3 * p, ph[p] * cabs2(yr));
+        wave_put(3 * p + 1, ph[p] * q.x);
+        wave_put(3 * p + 2, ph[p] * q.y);
+      }
+    }
+    if (tid < Mb) wr[tid] = W[r * MB + tid];
+    block_finish(3 * Mb);
+    if (tid < Mb) {
+      const int p = tid;
+      const double d = red[3 * p] * invT;
+      Cd z{red[3 * p + 1] * invT / d, red[3 * p + 2] * invT / d};
+      if (p == r) z = Cd{1.0 - 1.0 / sqrt(d), 0.0};
+      zt[r * MB + p] = z;
+      dt[r * MB + p] = d;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < MB; ++p) y[p] = cfms(zt[r * MB + p], yr, y[p]);
+    for (int e = tid; e < Mb * Mb; e += nt) {
+      const int p = e / Mb, c = e - p * Mb;
+      W[p * MB + c] = cfms(zt[r * MB + p], wr[c], W[p * MB + c]);
+    }
+    __syncthreads();
+    }
+  };
+  static_for(fwd_step, std::make_integer_sequence<int, MB>{});
+  // adjoint seeds
+  for (int i = tid; i < Mb * Mb; i += nt) {
+    const int r = i / Mb, c = i - r * Mb;
+    gWl[r * MB + c] = a.gW[(size_t)f * Mb * Mb + i];
+  }
+#pragma unroll
+  for (int p = 0; p < MB; ++p) {
+    double g = 0.0;
+    if (p < Mb && own) {
+      const int n = a.rm.src[p], l = a.rm.tap[p];
+      g = 2.0 * a.gS[p];
+      if (t >= l) g += 2.0 * a.gP[((size_t)n * F + f) * T + t - l];
+    }
+    gy[p] = cscale(y[p], g);
+  }
+  __syncthreads();
+  auto rev_step = [&](auto rc) {
+    constexpr int r = MB - 1 - decltype(rc)::value;
+    if (r < Mb) {
+    const double sc = 1.0 - zt[r * MB + r].x;
+    y[r] = cscale(y[r], 1.0 / sc);  // row r before the step
+    const Cd yr = y[r];
+    if (tid < Mb) wr[tid] = cscale(W[r * MB + tid], 1.0 / sc);
+#pragma unroll
+    for (int p = 0; p < MB; ++p) {
+      if (p < Mb) {
+        const Cd q = cmulc(gy[p], yr);
+        wave_put(2 * p, q.x);
+        wave_put(2 * p + 1, q.y);
+      }
+    }
+    block_finish(2 * Mb);  // also completes wr
+    if (tid < Mb) {
+      const int p = tid;
+      double gx = red[2 * p], gyv = red[2 * p + 1];
+      for (int c = 0; c < Mb; ++c) {
+        const Cd q = cmulc(gWl[p * MB + c], wr[c]);
+        gx += q.x;
+        gyv += q.y;
+      }
+      const Cd gz{-gx, -gyv};
+      const double d = dt[r * MB + p];
+      if (p == r) {
+        ga[p] = Cd{0.0, 0.0};
+        gd[p] = 0.5 * pow(d, -1.5) * gz.x;
+      } else {
+        const Cd z = zt[r * MB + p];
+        ga[p] = cscale(gz, 1.0 / d);
+        gd[p] = -(z.x * gz.x + z.y * gz.y) / d;
+      }
+    }
+    __syncthreads();
+    {
+      const double y2 = cabs2(yr);
+      Cd gyr = cscale(gy[r], sc);
+#pragma unroll
+      for (int p = 0; p < MB; ++p) {
+        if (p >= Mb) continue;
+        const double phs = ph[p] * invT;
+        gyr = cfma(cscale(yr, 2.0 * phs), Cd{gd[p], 0.0}, gyr);
+        gph[p] += y2 * gd[p] * invT;
+        if (p == r) continue;
+        const Cd z = zt[r * MB + p];
+        gyr = cfms(cconj(z), gy[p], gyr);
+        const Cd yp = cfma(z, yr, y[p]);
+        y[p] = yp;
+        gyr = cfma(cscale(yp, phs), cconj(ga[p]), gyr);
+        gy[p] = cfma(cscale(yr, phs), ga[p], gy[p]);
+        gph[p] += cmul(cconj(yp), cmul(yr, ga[p])).x * invT;
+      }
+      gy[r] = gyr;
+    }
+    if (tid < Mb) {
+      const int c = tid;
+      Cd g = cscale(gWl[r * MB + c], sc);
+      for (int p = 0; p < Mb; ++p) {
+        if (p == r) continue;
+        g = cfms(cconj(zt[r * MB + p]), gWl[p * MB + c], g);
+        W[p * MB + c] = cfma(zt[r * MB + p], wr[c], W[p * MB + c]);
+      }
+      gWl[r * MB + c] = g;
+      W[r * MB + c] = wr[c];
+    }
+    __syncthreads();
+    }
+  };
+  static_for(rev_step, std::make_integer_sequence<int, MB>{});
+  // columns and the row adjoint of W to memory; the steps that mix frames
+  // (demix and lambda adjoints) run as separate launches
+  Cd* gY = a.gY + (size_t)f * Mb * T;
+  double* gphi = a.gphi + (size_t)f * Mb * T;
+  if (own) {
+#pragma unroll
+    for (int p = 0; p < MB; ++p)
+      if (p < Mb) {
+        gY[p * T + t] = gy[p];
+        gphi[p * T + t] = gph[p];
+      }
+  }
+  for (int i = tid; i < Mb * Mb; i += nt) {
+    const int r = i / Mb, c = i - r * Mb;
+    a.gW[(size_t)f * Mb * Mb + i] = gWl[r * MB + c];
+  }
+}
+
+// One wave per (f, r, c), lanes over frames: gW[f][r][c] += sum_t gY[r][t] conj(xbar_c[t]).
+__global__ void __launch_bounds__(256) k_adj_demix_w(AdjArgs a) {
+  const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int Mb = a.Mb, T = a.T;
+  if (i >= (size_t)a.F * Mb * Mb) return;
+  const int c = (int)(i % Mb), r = (int)((i / Mb) % Mb), f = (int)(i / ((size_t)Mb * Mb));
+  const Cd* g = a.gY + ((size_t)f * Mb + r) * T;
+  double sx = 0.0, sy = 0.0;
+  for (int t = lane; t < T; t += 64) {
+    const Cd q = cmulc(g[t], xbar(a, f, c, t));
+    sx += q.x;
+    sy += q.y;
+  }
+  sx = group_sum<64>(sx);
+  sy = group_sum<64>(sy);
+  if (lane == 0) a.gW[i] = cadd(a.gW[i], Cd{sx, sy});
+}
+
+// Per (m, f, t): gX[m][f][t] += sum_d sum_r conj(Wk[r][d M + m]) gY[r][t + d].
+__global__ void __launch_bounds__(256) k_adj_demix_x(AdjArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int Mb = a.Mb, T = a.T, F = a.F;
+  if (i >= (size_t)a.M * F * T) return;
+  const int t = (int)(i % T), f = (int)((i / T) % F), m = (int)(i / ((size_t)F * T));
+  const Cd* Wk = a.Wk + (size_t)f * Mb * Mb;
+  const Cd* g = a.gY + (size_t)f * Mb * T;
+  Cd s{0.0, 0.0};
+  for (int d = 0; d < a.D && t + d < T; ++d)
+    for (int r = 0; r < Mb; ++r) s = cfma(cconj(Wk[r * Mb + d * a.M + m]), g[r * T + t + d], s);
+  a.gX[i] = cadd(a.gX[i], s);
+}
+
+// Per (n, f, s): glam[n][f][s] -= sum_l gphi_(n,l)[s + l] / lam^2 (phi = 1 / lambda).
+__global__ void __launch_bounds__(256) k_adj_phi(AdjArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int T = a.T, F = a.F;
+  if (i >= (size_t)a.N * F * T) return;
+  const int sv = (int)(i % T), f = (int)((i / T) % F), n = (int)(i / ((size_t)F * T));
+  const double* gp = a.gphi + (size_t)f * a.Mb * T;
+  const double il = a.ilam[i];
+  double g = 0.0;
+  for (int l = 0; l < a.rm.L[n] && sv + l < T; ++l) g += gp[(a.rm.r0[n] + l) * T + sv + l];
+  a.glam[i] -= g * il * il;
+}
+
+// Row bound of the register-column instance for Mbar (0: none; beyond 12 rows
+// the columns no longer fit 256 VGPRs).
+int adj_reg_rows(int Mb) { return Mb <= 4 ? 4 : Mb <= 8 ? 8 : Mb <= 12 ? 12 : 0; }
+size_t adj_reg_lds(int MB, int nthr) {
+  return (size_t)(3 * MB * MB + 2 * MB) * 16 + (size_t)(MB * MB + MB) * 8 + (size_t)(nthr / 64) * 3 * MB * 8;
+}
+
 // ------------------------------------------------------------------ lambda
 // One wave per (n, f, k), lanes over s: gB += sum_s glam Vk.
 __global__ void __launch_bounds__(256) k_adj_l1(AdjArgs a) {
@@ -691,12 +949,24 @@ hipError_t adj_iteration(const AdjPtrs& p, const Dims& d, double floor, hipStrea
   hipLaunchKernelGGL(k_adj_v2, blocks(nft), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_adj_b1, blocks(nfk * 64), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_adj_b2, blocks(nft), dim3(256), 0, s, a);
-  const size_t lds = adj_iss_lds(d.Mb, d.T);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_adj_iss, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+  const int MB = adj_reg_rows(d.Mb);
+  if (MB > 0 && d.T <= 512) {  // register columns: one thread per frame
+    const int nthr = (d.T + 63) / 64 * 64;
+    const size_t lds = adj_reg_lds(MB, nthr);
+    if (MB == 4) hipLaunchKernelGGL(k_adj_iss_reg<4>, dim3(d.F), dim3(nthr), lds, s, a);
+    if (MB == 8) hipLaunchKernelGGL(k_adj_iss_reg<8>, dim3(d.F), dim3(nthr), lds, s, a);
+    if (MB == 12) hipLaunchKernelGGL(k_adj_iss_reg<12>, dim3(d.F), dim3(nthr), lds, s, a);
+    hipLaunchKernelGGL(k_adj_demix_w, blocks((size_t)d.F * d.Mb * d.Mb * 64), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_adj_demix_x, blocks((size_t)d.M * d.F * d.T), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_adj_phi, blocks(nft), dim3(256), 0, s, a);
+  } else {
+    const size_t lds = adj_iss_lds(d.Mb, d.T);
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_adj_iss, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_adj_iss, dim3(d.F), dim3(256), lds, s, a);
   }
-  hipLaunchKernelGGL(k_adj_iss, dim3(d.F), dim3(256), lds, s, a);
   hipLaunchKernelGGL(k_adj_l1, blocks(nfk * 64), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_adj_l2, blocks(nkt * 64), dim3(256), 0, s, a);
   return hipGetLastError();

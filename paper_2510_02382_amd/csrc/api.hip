@@ -540,7 +540,9 @@ int ctfiss_sync_status(ctfiss_ctx* c, int32_t* fault_code) {
 
 int ctfiss_destroy(ctfiss_ctx* c) {
   if (!c) return CTFISS_E_ARG;
-  (void)hipStreamSynchronize(c->stream);
+  // enqueued work keeps running (kernels hold no pointer to the context);
+  // only pending timing events are waited for
+  if (!c->timed.empty()) (void)hipStreamSynchronize(c->stream);
   for (const TimedLaunch& t : c->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
