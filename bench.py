@@ -407,6 +407,63 @@ def adjoint_bench(args) -> int:
     return 0
 
 
+def small_bench(args) -> int:
+    """The paper's experimental shape (Sec. V-A, Table I): 8 s at 16 kHz, N=2, M = 4/6/8 microphones,
+    no frame stacking (Mbar = M, L_n = M / 2), STFT 1024/256 (F=513, T=501), K=3, 100 iterations.  At
+    these sizes an iteration is a few tens of microseconds of kernels, so launches matter: the FP32
+    ISS path is timed eagerly and with graph replay (ctfiss_set_graph)."""
+    import torch
+
+    from datagen import WORKLOADS, init_nmf, make_mixture
+    from paper_2510_02382_amd import Separator
+
+    wl = WORKLOADS[args.workload]
+    log(f"workload {wl.name}: F={wl.F} T={wl.T} M={wl.M} Mbar={wl.mbar} taps={wl.row_taps} K={wl.K} "
+        f"iters={wl.n_iter}")
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(make_mixture(wl, 0).X).to(dev).to(torch.complex64)
+    B0n, V0n = init_nmf(wl.N, wl.F, wl.K, wl.T, 0)
+    B0 = torch.from_numpy(B0n).to(dev).float()
+    V0 = torch.from_numpy(V0n).to(dev).float()
+    stream = torch.cuda.Stream(device=dev)
+    res = {}
+    for graph in (False, True):
+        with torch.cuda.stream(stream):
+            sep = Separator(wl.F, wl.T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision="fp32", stream=stream)
+            if graph:
+                sep.set_graph(True)
+            sep.set_input(X)
+            for _ in range(args.warmup + 1):
+                sep.set_state(B=B0, V=V0)
+                sep.iterate(wl.n_iter)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                sep.set_state(B=B0, V=V0)
+                sep.iterate(wl.n_iter)
+                C = sep.source_images()
+            stream.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            res["graph" if graph else "eager"] = {"ms_per_step": dt * 1e3, "status": sep.status(), "C": C}
+            sep.close()
+        log(f"{'graph' if graph else 'eager'}: {dt * 1e3:.3f} ms per separation ({wl.n_iter} iterations)")
+    same = bool(torch.equal(res["eager"]["C"], res["graph"]["C"]))
+    units = wl.F * wl.T * wl.n_iter
+    out = {
+        "metric": "F·T·iters/s ISS vs IP vs FP64-ISS at rel err ≤1e-4; HBM GB/s fraction",
+        "value": units / (res["graph"]["ms_per_step"] * 1e-3), "unit": "F·T·iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["graph"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"paper shape {wl.name}: 8 s, N=2, M={wl.M}, no frame stacking (Mbar={wl.mbar}), "
+                               f"STFT 1024/256, K={wl.K}, {wl.n_iter} iterations, graph replay",
+                   "F": wl.F, "T": wl.T, "Mbar": wl.mbar, "K": wl.K, "iterations": wl.n_iter},
+        "eager_ms_per_step": res["eager"]["ms_per_step"], "graph_equals_eager": same,
+        "status": res["graph"]["status"], "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,9 +476,10 @@ def main() -> int:
                     help="time the batch of uneven mixtures instead of the single long mixture")
     ap.add_argument("--batch", type=int, default=256, help="mixtures in --batched mode")
     ap.add_argument("--streams", type=int, default=8, help="c4: streams the mixtures are spread over")
-    ap.add_argument("--workload", choices=["c1", "c3", "c4"], default="c1",
+    ap.add_argument("--workload", choices=["c1", "c3", "c4", "P4", "P6", "P8"], default="c1",
                     help="c3: the 60 s, Mbar = 64 mixture (team launches) instead of the 10 s, Mbar = 24 one; "
-                         "c4: forward and reverse pass of 32 mixtures (gradients)")
+                         "c4: forward and reverse pass of 32 mixtures (gradients); P4/P6/P8: the paper's "
+                         "shapes, eager and graph replay")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -439,6 +497,8 @@ def main() -> int:
         return precision_bench(args)
     if args.workload == "c4":
         return adjoint_bench(args)
+    if args.workload in ("P4", "P6", "P8"):
+        return small_bench(args)
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4

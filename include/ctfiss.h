@@ -129,6 +129,16 @@ int ctfiss_set_state(ctfiss_ctx* ctx, const void* W, const void* B, const void* 
  * normalisation of Eqs. (19)-(21).  Requires set_input and set_state. */
 int ctfiss_iterate(ctfiss_ctx* ctx, int32_t n_iter);
 
+/* Graph mode (enable != 0): ctfiss_iterate captures the launches of an
+ * n_iter-iteration call once into a HIP graph (one per n_iter and per
+ * whether the carried Y is valid at the start, up to 8 kept) and replays it
+ * on later calls; the results are those of the launches it was captured from.
+ * Useful where launches dominate (small bins, few frames).  Not with profiling
+ * (such calls run eagerly), not for contexts on the NULL stream or with team
+ * launches (CTFISS_E_UNSUPPORTED).  Disabling synchronises the stream and
+ * frees the graphs. */
+int ctfiss_set_graph(ctfiss_ctx* ctx, int enable);
+
 /* Copy the current state out (device-to-device on the context's stream).
  * Any of W, B, V may be NULL to skip it. */
 int ctfiss_get_state(ctfiss_ctx* ctx, void* W, void* B, void* V);

@@ -33,7 +33,7 @@ EXPORTS = (
     "ctfiss_status_string", "ctfiss_set_profiling", "ctfiss_kernel_stats",
     "ctfiss_batch_workspace_size", "ctfiss_batch_create", "ctfiss_batch_set_input", "ctfiss_batch_set_state",
     "ctfiss_batch_iterate", "ctfiss_batch_source_images", "ctfiss_batch_sync_status", "ctfiss_batch_destroy",
-    "ctfiss_adjoint_workspace_size", "ctfiss_backward",
+    "ctfiss_adjoint_workspace_size", "ctfiss_backward", "ctfiss_set_graph",
 )
 
 
@@ -79,6 +79,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "ctfiss_batch_destroy": ([vp], i32),
         "ctfiss_adjoint_workspace_size": ([ctypes.POINTER(Shape), i32, ctypes.POINTER(sz)], i32),
         "ctfiss_backward": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, sz], i32),
+        "ctfiss_set_graph": ([vp, i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -179,6 +180,10 @@ def ctfiss_kernel_stats(ctx, which: int) -> tuple[int, float]:
     ms = ctypes.c_double(0.0)
     _check(_lib.ctfiss_kernel_stats(ctx, int(which), ctypes.byref(n), ctypes.byref(ms)), "ctfiss_kernel_stats")
     return int(n.value), float(ms.value)
+
+
+def ctfiss_set_graph(ctx, enable: bool) -> None:
+    _check(_lib.ctfiss_set_graph(ctx, 1 if enable else 0), "ctfiss_set_graph")
 
 
 def ctfiss_adjoint_workspace_size(shape: Shape, n_iter: int) -> int:

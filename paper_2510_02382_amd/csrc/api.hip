@@ -279,6 +279,13 @@ struct ctfiss_ctx {
   bool have_input, have_state;
   bool y_valid;  // the carried Y holds W xbar of the current W (ISS)
   unsigned epoch;  // tag base of the last team launch's exchange words
+  bool graph;      // ctfiss_iterate replays captured HIP graphs
+  struct GraphEntry {
+    int n;
+    bool y_valid;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
   int prof;  // bit mask of timed kernel classes
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> pool;
@@ -287,6 +294,11 @@ struct ctfiss_ctx {
 };
 
 namespace {
+
+void drop_graphs(ctfiss_ctx* c) {
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
 
 hipError_t ev_get(ctfiss_ctx* c, hipEvent_t* e) {
   if (!c->pool.empty()) {
@@ -405,6 +417,7 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   c->ptr.xch = plan.team > 1 ? static_cast<void*>(c->ws + lay.xch) : nullptr;
   c->have_input = c->have_state = c->y_valid = false;
   c->epoch = 0;
+  c->graph = false;
   c->prof = 0;
   for (int i = 0; i < kClasses; ++i) {
     c->launches[i] = 0;
@@ -425,6 +438,10 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
 
 int ctfiss_set_input(ctfiss_ctx* c, const void* X) {
   if (!c || !X) return CTFISS_E_ARG;
+  if (X != c->ptr.X && !c->graphs.empty()) {  // captured launches hold the old pointer
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return CTFISS_E_HIP;
+    drop_graphs(c);
+  }
   c->ptr.X = X;
   c->have_input = true;
   c->y_valid = false;
@@ -451,9 +468,13 @@ int ctfiss_set_state(ctfiss_ctx* c, const void* W, const void* B, const void* V)
   return CTFISS_OK;
 }
 
-int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
-  if (!c || n_iter < 0) return CTFISS_E_ARG;
-  if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
+}  // extern "C"
+
+namespace {
+
+// The launches of n_iter iterations on the context's stream (updates the
+// host-side state as the launches will leave the device state).
+int enqueue_iterations(ctfiss_ctx* c, int32_t n_iter) {
   const bool tap0 = c->vrule == CTFISS_VRULE_PAPER_TAP0;
   const bool f32 = c->prec != CTFISS_FP64;
   const Dims& d = c->d;
@@ -487,6 +508,57 @@ int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
     hipError_t e = timed(c, 3, [&] { return f32 ? apply_mu_t<float>(d, p, sy, s) : apply_mu_t<double>(d, p, sy, s); });
     if (e != hipSuccess) return CTFISS_E_HIP;
   }
+  return CTFISS_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
+  if (!c || n_iter < 0) return CTFISS_E_ARG;
+  if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
+  if (!c->graph || n_iter == 0 || c->prof != 0) return enqueue_iterations(c, n_iter);
+  // graph mode: one captured graph per (n_iter, carried Y valid at the start);
+  // every argument of the launches is fixed per context, so a replay is the
+  // same work as the launches it was captured from
+  const bool yv = c->y_valid;
+  for (auto& g : c->graphs) {
+    if (g.n == n_iter && g.y_valid == yv) {
+      if (hipGraphLaunch(g.exec, c->stream) != hipSuccess) return CTFISS_E_HIP;
+      if (c->rule == CTFISS_RULE_ISS) c->y_valid = true;
+      return CTFISS_OK;
+    }
+  }
+  if (c->graphs.size() >= 8) drop_graphs(c);
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return CTFISS_E_HIP;
+  const int st = enqueue_iterations(c, n_iter);
+  const hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+  if (st != CTFISS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ee != hipSuccess || !graph) return CTFISS_E_HIP;
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return CTFISS_E_HIP;
+  c->graphs.push_back({n_iter, yv, exec});
+  return hipGraphLaunch(exec, c->stream) == hipSuccess ? CTFISS_OK : CTFISS_E_HIP;
+}
+
+int ctfiss_set_graph(ctfiss_ctx* c, int enable) {
+  if (!c) return CTFISS_E_ARG;
+  if (enable) {
+    // team launches take a new tag base per launch; capture needs a created stream
+    if (c->plan.team > 1 || c->stream == nullptr) return CTFISS_E_UNSUPPORTED;
+  } else if (!c->graphs.empty()) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return CTFISS_E_HIP;
+    drop_graphs(c);
+  }
+  c->graph = enable != 0;
   return CTFISS_OK;
 }
 
@@ -541,8 +613,9 @@ int ctfiss_sync_status(ctfiss_ctx* c, int32_t* fault_code) {
 int ctfiss_destroy(ctfiss_ctx* c) {
   if (!c) return CTFISS_E_ARG;
   // enqueued work keeps running (kernels hold no pointer to the context);
-  // only pending timing events are waited for
-  if (!c->timed.empty()) (void)hipStreamSynchronize(c->stream);
+  // only pending timing events and captured graphs are waited for
+  if (!c->timed.empty() || !c->graphs.empty()) (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
   for (const TimedLaunch& t : c->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);

@@ -59,6 +59,10 @@ class Separator:
     def iterate(self, n_iter: int) -> None:
         b.ctfiss_iterate(self.ctx, n_iter)
 
+    def set_graph(self, enable: bool = True) -> None:
+        """Replay captured HIP graphs for iterate() (ctfiss_set_graph); needs a non-NULL stream."""
+        b.ctfiss_set_graph(self.ctx, enable)
+
     def state(self):
         W = torch.empty((self.F, self.Mbar, self.Mbar), dtype=self.cdtype, device=self.device)
         B = torch.empty((self.N, self.F, self.K), dtype=self.rdtype, device=self.device)
