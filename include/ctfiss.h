@@ -139,6 +139,26 @@ int ctfiss_iterate(ctfiss_ctx* ctx, int32_t n_iter);
  * frees the graphs. */
 int ctfiss_set_graph(ctfiss_ctx* ctx, int enable);
 
+/* Launch shape of the context's W update: lanes per row group (G), frames per
+ * lane (cpl), rows per group (rpl) and workgroups per bin (team, 1 = one). */
+int ctfiss_get_plan(ctfiss_ctx* ctx, int32_t* G, int32_t* cpl, int32_t* rpl, int32_t* team);
+
+/* Measured choice of the W update's launch shape: every instantiated shape that
+ * fits the context's shape (team shapes where the default plan is a team plan)
+ * runs the W update `trials` times on the context's input and state (after
+ * one warm-up run), timed with events; the fastest becomes the context's plan
+ * and is cached for the process, per (precision, rule, Mbar, M, D, N, largest
+ * tap count, T rounded up to 32), so that contexts created later for such a
+ * shape start with it (CTFISS_PLAN in the environment still overrides).  The
+ * state is restored afterwards and the status word cleared.  Synchronises;
+ * allocates a state-sized stream-ordered buffer for the duration of the call.
+ * Not in graph mode (CTFISS_E_UNSUPPORTED). */
+int ctfiss_autotune(ctfiss_ctx* ctx, int32_t trials);
+
+/* Forget every plan ctfiss_autotune cached (contexts created afterwards take
+ * the built-in rule again; existing contexts keep their plans). */
+int ctfiss_clear_tuned_plans(void);
+
 /* Copy the current state out (device-to-device on the context's stream).
  * Any of W, B, V may be NULL to skip it. */
 int ctfiss_get_state(ctfiss_ctx* ctx, void* W, void* B, void* V);

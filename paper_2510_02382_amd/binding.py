@@ -33,7 +33,8 @@ EXPORTS = (
     "ctfiss_status_string", "ctfiss_set_profiling", "ctfiss_kernel_stats",
     "ctfiss_batch_workspace_size", "ctfiss_batch_create", "ctfiss_batch_set_input", "ctfiss_batch_set_state",
     "ctfiss_batch_iterate", "ctfiss_batch_source_images", "ctfiss_batch_sync_status", "ctfiss_batch_destroy",
-    "ctfiss_adjoint_workspace_size", "ctfiss_backward", "ctfiss_set_graph",
+    "ctfiss_adjoint_workspace_size", "ctfiss_backward", "ctfiss_set_graph", "ctfiss_get_plan", "ctfiss_autotune",
+    "ctfiss_clear_tuned_plans",
 )
 
 
@@ -80,6 +81,10 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "ctfiss_adjoint_workspace_size": ([ctypes.POINTER(Shape), i32, ctypes.POINTER(sz)], i32),
         "ctfiss_backward": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, sz], i32),
         "ctfiss_set_graph": ([vp, i32], i32),
+        "ctfiss_get_plan": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+                            i32),
+        "ctfiss_autotune": ([vp, i32], i32),
+        "ctfiss_clear_tuned_plans": ([], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -180,6 +185,20 @@ def ctfiss_kernel_stats(ctx, which: int) -> tuple[int, float]:
     ms = ctypes.c_double(0.0)
     _check(_lib.ctfiss_kernel_stats(ctx, int(which), ctypes.byref(n), ctypes.byref(ms)), "ctfiss_kernel_stats")
     return int(n.value), float(ms.value)
+
+
+def ctfiss_get_plan(ctx) -> tuple[int, int, int, int]:
+    v = [ctypes.c_int32(0) for _ in range(4)]
+    _check(_lib.ctfiss_get_plan(ctx, *[ctypes.byref(x) for x in v]), "ctfiss_get_plan")
+    return tuple(int(x.value) for x in v)
+
+
+def ctfiss_autotune(ctx, trials: int) -> None:
+    _check(_lib.ctfiss_autotune(ctx, int(trials)), "ctfiss_autotune")
+
+
+def ctfiss_clear_tuned_plans() -> None:
+    _check(_lib.ctfiss_clear_tuned_plans(), "ctfiss_clear_tuned_plans")
 
 
 def ctfiss_set_graph(ctx, enable: bool) -> None:

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -93,7 +94,52 @@ constexpr GR kTeam32[] = {{16, 1}, {16, 2}, {32, 2}};
 constexpr GR kTeam64[] = {{16, 1}, {16, 2}};
 }  // namespace
 
+// Plans measured by ctfiss_autotune, per (precision, rule, Mbar, M, D, N, Lmax,
+// T rounded up to a multiple of 32): later contexts of such a shape take them.
+namespace {
+struct TuneKey {
+  int prec, rule, Mb, M, D, N, lmax, tb;
+  bool operator==(const TuneKey& o) const {
+    return prec == o.prec && rule == o.rule && Mb == o.Mb && M == o.M && D == o.D && N == o.N && lmax == o.lmax &&
+           tb == o.tb;
+  }
+};
+struct TuneEntry {
+  TuneKey key;
+  Plan plan;
+};
+std::vector<TuneEntry>& tune_cache() {
+  static std::vector<TuneEntry> cache;
+  return cache;
+}
+std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+TuneKey tune_key(int prec, int rule, const Dims& d) {
+  return TuneKey{prec, rule, d.Mb, d.M, d.D, d.N, d.lmax, (d.T + 31) / 32 * 32};
+}
+}  // namespace
+
+bool tuned_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
+  const TuneKey k = tune_key(prec, rule, d);
+  std::lock_guard<std::mutex> lock(tune_mutex());
+  for (const auto& e : tune_cache()) {
+    if (!(e.key == k)) continue;
+    // re-derive for this T (the bucket may hold a slightly shorter signal)
+    Plan p;
+    if (e.plan.team > 1) {
+      if (plan_for_team(prec, d, max_lds, e.plan.G, e.plan.RPL, e.plan.team, 0, &p)) { *out = p; return true; }
+    } else if (plan_for(prec, rule, d, max_lds, e.plan.G, e.plan.RPL, 0, &p)) {
+      *out = p;
+      return true;
+    }
+  }
+  return false;
+}
+
 bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
+  if (tuned_plan(prec, rule, d, max_lds, out)) return true;
   const GR* list;
   int n;
   const bool f32 = prec != CTFISS_FP64;
@@ -414,7 +460,7 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   c->ptr.status = reinterpret_cast<int*>(c->ws + lay.status);
   c->ptr.work = reinterpret_cast<int*>(c->ws + lay.work);
   c->ptr.Y = c->ws + lay.Y;
-  c->ptr.xch = plan.team > 1 ? static_cast<void*>(c->ws + lay.xch) : nullptr;
+  c->ptr.xch = lay.team > 1 ? static_cast<void*>(c->ws + lay.xch) : nullptr;
   c->have_input = c->have_state = c->y_valid = false;
   c->epoch = 0;
   c->graph = false;
@@ -426,7 +472,7 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   hipError_t ze = launch_zero_status(c->ptr.status, c->stream);
   // exchange words start untagged (every launch's tags are nonzero)
   if (ze == hipSuccess && c->ptr.xch)
-    ze = hipMemsetAsync(c->ptr.xch, 0, (size_t)d.F * team_words(d.Mb, d.lmax, plan.team, precision != CTFISS_FP64 ? 4 : 8) * 8,
+    ze = hipMemsetAsync(c->ptr.xch, 0, (size_t)d.F * team_words(d.Mb, d.lmax, lay.team, precision != CTFISS_FP64 ? 4 : 8) * 8,
                         c->stream);
   if (ze != hipSuccess) {
     delete c;
@@ -802,6 +848,119 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
   if (e == hipSuccess) e = cp(c->ptr.V, ws + L.ckV + n_iter * vb, vb);
   c->y_valid = false;
   return e == hipSuccess ? CTFISS_OK : CTFISS_E_HIP;
+}
+
+int ctfiss_get_plan(ctfiss_ctx* c, int32_t* G, int32_t* cpl, int32_t* rpl, int32_t* team) {
+  if (!c) return CTFISS_E_ARG;
+  if (G) *G = c->plan.G;
+  if (cpl) *cpl = c->plan.CPL;
+  if (rpl) *rpl = c->plan.RPL;
+  if (team) *team = c->plan.team;
+  return CTFISS_OK;
+}
+
+int ctfiss_clear_tuned_plans(void) {
+  std::lock_guard<std::mutex> lock(tune_mutex());
+  tune_cache().clear();
+  return CTFISS_OK;
+}
+
+int ctfiss_autotune(ctfiss_ctx* c, int32_t trials) {
+  if (!c || trials < 1) return CTFISS_E_ARG;
+  if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
+  if (c->graph) return CTFISS_E_UNSUPPORTED;  // captured graphs hold the current plan
+  const Dims& d = c->d;
+  int dev = 0, max_lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return CTFISS_E_HIP;
+  // candidates: every instantiated (G, RPL) with its smallest fitting frames per lane; team
+  // shapes only where the default plan is a team plan (the workspace holds their exchange words)
+  std::vector<Plan> cand;
+  const int Gs[] = {16, 32, 64};
+  for (int G : Gs)
+    for (int rpl = 1; rpl <= 2; ++rpl) {
+      Plan p;
+      if (c->plan.team > 1) {
+        for (int P = 2; P <= c->lay.team; ++P)
+          if (plan_for_team(c->prec, d, (size_t)max_lds, G, rpl, P, 0, &p)) cand.push_back(p);
+      } else if (plan_for(c->prec, c->rule, d, (size_t)max_lds, G, rpl, 0, &p)) {
+        cand.push_back(p);
+      }
+    }
+  if (cand.empty()) return CTFISS_OK;
+  // time the W update on the context's own data; the state is restored afterwards
+  const size_t rs = c->prec != CTFISS_FP64 ? 4 : 8;
+  const size_t wb = (size_t)d.F * d.Mb * d.Mb * 2 * rs, bb = (size_t)d.N * d.F * d.K * rs, vb = (size_t)d.N * d.K * d.T * rs;
+  char* save = nullptr;
+  if (hipMallocAsync(reinterpret_cast<void**>(&save), wb + bb + vb, c->stream) != hipSuccess) return CTFISS_E_HIP;
+  hipError_t e = hipMemcpyAsync(save, c->ptr.W, wb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(save + wb, c->ptr.B, bb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(save + wb + bb, c->ptr.V, vb, hipMemcpyDeviceToDevice, c->stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  const Plan keep = c->plan;
+  Plan best = keep;
+  float best_ms = -1.f;
+  const bool f32 = c->prec != CTFISS_FP64;
+  for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+    Plan p = cand[i];
+    p.blocks = c->prec == CTFISS_MIXED ? resident_wblocks<float, true>(c->rule, p, d)
+               : f32                   ? resident_wblocks<float>(c->rule, p, d)
+                                       : resident_wblocks<double>(c->rule, p, d);
+    if (p.blocks < 1) continue;
+    float total = 0.f;
+    for (int t = 0; t <= trials && e == hipSuccess; ++t) {  // the first run warms up
+      e = f32 ? lambda_t<float>(d, c->ptr, false, c->stream) : lambda_t<double>(d, c->ptr, false, c->stream);
+      c->epoch = c->epoch % 0x1FFFFFFu + 1u;
+      if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+      if (e == hipSuccess) {
+        if (c->prec == CTFISS_MIXED)
+          e = wupdate_t<float, true>(c->rule, p, d, c->ptr, false, false, c->epoch, c->stream);
+        else if (f32)
+          e = wupdate_t<float>(c->rule, p, d, c->ptr, false, false, c->epoch, c->stream);
+        else
+          e = wupdate_t<double>(c->rule, p, d, c->ptr, false, false, c->epoch, c->stream);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (t > 0) total += ms;
+      // back to the saved state for the next run
+      if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.W, save, wb, hipMemcpyDeviceToDevice, c->stream);
+    }
+    if (e == hipSuccess && (best_ms < 0.f || total < best_ms)) {
+      best_ms = total;
+      best = p;
+    }
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.W, save, wb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.B, save + wb, bb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.V, save + wb + bb, vb, hipMemcpyDeviceToDevice, c->stream);
+  (void)hipFreeAsync(save, c->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  c->y_valid = false;
+  (void)launch_zero_status(c->ptr.status, c->stream);
+  if (e != hipSuccess) {
+    c->plan = keep;
+    return CTFISS_E_HIP;
+  }
+  c->plan = best;
+  {
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    const TuneKey k = tune_key(c->prec, c->rule, d);
+    bool found = false;
+    for (auto& te : tune_cache())
+      if (te.key == k) {
+        te.plan = best;
+        found = true;
+      }
+    if (!found) tune_cache().push_back({k, best});
+  }
+  return CTFISS_OK;
 }
 
 int ctfiss_set_profiling(ctfiss_ctx* c, int mask) {

@@ -59,6 +59,16 @@ class Separator:
     def iterate(self, n_iter: int) -> None:
         b.ctfiss_iterate(self.ctx, n_iter)
 
+    def plan(self):
+        """(G, frames per lane, rows per group, workgroups per bin) of the W update."""
+        return b.ctfiss_get_plan(self.ctx)
+
+    def autotune(self, trials: int = 3):
+        """Time every fitting launch shape of the W update on this context's data and keep the
+        fastest (ctfiss_autotune; cached for later contexts of the shape).  Returns plan()."""
+        b.ctfiss_autotune(self.ctx, trials)
+        return self.plan()
+
     def set_graph(self, enable: bool = True) -> None:
         """Replay captured HIP graphs for iterate() (ctfiss_set_graph); needs a non-NULL stream."""
         b.ctfiss_set_graph(self.ctx, enable)
