@@ -25,8 +25,12 @@ CASES = {
     "uneven_taps": (4, 41, 2, 3, (4, 2), 2, 4),
     "three_sources": (3, 50, 3, 1, (1, 1, 1), 3, 3),
     "c4_slice": (6, 375, 3, 4, (6, 6), 10, 20),
+    # beyond the register-column sweep adjoint (Mbar <= 12, T <= 512): the per-bin scratch forms
+    "rows16_lds": (2, 40, 4, 4, (8, 8), 2, 2),         # Mbar = 16, adjoints in LDS
+    "long_T_global": (2, 600, 2, 2, (2, 2), 2, 2),     # T = 600, adjoints in global scratch
 }
-TOL = {"small": 1e-8, "uneven_taps": 1e-8, "three_sources": 1e-8, "c4_slice": 1e-6}
+TOL = {"small": 1e-8, "uneven_taps": 1e-8, "three_sources": 1e-8, "c4_slice": 1e-6, "rows16_lds": 1e-8,
+       "long_T_global": 1e-8}
 
 
 def rel(a, b):
