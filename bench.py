@@ -336,9 +336,10 @@ def adjoint_bench(args) -> int:
     """Differentiation workload: 32 mixtures of 6 s (N=2, M=3, STFT 1024/256: F=513, T=376, D=4
     stacked frames: Mbar=12, taps 6+6, K=10), 20 unrolled iterations, loss = mean squared error of
     the source images against the known synthetic images.  One step = forward and reverse pass
-    (ctfiss_backward) of all 32 mixtures, FP64, one context per mixture, spread over --streams streams.  Mixture 0's gradients are
-    checked against the FP64 PyTorch autograd reference on the host, which is also timed there as
-    the CPU baseline."""
+    (ctfiss_backward) of all 32 mixtures, one context per mixture, spread over --streams streams,
+    in complex64 (value) and in FP64 (alongside).  Mixture 0's gradients of both are checked
+    against the FP64 PyTorch autograd reference on the host, which is also timed there as the
+    CPU baseline."""
     import torch
 
     from datagen import WORKLOADS, init_nmf, make_mixture
@@ -361,12 +362,16 @@ def adjoint_bench(args) -> int:
     # stream of its forward
     streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, args.streams))]
 
-    def step(sample=None):
+    # the inputs in each precision, resident before timing
+    typed = {cd: [(X.to(cd), B0.to(rd), V0.to(rd), img.to(cd)) for X, B0, V0, img in mixes]
+             for cd, rd in ((torch.complex64, torch.float32), (torch.complex128, torch.float64))}
+
+    def step(cd=torch.complex128, sample=None):
         out = None
         cur = torch.cuda.current_stream(dev)
         for st in streams:
             st.wait_stream(cur)
-        for i, (X, B0, V0, img) in enumerate(mixes if sample is None else mixes[:sample]):
+        for i, (X, B0, V0, img) in enumerate(typed[cd] if sample is None else typed[cd][:sample]):
             st = streams[i % len(streams)]
             with torch.cuda.stream(st):
                 Xg = X.clone().requires_grad_(True)
@@ -378,16 +383,20 @@ def adjoint_bench(args) -> int:
                     out = (loss, Xg.grad, Bg.grad)
         for st in streams:
             cur.wait_stream(st)
-        return (float(out[0]), out[1], out[2])
+        return (float(out[0].detach()), out[1], out[2])
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        first = step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    def timed_steps(cd):
+        for _ in range(args.warmup):
+            step(cd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fst = step(cd)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, fst
+
+    dt, first = timed_steps(torch.complex64)
+    dt64, first64 = timed_steps(torch.complex128)
     units = nmix * wl.F * wl.T * wl.n_iter
     value = units / dt
     # forward alone, for the split
@@ -397,8 +406,8 @@ def adjoint_bench(args) -> int:
             separate(X, B0, V0, wl.D, wl.row_taps, wl.n_iter)
     torch.cuda.synchronize()
     dt_fwd = time.perf_counter() - t0
-    log(f"forward + reverse: {dt * 1e3:.1f} ms per step of {nmix} mixtures ({value:.3e} F·T·it/s); "
-        f"forward alone {dt_fwd * 1e3:.1f} ms")
+    log(f"forward + reverse, complex64: {dt * 1e3:.1f} ms per step of {nmix} mixtures ({value:.3e} F·T·it/s); "
+        f"FP64: {dt64 * 1e3:.1f} ms; FP64 forward alone {dt_fwd * 1e3:.1f} ms")
     cpu = None
     check = None
     if not args.no_cpu_baseline:
@@ -412,12 +421,15 @@ def adjoint_bench(args) -> int:
         loss = ot.mse(C, img.cpu())
         loss.backward()
         dtc = time.perf_counter() - t0
-        gx = first[1].cpu().numpy()
-        gb = first[2].cpu().numpy()
         import numpy as np
-        check = {"mixture": 0, "loss": first[0], "loss_reference": float(loss),
-                 "gX_rel_err": float(np.linalg.norm(gx - Xt.grad.numpy()) / np.linalg.norm(Xt.grad.numpy())),
-                 "gB0_rel_err": float(np.linalg.norm(gb - Bt.grad.numpy()) / np.linalg.norm(Bt.grad.numpy()))}
+
+        def errs(fst):
+            gx = fst[1].cpu().numpy().astype(np.complex128)
+            gb = fst[2].cpu().numpy().astype(np.float64)
+            return {"loss": fst[0],
+                    "gX_rel_err": float(np.linalg.norm(gx - Xt.grad.numpy()) / np.linalg.norm(Xt.grad.numpy())),
+                    "gB0_rel_err": float(np.linalg.norm(gb - Bt.grad.numpy()) / np.linalg.norm(Bt.grad.numpy()))}
+        check = {"mixture": 0, "loss_reference": float(loss), "complex64": errs(first), "fp64": errs(first64)}
         cpu = {"value": wl.F * wl.T * wl.n_iter / dtc, "unit": "F·T·iters/s (forward + reverse)", "cores": nthreads,
                "kind": "oracle", "sample": f"mixture 0 of the batch: FP64 PyTorch autograd forward and reverse on the "
                                            f"host, {nthreads} threads, {dtc:.1f} s"}
@@ -426,12 +438,13 @@ def adjoint_bench(args) -> int:
         "metric": "F·T·iters/s ISS vs IP vs FP64-ISS at rel err ≤1e-4; HBM GB/s fraction",
         "value": value, "unit": "F·T·iters/s (forward + reverse)", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"c4 differentiation: {nmix} mixtures of 6 s, N=2, M=3, STFT 1024/256, D=4 "
                                f"(Mbar=12, taps 6+6), K=10, 20 unrolled iterations, image MSE loss, gradients "
                                f"w.r.t. the mixture STFT and the initial bases",
                    "F": wl.F, "T": wl.T, "Mbar": wl.mbar, "K": wl.K, "iterations": wl.n_iter, "mixtures": nmix},
-        "forward_ms_per_step": dt_fwd * 1e3, "streams": len(streams), "gradient_check": check, "cpu_baseline": cpu,
+        "fp64_ms_per_step": dt64 * 1e3, "fp64_forward_ms_per_step": dt_fwd * 1e3, "streams": len(streams),
+        "gradient_check": check, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -184,12 +184,13 @@ int ctfiss_nll(ctfiss_ctx* ctx, double* out);
  * with the state saved before every iteration; each iteration is then
  * reversed from its saved state (hand-written adjoint kernels of the rescale,
  * activation and basis updates, the ISS sweep row by row and the demix).
- * FP64 ISS contexts with the all-taps activation rule and Mbar <= 32 only
- * (else CTFISS_E_UNSUPPORTED).  aws: device workspace of
+ * ISS contexts in FP32 (complex64, the kernels' arithmetic in FP32) or FP64,
+ * with the all-taps activation rule and Mbar <= 32 only (else
+ * CTFISS_E_UNSUPPORTED).  aws: device workspace of
  * ctfiss_adjoint_workspace_size() bytes (256-byte aligned), scratch for the
  * call.  The context ends in the forward's final state, as after
  * ctfiss_iterate.  Enqueued on the context's stream. */
-int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int32_t n_iter, size_t* bytes);
+int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int precision, int32_t n_iter, size_t* bytes);
 int ctfiss_backward(ctfiss_ctx* ctx, int32_t n_iter, const void* B0, const void* V0, const void* gC, void* gX,
                     void* gB0, void* gV0, void* aws, size_t aws_bytes);
 

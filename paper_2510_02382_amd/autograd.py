@@ -3,7 +3,8 @@
     C = separate(X, B0, V0, D, taps, n_iter)
 
 runs W = I, (B0, V0), n_iter CTF-MNMF-ISS iterations and the source images
-through the C ABI (FP64 contexts), and its backward calls ctfiss_backward,
+through the C ABI (FP64 contexts for complex128 inputs, FP32 for complex64),
+and its backward calls ctfiss_backward,
 whose hand-written adjoint kernels re-run the forward with the state saved per
 iteration and reverse it.  Gradients flow to X (complex [M, F, T]), B0 and V0.
 """
@@ -19,7 +20,8 @@ class _Separate(torch.autograd.Function):
     def forward(ctx, X, B0, V0, D, taps, n_iter, floor):
         M, F, T = X.shape
         N, _, K = B0.shape
-        sep = Separator(F, T, M, D, N, K, taps, precision="fp64", floor=floor, device=X.device)
+        precision = "fp32" if X.dtype == torch.complex64 else "fp64"
+        sep = Separator(F, T, M, D, N, K, taps, precision=precision, floor=floor, device=X.device)
         Xc, Bc, Vc = X.detach().contiguous(), B0.detach().contiguous(), V0.detach().contiguous()
         sep.set_input(Xc)
         sep.set_state(B=Bc, V=Vc)
@@ -42,5 +44,6 @@ class _Separate(torch.autograd.Function):
 
 def separate(X: torch.Tensor, B0: torch.Tensor, V0: torch.Tensor, D: int, taps, n_iter: int,
              floor: float = 1e-8) -> torch.Tensor:
-    """Source images [N, M, F, T] (complex128) after n_iter iterations, differentiable in X, B0, V0."""
+    """Source images [N, M, F, T] after n_iter iterations, differentiable in X, B0, V0 (complex128 /
+    float64 tensors run in FP64, complex64 / float32 in FP32)."""
     return _Separate.apply(X, B0, V0, int(D), tuple(int(t) for t in taps), int(n_iter), float(floor))

@@ -78,7 +78,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "ctfiss_batch_source_images": ([vp, ctypes.POINTER(vp)], i32),
         "ctfiss_batch_sync_status": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "ctfiss_batch_destroy": ([vp], i32),
-        "ctfiss_adjoint_workspace_size": ([ctypes.POINTER(Shape), i32, ctypes.POINTER(sz)], i32),
+        "ctfiss_adjoint_workspace_size": ([ctypes.POINTER(Shape), i32, i32, ctypes.POINTER(sz)], i32),
         "ctfiss_backward": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, sz], i32),
         "ctfiss_set_graph": ([vp, i32], i32),
         "ctfiss_get_plan": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
@@ -205,9 +205,9 @@ def ctfiss_set_graph(ctx, enable: bool) -> None:
     _check(_lib.ctfiss_set_graph(ctx, 1 if enable else 0), "ctfiss_set_graph")
 
 
-def ctfiss_adjoint_workspace_size(shape: Shape, n_iter: int) -> int:
+def ctfiss_adjoint_workspace_size(shape: Shape, precision: int, n_iter: int) -> int:
     out = ctypes.c_size_t(0)
-    _check(_lib.ctfiss_adjoint_workspace_size(ctypes.byref(shape), int(n_iter), ctypes.byref(out)),
+    _check(_lib.ctfiss_adjoint_workspace_size(ctypes.byref(shape), int(precision), int(n_iter), ctypes.byref(out)),
            "ctfiss_adjoint_workspace_size")
     return int(out.value)
 

@@ -27,64 +27,70 @@
 namespace ctfiss {
 namespace {
 
-using Cd = Cx<double>;
 
-__device__ __forceinline__ Cd cconj(Cd a) { return {a.x, -a.y}; }
-__device__ __forceinline__ Cd cscale(Cd a, double s) { return {a.x * s, a.y * s}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> cconj(Cx<R> a) { return {a.x, -a.y}; }
+__device__ __forceinline__ float sqrt_t(float v) { return sqrtf(v); }
+__device__ __forceinline__ double sqrt_t(double v) { return sqrt(v); }
+template <typename R>
+__device__ __forceinline__ Cx<R> cscale(Cx<R> a, R s) { return {a.x * s, a.y * s}; }
 
+template <typename R>
 struct AdjArgs {
   // forward quantities of the iteration being reversed
-  const Cd* X;       // [M][F][T]
-  const Cd* Wk;      // [F][Mb][Mb] state at the start of the iteration
-  const double* Bk;  // [N][F][K]
-  const double* Vk;  // [N][K][T]
-  const Cd* Ws;      // [F][Mb][Mb] after the sweep, before the rescale
-  const double* Bh;  // [N][F][K] after the basis update, before the rescale
-  const double* Vh;  // [N][K][T] after the activation update
-  const double* ilam;  // [N][F][T] 1 / (Bk Vk)
-  const double* P;     // [N][F][T] tap-aligned powers of the swept rows
-  const double* mu;    // [Mb]
+  const Cx<R>* X;       // [M][F][T]
+  const Cx<R>* Wk;      // [F][Mb][Mb] state at the start of the iteration
+  const R* Bk;  // [N][F][K]
+  const R* Vk;  // [N][K][T]
+  const Cx<R>* Ws;      // [F][Mb][Mb] after the sweep, before the rescale
+  const R* Bh;  // [N][F][K] after the basis update, before the rescale
+  const R* Vh;  // [N][K][T] after the activation update
+  const R* ilam;  // [N][F][T] 1 / (Bk Vk)
+  const R* P;     // [N][F][T] tap-aligned powers of the swept rows
+  const R* mu;    // [Mb]
   // adjoints
-  Cd* gW;       // [F][Mb][Mb] in: of W', out: of Wk
-  double* gB;   // [N][F][K]   in: of B', out: of Bk
-  double* gV;   // [N][K][T]   in: of V', out: of Vk
-  double* gBh;  // [N][F][K]
-  double* gVh;  // [N][K][T]
-  double* gP;   // [N][F][T]
-  double* glam;   // [N][F][T] of lambda = Bk Vk
-  double* glamh;  // [N][F][T] of lambda = B^ Vk
-  double* lamh;   // [N][F][T] B^ Vk
-  double* q1;     // [N][F][T] P / lamh^2
-  double* q2;     // [N][F][T] c / lamh
-  double* G1;     // [N][K][T] adjoint of the activation update's numerator sum
-  double* G2;     // [N][K][T] ... denominator sum
-  double* H1;     // [N][F][K] adjoint of the basis update's numerator sum
-  double* H2;     // [N][F][K] ... denominator sum
-  double* part;   // [F][Mb + N] rescale partial sums
-  double* gS;     // [Mb] adjoint of the row power sums
-  Cd* gX;         // [M][F][T] accumulated
+  Cx<R>* gW;       // [F][Mb][Mb] in: of W', out: of Wk
+  R* gB;   // [N][F][K]   in: of B', out: of Bk
+  R* gV;   // [N][K][T]   in: of V', out: of Vk
+  R* gBh;  // [N][F][K]
+  R* gVh;  // [N][K][T]
+  R* gP;   // [N][F][T]
+  R* glam;   // [N][F][T] of lambda = Bk Vk
+  R* glamh;  // [N][F][T] of lambda = B^ Vk
+  R* lamh;   // [N][F][T] B^ Vk
+  R* q1;     // [N][F][T] P / lamh^2
+  R* q2;     // [N][F][T] c / lamh
+  R* G1;     // [N][K][T] adjoint of the activation update's numerator sum
+  R* G2;     // [N][K][T] ... denominator sum
+  R* H1;     // [N][F][K] adjoint of the basis update's numerator sum
+  R* H2;     // [N][F][K] ... denominator sum
+  R* part;   // [F][Mb + N] rescale partial sums
+  R* gS;     // [Mb] adjoint of the row power sums
+  Cx<R>* gX;         // [M][F][T] accumulated
   int* status;
   // per-bin scratch of the sweep
-  Cd* Y;        // [F][Mb][T]
-  Cd* gY;       // [F][Mb][T]
-  double* gphi; // [F][Mb][T]
-  Cd* ztape;    // [F][Mb][Mb] z of row r's step, [f][r][p]
-  double* dtape;  // [F][Mb][Mb] d_p of row r's step
-  double floor;
+  Cx<R>* Y;        // [F][Mb][T]
+  Cx<R>* gY;       // [F][Mb][T]
+  R* gphi; // [F][Mb][T]
+  Cx<R>* ztape;    // [F][Mb][Mb] z of row r's step, [f][r][p]
+  R* dtape;  // [F][Mb][Mb] d_p of row r's step
+  R floor;
   int F, T, M, D, N, K, Mb;
   int sweep_lds;  // 1: the sweep keeps gY and gphi in LDS
   RowMap rm;
 };
 
-__device__ __forceinline__ double tapc(const RowMap& rm, int n, int s, int T) {
+template <typename R>
+__device__ __forceinline__ R tapc(const RowMap& rm, int n, int s, int T) {
   const int c = T - s;
-  return (double)(c < rm.L[n] ? c : rm.L[n]);
+  return (R)(c < rm.L[n] ? c : rm.L[n]);
 }
 
 // xbar_c[t] = x[m][f][t - d] for c = d M + m (zero before frame 0)
-__device__ __forceinline__ Cd xbar(const AdjArgs& a, int f, int c, int t) {
+template <typename R>
+__device__ __forceinline__ Cx<R> xbar(const AdjArgs<R>& a, int f, int c, int t) {
   const int d = c / a.M, m = c - d * a.M;
-  return t - d >= 0 ? a.X[((size_t)m * a.F + f) * a.T + t - d] : Cd{0.0, 0.0};
+  return t - d >= 0 ? a.X[((size_t)m * a.F + f) * a.T + t - d] : Cx<R>{R(0.0), R(0.0)};
 }
 
 // fn(integral_constant<int, R>) for R in the sequence, in order: every R is a
@@ -94,7 +100,8 @@ __device__ __forceinline__ void static_for(Fn&& fn, std::integer_sequence<int, R
   (fn(std::integral_constant<int, R>{}), ...);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
@@ -103,47 +110,48 @@ __device__ __forceinline__ double wave_sum(double v) {
 // gC [N][M][F][T]: H = W^{-1} (Gauss-Jordan, partial pivoting), then
 // g_H = g_C Y^H, g_Y = H^H g_C (rows of each source), g_W = -H^H g_H H^H + g_Y xbar^H,
 // g_xbar = W^H g_Y.  Writes gW and gX (the first contributions).
-__global__ void __launch_bounds__(256) k_adj_images(AdjArgs a, const Cd* __restrict__ W, const Cd* __restrict__ gC) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_images(AdjArgs<R> a, const Cx<R>* __restrict__ W, const Cx<R>* __restrict__ gC) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int f = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const int Mb = a.Mb, M = a.M, T = a.T, F = a.F;
-  Cd* Wl = reinterpret_cast<Cd*>(smem);     // [Mb][Mb]
-  Cd* aug = Wl + Mb * Mb;                   // [Mb][2 Mb]
-  Cd* gH = aug + 2 * Mb * Mb;               // [M][Mb]
-  Cd* A = gH + M * Mb;                      // [M][Mb]  gH H^H
-  Cd* colk = A + M * Mb;                    // [Mb] pivot column
+  Cx<R>* Wl = reinterpret_cast<Cx<R>*>(smem);     // [Mb][Mb]
+  Cx<R>* aug = Wl + Mb * Mb;                   // [Mb][2 Mb]
+  Cx<R>* gH = aug + 2 * Mb * Mb;               // [M][Mb]
+  Cx<R>* A = gH + M * Mb;                      // [M][Mb]  gH H^H
+  Cx<R>* colk = A + M * Mb;                    // [Mb] pivot column
   int* piv = reinterpret_cast<int*>(colk + Mb);
-  const Cd* Wf = W + (size_t)f * Mb * Mb;
+  const Cx<R>* Wf = W + (size_t)f * Mb * Mb;
   for (int i = tid; i < Mb * Mb; i += nt) {
     Wl[i] = Wf[i];
     const int r = i / Mb, c = i - r * Mb;
     aug[r * 2 * Mb + c] = Wf[i];
-    aug[r * 2 * Mb + Mb + c] = Cd{r == c ? 1.0 : 0.0, 0.0};
+    aug[r * 2 * Mb + Mb + c] = Cx<R>{r == c ? R(1.0) : R(0.0), R(0.0)};
   }
   __syncthreads();
   for (int k = 0; k < Mb; ++k) {
     if (tid == 0) {
       int best = k;
-      double bv = cabs2(aug[k * 2 * Mb + k]);
+      R bv = cabs2(aug[k * 2 * Mb + k]);
       for (int i = k + 1; i < Mb; ++i) {
-        const double v = cabs2(aug[i * 2 * Mb + k]);
+        const R v = cabs2(aug[i * 2 * Mb + k]);
         if (v > bv) { bv = v; best = i; }
       }
       piv[0] = best;
-      if (!(bv > 0.0)) latch(a.status, kFaultOutSingular);
+      if (!(bv > R(0.0))) latch(a.status, kFaultOutSingular);
     }
     __syncthreads();
     const int pr = piv[0];
     if (pr != k)
       for (int j = tid; j < 2 * Mb; j += nt) {
-        const Cd t0 = aug[k * 2 * Mb + j];
+        const Cx<R> t0 = aug[k * 2 * Mb + j];
         aug[k * 2 * Mb + j] = aug[pr * 2 * Mb + j];
         aug[pr * 2 * Mb + j] = t0;
       }
     __syncthreads();
-    const Cd p = aug[k * 2 * Mb + k];
-    const double den = cabs2(p);
-    const Cd pinv{p.x / den, -p.y / den};
+    const Cx<R> p = aug[k * 2 * Mb + k];
+    const R den = cabs2(p);
+    const Cx<R> pinv{p.x / den, -p.y / den};
     __syncthreads();
     for (int j = tid; j < 2 * Mb; j += nt) aug[k * 2 * Mb + j] = cmul(aug[k * 2 * Mb + j], pinv);
     for (int i = tid; i < Mb; i += nt) colk[i] = aug[i * 2 * Mb + k];
@@ -157,7 +165,7 @@ __global__ void __launch_bounds__(256) k_adj_images(AdjArgs a, const Cd* __restr
   // H[i][j] = aug[i][Mb + j]
   auto H = [&](int i, int j) { return aug[i * 2 * Mb + Mb + j]; };
   auto yv = [&](int r, int t) {
-    Cd s{0.0, 0.0};
+    Cx<R> s{R(0.0), R(0.0)};
     for (int c = 0; c < Mb; ++c) s = cfma(Wl[r * Mb + c], xbar(a, f, c, t), s);
     return s;
   };
@@ -165,15 +173,15 @@ __global__ void __launch_bounds__(256) k_adj_images(AdjArgs a, const Cd* __restr
   // gH[m][r] = sum_t gC[n(r)][m][t] conj(y_r[t])
   for (int e = tid; e < M * Mb; e += nt) {
     const int m = e / Mb, r = e - m * Mb;
-    Cd s{0.0, 0.0};
+    Cx<R> s{R(0.0), R(0.0)};
     for (int t = 0; t < T; ++t) s = cfma(gc(r, m, t), cconj(yv(r, t)), s);
     gH[e] = s;
   }
   // gY[r][t] = sum_m conj(H[m][r]) gC[n(r)][m][t]  (into the sweep scratch)
-  Cd* gY = a.gY + (size_t)f * Mb * T;
+  Cx<R>* gY = a.gY + (size_t)f * Mb * T;
   for (int e = tid; e < Mb * T; e += nt) {
     const int r = e / T, t = e - r * T;
-    Cd s{0.0, 0.0};
+    Cx<R> s{R(0.0), R(0.0)};
     for (int m = 0; m < M; ++m) s = cfma(cconj(H(m, r)), gc(r, m, t), s);
     gY[e] = s;
   }
@@ -181,7 +189,7 @@ __global__ void __launch_bounds__(256) k_adj_images(AdjArgs a, const Cd* __restr
   // A = gH H^H: A[m][c] = sum_r gH[m][r] conj(H[c][r])
   for (int e = tid; e < M * Mb; e += nt) {
     const int m = e / Mb, c = e - m * Mb;
-    Cd s{0.0, 0.0};
+    Cx<R> s{R(0.0), R(0.0)};
     for (int r = 0; r < Mb; ++r) s = cfma(gH[m * Mb + r], cconj(H(c, r)), s);
     A[e] = s;
   }
@@ -189,7 +197,7 @@ __global__ void __launch_bounds__(256) k_adj_images(AdjArgs a, const Cd* __restr
   // gW[r][c] = -sum_m conj(H[m][r]) A[m][c] + sum_t gY[r][t] conj(xbar_c[t])
   for (int e = tid; e < Mb * Mb; e += nt) {
     const int r = e / Mb, c = e - r * Mb;
-    Cd s{0.0, 0.0};
+    Cx<R> s{R(0.0), R(0.0)};
     for (int m = 0; m < M; ++m) s = cfms(cconj(H(m, r)), A[m * Mb + c], s);
     for (int t = 0; t < T; ++t) s = cfma(gY[r * T + t], cconj(xbar(a, f, c, t)), s);
     a.gW[(size_t)f * Mb * Mb + e] = s;
@@ -197,7 +205,7 @@ __global__ void __launch_bounds__(256) k_adj_images(AdjArgs a, const Cd* __restr
   // gX[m][f][t] = sum_d sum_r conj(W[r][d M + m]) gY[r][t + d]
   for (int e = tid; e < M * T; e += nt) {
     const int m = e / T, t = e - m * T;
-    Cd s{0.0, 0.0};
+    Cx<R> s{R(0.0), R(0.0)};
     for (int d = 0; d < a.D && t + d < T; ++d)
       for (int r = 0; r < Mb; ++r) s = cfma(cconj(Wl[r * Mb + d * M + m]), gY[r * T + t + d], s);
     a.gX[((size_t)m * F + f) * T + t] = s;
@@ -207,22 +215,23 @@ __global__ void __launch_bounds__(256) k_adj_images(AdjArgs a, const Cd* __restr
 // ------------------------------------------------------------------ rescale
 // part[f][r] = sum_c Re(conj(W'[r][c]) gW'[r][c]) with W' = W^s / mu_r;
 // part[f][Mb + n] = sum_k gB'[n][f][k] B'[n][f][k] with B' = B^ / mu_first(n)^2.
-__global__ void __launch_bounds__(256) k_adj_rescale_part(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_rescale_part(AdjArgs<R> a) {
   const int f = blockIdx.x, tid = threadIdx.x;
   const int Mb = a.Mb;
   if (tid < Mb) {
     const int r = tid;
-    double s = 0.0;
+    R s = R(0.0);
     for (int c = 0; c < Mb; ++c) {
       const size_t o = ((size_t)f * Mb + r) * Mb + c;
-      const Cd w = a.Ws[o], g = a.gW[o];
+      const Cx<R> w = a.Ws[o], g = a.gW[o];
       s += (w.x * g.x + w.y * g.y) / a.mu[r];
     }
     a.part[(size_t)f * (Mb + a.N) + r] = s;
   } else if (tid < Mb + a.N) {
     const int n = tid - Mb;
-    const double m0 = a.mu[a.rm.r0[n]];
-    double s = 0.0;
+    const R m0 = a.mu[a.rm.r0[n]];
+    R s = R(0.0);
     for (int k = 0; k < a.K; ++k) {
       const size_t o = ((size_t)n * a.F + f) * a.K + k;
       s += a.gB[o] * a.Bh[o] / (m0 * m0);
@@ -234,11 +243,12 @@ __global__ void __launch_bounds__(256) k_adj_rescale_part(AdjArgs a) {
 // One wave per row r (lanes over f): g_mu_r = -sum_f part[f][r] / mu_r, minus
 // 2 sum_f part[f][Mb + n] / mu_r for the first row of source n;
 // gS_r = g_mu_r / (2 mu_r F T).
-__global__ void __launch_bounds__(64) k_adj_rescale_final(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(64) k_adj_rescale_final(AdjArgs<R> a) {
   const int r = blockIdx.x, lane = threadIdx.x;
   const int W = a.Mb + a.N, n = a.rm.src[r];
   const bool first = a.rm.r0[n] == r;
-  double s = 0.0, sb = 0.0;
+  R s = R(0.0), sb = R(0.0);
   for (int f = lane; f < a.F; f += 64) {
     s += a.part[(size_t)f * W + r];
     if (first) sb += a.part[(size_t)f * W + a.Mb + n];
@@ -246,22 +256,23 @@ __global__ void __launch_bounds__(64) k_adj_rescale_final(AdjArgs a) {
   s = wave_sum(s);
   sb = wave_sum(sb);
   if (lane == 0) {
-    const double g = -(s + 2.0 * sb) / a.mu[r];
-    a.gS[r] = g / (2.0 * a.mu[r] * (double)a.F * (double)a.T);
+    const R g = -(s + R(2.0) * sb) / a.mu[r];
+    a.gS[r] = g / (R(2.0) * a.mu[r] * (R)a.F * (R)a.T);
   }
 }
 
 // gW^s = gW' / mu_r (in place), gB^ = gB' / mu_first^2, gV^ = gV'.
-__global__ void __launch_bounds__(256) k_adj_rescale_apply(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_rescale_apply(AdjArgs<R> a) {
   const size_t nW = (size_t)a.F * a.Mb * a.Mb, nB = (size_t)a.N * a.F * a.K, nV = (size_t)a.N * a.K * a.T;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nW) {
     const int r = (int)((i / a.Mb) % a.Mb);
-    a.gW[i] = cscale(a.gW[i], 1.0 / a.mu[r]);
+    a.gW[i] = cscale(a.gW[i], R(1.0) / a.mu[r]);
   } else if (i < nW + nB) {
     const size_t j = i - nW;
     const int n = (int)(j / ((size_t)a.F * a.K));
-    const double m0 = a.mu[a.rm.r0[n]];
+    const R m0 = a.mu[a.rm.r0[n]];
     a.gBh[j] = a.gB[j] / (m0 * m0);
   } else if (i < nW + nB + nV) {
     const size_t j = i - nW - nB;
@@ -271,29 +282,31 @@ __global__ void __launch_bounds__(256) k_adj_rescale_apply(AdjArgs a) {
 
 // ------------------------------------------------------------------ activation update
 // Per (n, f, s): lamh = B^ Vk, q1 = P / lamh^2, q2 = c / lamh.
-__global__ void __launch_bounds__(256) k_adj_v0(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_v0(AdjArgs<R> a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)a.N * a.F * a.T) return;
   const int s = (int)(i % a.T), f = (int)((i / a.T) % a.F), n = (int)(i / ((size_t)a.F * a.T));
-  const double* b = a.Bh + ((size_t)n * a.F + f) * a.K;
-  double lam = 0.0;
+  const R* b = a.Bh + ((size_t)n * a.F + f) * a.K;
+  R lam = R(0.0);
   for (int k = 0; k < a.K; ++k) lam += b[k] * a.Vk[((size_t)n * a.K + k) * a.T + s];
   a.lamh[i] = lam;
   a.q1[i] = a.P[i] / (lam * lam);
-  a.q2[i] = tapc(a.rm, n, s, a.T) / lam;
+  a.q2[i] = tapc<R>(a.rm, n, s, a.T) / lam;
 }
 
 // One wave per (n, k, s): num = sum_f B^ q1, den = sum_f B^ q2 (lanes over f);
 // where V^ was not clamped: gV[n][k][s] = gV^ sqrt(num / den), G1 = gV^ V^ / (2 num),
 // G2 = -gV^ V^ / (2 den); else all zero.
-__global__ void __launch_bounds__(256) k_adj_v1(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_v1(AdjArgs<R> a) {
   const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= (size_t)a.N * a.K * a.T) return;
   const int s = (int)(i % a.T), k = (int)((i / a.T) % a.K), n = (int)(i / ((size_t)a.K * a.T));
-  double num = 0.0, den = 0.0;
+  R num = R(0.0), den = R(0.0);
   for (int f = lane; f < a.F; f += 64) {
-    const double b = a.Bh[((size_t)n * a.F + f) * a.K + k];
+    const R b = a.Bh[((size_t)n * a.F + f) * a.K + k];
     const size_t o = ((size_t)n * a.F + f) * a.T + s;
     num += b * a.q1[o];
     den += b * a.q2[o];
@@ -301,34 +314,35 @@ __global__ void __launch_bounds__(256) k_adj_v1(AdjArgs a) {
   num = wave_sum(num);
   den = wave_sum(den);
   if (lane != 0) return;
-  const double ratio = sqrt(num / den);
-  const double val = a.Vk[i] * ratio;
-  const double g = a.gVh[i];
+  const R ratio = sqrt_t(num / den);
+  const R val = a.Vk[i] * ratio;
+  const R g = a.gVh[i];
   if (val >= a.floor) {
     a.gV[i] = g * ratio;
-    a.G1[i] = g * val / (2.0 * num);
-    a.G2[i] = -g * val / (2.0 * den);
+    a.G1[i] = g * val / (R(2.0) * num);
+    a.G2[i] = -g * val / (R(2.0) * den);
   } else {
-    a.gV[i] = 0.0;
-    a.G1[i] = 0.0;
-    a.G2[i] = 0.0;
+    a.gV[i] = R(0.0);
+    a.G1[i] = R(0.0);
+    a.G2[i] = R(0.0);
   }
 }
 
 // Per (n, f, s): lamh = B^ Vk; gP = sum_k G1 B^ / lamh^2 (first contribution);
 // glamh = sum_k (-2 G1 B^ P / lamh^3 - G2 B^ c / lamh^2).
-__global__ void __launch_bounds__(256) k_adj_v2(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_v2(AdjArgs<R> a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)a.N * a.F * a.T) return;
   const int s = (int)(i % a.T), f = (int)((i / a.T) % a.F), n = (int)(i / ((size_t)a.F * a.T));
-  const double* b = a.Bh + ((size_t)n * a.F + f) * a.K;
-  const double lam = a.lamh[i];
-  const double p = a.P[i], c = tapc(a.rm, n, s, a.T);
-  double gp = 0.0, gl = 0.0;
+  const R* b = a.Bh + ((size_t)n * a.F + f) * a.K;
+  const R lam = a.lamh[i];
+  const R p = a.P[i], c = tapc<R>(a.rm, n, s, a.T);
+  R gp = R(0.0), gl = R(0.0);
   for (int k = 0; k < a.K; ++k) {
     const size_t o = ((size_t)n * a.K + k) * a.T + s;
     gp += a.G1[o] * b[k] / (lam * lam);
-    gl += -2.0 * a.G1[o] * b[k] * p / (lam * lam * lam) - a.G2[o] * b[k] * c / (lam * lam);
+    gl += -R(2.0) * a.G1[o] * b[k] * p / (lam * lam * lam) - a.G2[o] * b[k] * c / (lam * lam);
   }
   a.gP[i] = gp;
   a.glamh[i] = gl;
@@ -340,17 +354,18 @@ __global__ void __launch_bounds__(256) k_adj_v2(AdjArgs a) {
 // update with lam = 1 / ilam: num = sum_s P Vk / lam^2, den = sum_s c Vk / lam;
 // where B^ was not clamped: gB = gB^ sqrt(num / den), H1 = gB^ B^ / (2 num),
 // H2 = -gB^ B^ / (2 den); else zero.
-__global__ void __launch_bounds__(256) k_adj_b1(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_b1(AdjArgs<R> a) {
   const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= (size_t)a.N * a.F * a.K) return;
   const int k = (int)(i % a.K), f = (int)((i / a.K) % a.F), n = (int)(i / ((size_t)a.F * a.K));
   const size_t fo = ((size_t)n * a.F + f) * a.T, ko = ((size_t)n * a.K + k) * a.T;
-  double gbh = 0.0, num = 0.0, den = 0.0;
+  R gbh = R(0.0), num = R(0.0), den = R(0.0);
   for (int s = lane; s < a.T; s += 64) {
-    const double c = tapc(a.rm, n, s, a.T), p = a.P[fo + s], v = a.Vk[ko + s];
+    const R c = tapc<R>(a.rm, n, s, a.T), p = a.P[fo + s], v = a.Vk[ko + s];
     gbh += a.G1[ko + s] * a.q1[fo + s] + a.G2[ko + s] * a.q2[fo + s] + a.glamh[fo + s] * v;
-    const double il = a.ilam[fo + s];
+    const R il = a.ilam[fo + s];
     num += p * v * il * il;
     den += c * v * il;
   }
@@ -358,31 +373,32 @@ __global__ void __launch_bounds__(256) k_adj_b1(AdjArgs a) {
   num = wave_sum(num);
   den = wave_sum(den);
   if (lane != 0) return;
-  const double ratio = sqrt(num / den);
-  const double val = a.Bk[i] * ratio;
+  const R ratio = sqrt_t(num / den);
+  const R val = a.Bk[i] * ratio;
   if (val >= a.floor) {
     a.gB[i] = gbh * ratio;
-    a.H1[i] = gbh * val / (2.0 * num);
-    a.H2[i] = -gbh * val / (2.0 * den);
+    a.H1[i] = gbh * val / (R(2.0) * num);
+    a.H2[i] = -gbh * val / (R(2.0) * den);
   } else {
-    a.gB[i] = 0.0;
-    a.H1[i] = 0.0;
-    a.H2[i] = 0.0;
+    a.gB[i] = R(0.0);
+    a.H1[i] = R(0.0);
+    a.H2[i] = R(0.0);
   }
 }
 
 // Per (n, f, s): gP += sum_k H1 Vk / lam^2;  glam = sum_k (-2 H1 Vk P / lam^3 - H2 c Vk / lam^2).
-__global__ void __launch_bounds__(256) k_adj_b2(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_b2(AdjArgs<R> a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)a.N * a.F * a.T) return;
   const int s = (int)(i % a.T), f = (int)((i / a.T) % a.F), n = (int)(i / ((size_t)a.F * a.T));
-  const double il = a.ilam[i], p = a.P[i], c = tapc(a.rm, n, s, a.T);
-  double gp = 0.0, gl = 0.0;
+  const R il = a.ilam[i], p = a.P[i], c = tapc<R>(a.rm, n, s, a.T);
+  R gp = R(0.0), gl = R(0.0);
   for (int k = 0; k < a.K; ++k) {
-    const double v = a.Vk[((size_t)n * a.K + k) * a.T + s];
+    const R v = a.Vk[((size_t)n * a.K + k) * a.T + s];
     const size_t o = ((size_t)n * a.F + f) * a.K + k;
     gp += a.H1[o] * v * il * il;
-    gl += -2.0 * a.H1[o] * v * p * il * il * il - a.H2[o] * c * v * il * il;
+    gl += -R(2.0) * a.H1[o] * v * p * il * il * il - a.H2[o] * c * v * il * il;
   }
   a.gP[i] += gp;
   a.glam[i] = gl;
@@ -393,35 +409,36 @@ __global__ void __launch_bounds__(256) k_adj_b2(AdjArgs a) {
 // recorded.  Backward from gW^s and gY^s = 2 y (tap-aligned gP) + 2 gS_r y_r,
 // rows r = Mb-1 .. 0.  Then the demix (gW += gY xbar^H, gxbar = Wk^H gY) and
 // glam += -sum_l gphi_(n,l)[s + l] / lam^2.
-__global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_iss(AdjArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int f = blockIdx.x, tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int Mb = a.Mb, T = a.T, F = a.F;
-  const double invT = 1.0 / T;
-  Cd* W = reinterpret_cast<Cd*>(smem);   // [Mb][Mb]
-  Cd* gWl = W + Mb * Mb;                 // [Mb][Mb]
-  Cd* zl = gWl + Mb * Mb;                // [Mb]
-  Cd* ga = zl + Mb;                      // [Mb] adjoint of a_p
-  Cd* wr = ga + Mb;                      // [Mb] row r of W
-  double* dl = reinterpret_cast<double*>(wr + Mb);  // [Mb]
-  double* gd = dl + Mb;                  // [Mb] adjoint of d_p
-  Cd* yr = reinterpret_cast<Cd*>(gd + Mb);  // [T]
+  const R invT = R(1.0) / T;
+  Cx<R>* W = reinterpret_cast<Cx<R>*>(smem);   // [Mb][Mb]
+  Cx<R>* gWl = W + Mb * Mb;                 // [Mb][Mb]
+  Cx<R>* zl = gWl + Mb * Mb;                // [Mb]
+  Cx<R>* ga = zl + Mb;                      // [Mb] adjoint of a_p
+  Cx<R>* wr = ga + Mb;                      // [Mb] row r of W
+  R* dl = reinterpret_cast<R*>(wr + Mb);  // [Mb]
+  R* gd = dl + Mb;                  // [Mb] adjoint of d_p
+  Cx<R>* yr = reinterpret_cast<Cx<R>*>(gd + Mb);  // [T]
   // the rows (read-mostly) stay in global memory; their adjoints and the
   // weight adjoints go to LDS when they fit (every step reads and writes them)
-  Cd* Y = a.Y + (size_t)f * Mb * T;
-  Cd* gY = a.sweep_lds ? yr + T : a.gY + (size_t)f * Mb * T;
-  double* gphi = a.sweep_lds ? reinterpret_cast<double*>(gY + (size_t)Mb * T) : a.gphi + (size_t)f * Mb * T;
-  Cd* zt = a.ztape + (size_t)f * Mb * Mb;
-  double* dt = a.dtape + (size_t)f * Mb * Mb;
+  Cx<R>* Y = a.Y + (size_t)f * Mb * T;
+  Cx<R>* gY = a.sweep_lds ? yr + T : a.gY + (size_t)f * Mb * T;
+  R* gphi = a.sweep_lds ? reinterpret_cast<R*>(gY + (size_t)Mb * T) : a.gphi + (size_t)f * Mb * T;
+  Cx<R>* zt = a.ztape + (size_t)f * Mb * Mb;
+  R* dt = a.dtape + (size_t)f * Mb * Mb;
   auto phi = [&](int p, int t) {
     const int l = a.rm.tap[p];
-    return t >= l ? a.ilam[((size_t)a.rm.src[p] * F + f) * T + t - l] : 0.0;
+    return t >= l ? a.ilam[((size_t)a.rm.src[p] * F + f) * T + t - l] : R(0.0);
   };
   for (int i = tid; i < Mb * Mb; i += nt) W[i] = a.Wk[(size_t)f * Mb * Mb + i];
   __syncthreads();
   for (int e = tid; e < Mb * T; e += nt) {
     const int r = e / T, t = e - r * T;
-    Cd s{0.0, 0.0};
+    Cx<R> s{R(0.0), R(0.0)};
     for (int c = 0; c < Mb; ++c) s = cfma(W[r * Mb + c], xbar(a, f, c, t), s);
     Y[e] = s;
   }
@@ -432,12 +449,12 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
     if (tid < Mb) wr[tid] = W[r * Mb + tid];
     __syncthreads();
     for (int p = wave; p < Mb; p += nw) {
-      double d = 0.0, ax = 0.0, ay = 0.0;
+      R d = R(0.0), ax = R(0.0), ay = R(0.0);
       for (int t = lane; t < T; t += 64) {
-        const double ph = phi(p, t);
-        const Cd y = yr[t], yp = Y[p * T + t];
+        const R ph = phi(p, t);
+        const Cx<R> y = yr[t], yp = Y[p * T + t];
         d += ph * cabs2(y);
-        const Cd q = cmulc(yp, y);
+        const Cx<R> q = cmulc(yp, y);
         ax += ph * q.x;
         ay += ph * q.y;
       }
@@ -445,8 +462,8 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
       ax = wave_sum(ax) * invT;
       ay = wave_sum(ay) * invT;
       if (lane == 0) {
-        Cd z{ax / d, ay / d};
-        if (p == r) z = Cd{1.0 - 1.0 / sqrt(d), 0.0};
+        Cx<R> z{ax / d, ay / d};
+        if (p == r) z = Cx<R>{R(1.0) - R(1.0) / sqrt_t(d), R(0.0)};
         zl[p] = z;
         dl[p] = d;
         zt[r * Mb + p] = z;
@@ -469,69 +486,69 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
   for (int e = tid; e < Mb * T; e += nt) {
     const int r = e / T, t = e - r * T;
     const int n = a.rm.src[r], l = a.rm.tap[r];
-    double g = 2.0 * a.gS[r];
-    if (t >= l) g += 2.0 * a.gP[((size_t)n * F + f) * T + t - l];
+    R g = R(2.0) * a.gS[r];
+    if (t >= l) g += R(2.0) * a.gP[((size_t)n * F + f) * T + t - l];
     gY[e] = cscale(Y[e], g);
-    gphi[e] = 0.0;
+    gphi[e] = R(0.0);
   }
   __syncthreads();
   for (int r = Mb - 1; r >= 0; --r) {
-    const Cd zr = zt[r * Mb + r];
-    const double sc = 1.0 - zr.x;  // y_r' = sc y_r
+    const Cx<R> zr = zt[r * Mb + r];
+    const R sc = R(1.0) - zr.x;  // y_r' = sc y_r
     // rows before the step: y_r = y_r' / sc (the other rows after the reductions)
     for (int t = tid; t < T; t += nt) {
-      const Cd v = cscale(Y[r * T + t], 1.0 / sc);
+      const Cx<R> v = cscale(Y[r * T + t], R(1.0) / sc);
       Y[r * T + t] = v;
       yr[t] = v;
     }
     if (tid < Mb) {
-      wr[tid] = cscale(W[r * Mb + tid], 1.0 / sc);
+      wr[tid] = cscale(W[r * Mb + tid], R(1.0) / sc);
       zl[tid] = zt[r * Mb + tid];
       dl[tid] = dt[r * Mb + tid];
     }
     __syncthreads();
     // g_z_p = -sum_c gW'[p][c] conj(w_r[c]) - sum_t gY'[p][t] conj(y_r[t])
     for (int p = wave; p < Mb; p += nw) {
-      double gx = 0.0, gy = 0.0;
+      R gx = R(0.0), gy = R(0.0);
       for (int t = lane; t < T; t += 64) {
-        const Cd q = cmulc(gY[p * T + t], yr[t]);
+        const Cx<R> q = cmulc(gY[p * T + t], yr[t]);
         gx += q.x;
         gy += q.y;
       }
       for (int c = lane; c < Mb; c += 64) {
-        const Cd q = cmulc(gWl[p * Mb + c], wr[c]);
+        const Cx<R> q = cmulc(gWl[p * Mb + c], wr[c]);
         gx += q.x;
         gy += q.y;
       }
       gx = -wave_sum(gx);
       gy = -wave_sum(gy);
       if (lane == 0) {
-        const Cd gz{gx, gy};
-        const double d = dl[p];
+        const Cx<R> gz{gx, gy};
+        const R d = dl[p];
         if (p == r) {
-          ga[p] = Cd{0.0, 0.0};
-          gd[p] = 0.5 * pow(d, -1.5) * gz.x;
+          ga[p] = Cx<R>{R(0.0), R(0.0)};
+          gd[p] = R(0.5) * gz.x / (d * sqrt_t(d));  // d^{-3/2} / 2
         } else {
-          const Cd z = zl[p];
-          ga[p] = cscale(gz, 1.0 / d);
+          const Cx<R> z = zl[p];
+          ga[p] = cscale(gz, R(1.0) / d);
           gd[p] = -(z.x * gz.x + z.y * gz.y) / d;
         }
       }
     }
     __syncthreads();
     for (int t = tid; t < T; t += nt) {
-      const Cd y = yr[t];
-      const double y2 = cabs2(y);
-      Cd gyr = cscale(gY[r * T + t], sc);
+      const Cx<R> y = yr[t];
+      const R y2 = cabs2(y);
+      Cx<R> gyr = cscale(gY[r * T + t], sc);
       for (int p = 0; p < Mb; ++p) {
-        const double ph = phi(p, t) * invT;
-        gyr = cfma(cscale(y, 2.0 * ph), Cd{gd[p], 0.0}, gyr);
+        const R ph = phi(p, t) * invT;
+        gyr = cfma(cscale(y, R(2.0) * ph), Cx<R>{gd[p], R(0.0)}, gyr);
         gphi[p * T + t] += y2 * gd[p] * invT;
         if (p == r) continue;
-        const Cd z = zl[p];
-        const Cd gp = gY[p * T + t];
+        const Cx<R> z = zl[p];
+        const Cx<R> gp = gY[p * T + t];
         gyr = cfms(cconj(z), gp, gyr);
-        const Cd yp = cfma(z, y, Y[p * T + t]);  // row p before the step
+        const Cx<R> yp = cfma(z, y, Y[p * T + t]);  // row p before the step
         Y[p * T + t] = yp;
         gyr = cfma(cscale(yp, ph), cconj(ga[p]), gyr);
         gY[p * T + t] = cfma(cscale(y, ph), ga[p], gp);
@@ -541,7 +558,7 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
     }
     if (tid < Mb) {
       const int c = tid;
-      Cd g = cscale(gWl[r * Mb + c], sc);
+      Cx<R> g = cscale(gWl[r * Mb + c], sc);
       for (int p = 0; p < Mb; ++p) {
         if (p == r) continue;
         g = cfms(cconj(zl[p]), gWl[p * Mb + c], g);
@@ -553,16 +570,16 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
     __syncthreads();
   }
   // demix: gW = gWl + gY xbar^H; gxbar = Wk^H gY
-  const Cd* Wk = a.Wk + (size_t)f * Mb * Mb;
+  const Cx<R>* Wk = a.Wk + (size_t)f * Mb * Mb;
   for (int e = tid; e < Mb * Mb; e += nt) {
     const int r = e / Mb, c = e - r * Mb;
-    Cd s = gWl[e];
+    Cx<R> s = gWl[e];
     for (int t = 0; t < T; ++t) s = cfma(gY[r * T + t], cconj(xbar(a, f, c, t)), s);
     a.gW[(size_t)f * Mb * Mb + e] = s;
   }
   for (int e = tid; e < a.M * T; e += nt) {
     const int m = e / T, t = e - m * T;
-    Cd s{0.0, 0.0};
+    Cx<R> s{R(0.0), R(0.0)};
     for (int d = 0; d < a.D && t + d < T; ++d)
       for (int r = 0; r < Mb; ++r) s = cfma(cconj(Wk[r * Mb + d * a.M + m]), gY[r * T + t + d], s);
     const size_t o = ((size_t)m * F + f) * T + t;
@@ -572,8 +589,8 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
   for (int e = tid; e < a.N * T; e += nt) {
     const int n = e / T, s = e - n * T;
     const size_t o = ((size_t)n * F + f) * T + s;
-    const double il = a.ilam[o];
-    double g = 0.0;
+    const R il = a.ilam[o];
+    R g = R(0.0);
     for (int l = 0; l < a.rm.L[n] && s + l < T; ++l) g += gphi[(a.rm.r0[n] + l) * T + s + l];
     a.glam[o] -= g * il * il;
   }
@@ -586,50 +603,50 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs a) {
 // array is indexed at run time.  Only the frame sums of each step cross
 // threads (wave sums, then LDS across waves).  The coefficients z and d_p of
 // the forward sweep stay in LDS.  Same arithmetic as k_adj_iss.
-template <int MB>
-__global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
+template <typename R, int MB>
+__global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int f = blockIdx.x, tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   const int Mb = a.Mb, T = a.T, F = a.F, t = tid;
   const bool own = t < T;
-  const double invT = 1.0 / T;
-  Cd* W = reinterpret_cast<Cd*>(smem);  // [Mb][Mb]
-  Cd* gWl = W + MB * MB;                // [Mb][Mb]
-  Cd* zt = gWl + MB * MB;               // [MB][MB] z of step r, [r][p]
-  Cd* ga = zt + MB * MB;                // [MB]
-  Cd* wr = ga + MB;                     // [MB]
-  double* dt = reinterpret_cast<double*>(wr + MB);  // [MB][MB]
-  double* gd = dt + MB * MB;                        // [MB]
-  double* red = gd + MB;                            // [nw][3 MB] partial frame sums
+  const R invT = R(1.0) / T;
+  Cx<R>* W = reinterpret_cast<Cx<R>*>(smem);  // [Mb][Mb]
+  Cx<R>* gWl = W + MB * MB;                // [Mb][Mb]
+  Cx<R>* zt = gWl + MB * MB;               // [MB][MB] z of step r, [r][p]
+  Cx<R>* ga = zt + MB * MB;                // [MB]
+  Cx<R>* wr = ga + MB;                     // [MB]
+  R* dt = reinterpret_cast<R*>(wr + MB);  // [MB][MB]
+  R* gd = dt + MB * MB;                        // [MB]
+  R* red = gd + MB;                            // [nw][3 MB] partial frame sums
   for (int i = tid; i < Mb * Mb; i += nt) {
     const int r = i / Mb, c = i - r * Mb;
     W[r * MB + c] = a.Wk[(size_t)f * Mb * Mb + i];
   }
   __syncthreads();
-  Cd y[MB], gy[MB];
-  double ph[MB], gph[MB];
+  Cx<R> y[MB], gy[MB];
+  R ph[MB], gph[MB];
 #pragma unroll
   for (int p = 0; p < MB; ++p) {
-    Cd s{0.0, 0.0};
-    double w = 0.0;
+    Cx<R> s{R(0.0), R(0.0)};
+    R w = R(0.0);
     if (p < Mb && own) {
       for (int c = 0; c < Mb; ++c) s = cfma(W[p * MB + c], xbar(a, f, c, t), s);
       const int l = a.rm.tap[p];
-      w = t >= l ? a.ilam[((size_t)a.rm.src[p] * F + f) * T + t - l] : 0.0;
+      w = t >= l ? a.ilam[((size_t)a.rm.src[p] * F + f) * T + t - l] : R(0.0);
     }
     y[p] = s;
     ph[p] = w;
-    gph[p] = 0.0;
+    gph[p] = R(0.0);
   }
   // frame sum v of this wave into its slot; then block_finish adds the waves' slots
-  auto wave_put = [&](int v, double x) {
-    const double s = group_sum<64>(x);  // DPP within rows of 16 lanes, two cross-row steps
+  auto wave_put = [&](int v, R x) {
+    const R s = group_sum<64>(x);  // DPP within rows of 16 lanes, two cross-row steps
     if (lane == 0) red[wave * 3 * MB + v] = s;
   };
   auto block_finish = [&](int nv) {
     __syncthreads();
     if (tid < nv) {
-      double s = 0.0;
+      R s = R(0.0);
       for (int w2 = 0; w2 < nw; ++w2) s += red[w2 * 3 * MB + tid];
       red[tid] = s;  // wave 0's slot: every wave has read its partial above
     }
@@ -639,11 +656,11 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
   auto fwd_step = [&](auto rc) {
     constexpr int r = decltype(rc)::value;
     if (r < Mb) {
-    const Cd yr = y[r];
+    const Cx<R> yr = y[r];
 #pragma unroll
     for (int p = 0; p < MB; ++p) {
       if (p < Mb) {
-        const Cd q = cmulc(y[p], yr);
+        const Cx<R> q = cmulc(y[p], yr);
         wave_put(3 * p, ph[p] * cabs2(yr));
         wave_put(3 * p + 1, ph[p] * q.x);
         wave_put(3 * p + 2, ph[p] * q.y);
@@ -653,9 +670,9 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
     block_finish(3 * Mb);
     if (tid < Mb) {
       const int p = tid;
-      const double d = red[3 * p] * invT;
-      Cd z{red[3 * p + 1] * invT / d, red[3 * p + 2] * invT / d};
-      if (p == r) z = Cd{1.0 - 1.0 / sqrt(d), 0.0};
+      const R d = red[3 * p] * invT;
+      Cx<R> z{red[3 * p + 1] * invT / d, red[3 * p + 2] * invT / d};
+      if (p == r) z = Cx<R>{R(1.0) - R(1.0) / sqrt_t(d), R(0.0)};
       zt[r * MB + p] = z;
       dt[r * MB + p] = d;
     }
@@ -677,11 +694,11 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
   }
 #pragma unroll
   for (int p = 0; p < MB; ++p) {
-    double g = 0.0;
+    R g = R(0.0);
     if (p < Mb && own) {
       const int n = a.rm.src[p], l = a.rm.tap[p];
-      g = 2.0 * a.gS[p];
-      if (t >= l) g += 2.0 * a.gP[((size_t)n * F + f) * T + t - l];
+      g = R(2.0) * a.gS[p];
+      if (t >= l) g += R(2.0) * a.gP[((size_t)n * F + f) * T + t - l];
     }
     gy[p] = cscale(y[p], g);
   }
@@ -689,14 +706,14 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
   auto rev_step = [&](auto rc) {
     constexpr int r = MB - 1 - decltype(rc)::value;
     if (r < Mb) {
-    const double sc = 1.0 - zt[r * MB + r].x;
-    y[r] = cscale(y[r], 1.0 / sc);  // row r before the step
-    const Cd yr = y[r];
-    if (tid < Mb) wr[tid] = cscale(W[r * MB + tid], 1.0 / sc);
+    const R sc = R(1.0) - zt[r * MB + r].x;
+    y[r] = cscale(y[r], R(1.0) / sc);  // row r before the step
+    const Cx<R> yr = y[r];
+    if (tid < Mb) wr[tid] = cscale(W[r * MB + tid], R(1.0) / sc);
 #pragma unroll
     for (int p = 0; p < MB; ++p) {
       if (p < Mb) {
-        const Cd q = cmulc(gy[p], yr);
+        const Cx<R> q = cmulc(gy[p], yr);
         wave_put(2 * p, q.x);
         wave_put(2 * p + 1, q.y);
       }
@@ -704,37 +721,37 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
     block_finish(2 * Mb);  // also completes wr
     if (tid < Mb) {
       const int p = tid;
-      double gx = red[2 * p], gyv = red[2 * p + 1];
+      R gx = red[2 * p], gyv = red[2 * p + 1];
       for (int c = 0; c < Mb; ++c) {
-        const Cd q = cmulc(gWl[p * MB + c], wr[c]);
+        const Cx<R> q = cmulc(gWl[p * MB + c], wr[c]);
         gx += q.x;
         gyv += q.y;
       }
-      const Cd gz{-gx, -gyv};
-      const double d = dt[r * MB + p];
+      const Cx<R> gz{-gx, -gyv};
+      const R d = dt[r * MB + p];
       if (p == r) {
-        ga[p] = Cd{0.0, 0.0};
-        gd[p] = 0.5 * pow(d, -1.5) * gz.x;
+        ga[p] = Cx<R>{R(0.0), R(0.0)};
+        gd[p] = R(0.5) * gz.x / (d * sqrt_t(d));  // d^{-3/2} / 2
       } else {
-        const Cd z = zt[r * MB + p];
-        ga[p] = cscale(gz, 1.0 / d);
+        const Cx<R> z = zt[r * MB + p];
+        ga[p] = cscale(gz, R(1.0) / d);
         gd[p] = -(z.x * gz.x + z.y * gz.y) / d;
       }
     }
     __syncthreads();
     {
-      const double y2 = cabs2(yr);
-      Cd gyr = cscale(gy[r], sc);
+      const R y2 = cabs2(yr);
+      Cx<R> gyr = cscale(gy[r], sc);
 #pragma unroll
       for (int p = 0; p < MB; ++p) {
         if (p >= Mb) continue;
-        const double phs = ph[p] * invT;
-        gyr = cfma(cscale(yr, 2.0 * phs), Cd{gd[p], 0.0}, gyr);
+        const R phs = ph[p] * invT;
+        gyr = cfma(cscale(yr, R(2.0) * phs), Cx<R>{gd[p], R(0.0)}, gyr);
         gph[p] += y2 * gd[p] * invT;
         if (p == r) continue;
-        const Cd z = zt[r * MB + p];
+        const Cx<R> z = zt[r * MB + p];
         gyr = cfms(cconj(z), gy[p], gyr);
-        const Cd yp = cfma(z, yr, y[p]);
+        const Cx<R> yp = cfma(z, yr, y[p]);
         y[p] = yp;
         gyr = cfma(cscale(yp, phs), cconj(ga[p]), gyr);
         gy[p] = cfma(cscale(yr, phs), ga[p], gy[p]);
@@ -744,7 +761,7 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
     }
     if (tid < Mb) {
       const int c = tid;
-      Cd g = cscale(gWl[r * MB + c], sc);
+      Cx<R> g = cscale(gWl[r * MB + c], sc);
       for (int p = 0; p < Mb; ++p) {
         if (p == r) continue;
         g = cfms(cconj(zt[r * MB + p]), gWl[p * MB + c], g);
@@ -759,8 +776,8 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
   static_for(rev_step, std::make_integer_sequence<int, MB>{});
   // columns and the row adjoint of W to memory; the steps that mix frames
   // (demix and lambda adjoints) run as separate launches
-  Cd* gY = a.gY + (size_t)f * Mb * T;
-  double* gphi = a.gphi + (size_t)f * Mb * T;
+  Cx<R>* gY = a.gY + (size_t)f * Mb * T;
+  R* gphi = a.gphi + (size_t)f * Mb * T;
   if (own) {
 #pragma unroll
     for (int p = 0; p < MB; ++p)
@@ -776,47 +793,50 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs a) {
 }
 
 // One wave per (f, r, c), lanes over frames: gW[f][r][c] += sum_t gY[r][t] conj(xbar_c[t]).
-__global__ void __launch_bounds__(256) k_adj_demix_w(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_demix_w(AdjArgs<R> a) {
   const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   const int Mb = a.Mb, T = a.T;
   if (i >= (size_t)a.F * Mb * Mb) return;
   const int c = (int)(i % Mb), r = (int)((i / Mb) % Mb), f = (int)(i / ((size_t)Mb * Mb));
-  const Cd* g = a.gY + ((size_t)f * Mb + r) * T;
-  double sx = 0.0, sy = 0.0;
+  const Cx<R>* g = a.gY + ((size_t)f * Mb + r) * T;
+  R sx = R(0.0), sy = R(0.0);
   for (int t = lane; t < T; t += 64) {
-    const Cd q = cmulc(g[t], xbar(a, f, c, t));
+    const Cx<R> q = cmulc(g[t], xbar(a, f, c, t));
     sx += q.x;
     sy += q.y;
   }
   sx = group_sum<64>(sx);
   sy = group_sum<64>(sy);
-  if (lane == 0) a.gW[i] = cadd(a.gW[i], Cd{sx, sy});
+  if (lane == 0) a.gW[i] = cadd(a.gW[i], Cx<R>{sx, sy});
 }
 
 // Per (m, f, t): gX[m][f][t] += sum_d sum_r conj(Wk[r][d M + m]) gY[r][t + d].
-__global__ void __launch_bounds__(256) k_adj_demix_x(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_demix_x(AdjArgs<R> a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int Mb = a.Mb, T = a.T, F = a.F;
   if (i >= (size_t)a.M * F * T) return;
   const int t = (int)(i % T), f = (int)((i / T) % F), m = (int)(i / ((size_t)F * T));
-  const Cd* Wk = a.Wk + (size_t)f * Mb * Mb;
-  const Cd* g = a.gY + (size_t)f * Mb * T;
-  Cd s{0.0, 0.0};
+  const Cx<R>* Wk = a.Wk + (size_t)f * Mb * Mb;
+  const Cx<R>* g = a.gY + (size_t)f * Mb * T;
+  Cx<R> s{R(0.0), R(0.0)};
   for (int d = 0; d < a.D && t + d < T; ++d)
     for (int r = 0; r < Mb; ++r) s = cfma(cconj(Wk[r * Mb + d * a.M + m]), g[r * T + t + d], s);
   a.gX[i] = cadd(a.gX[i], s);
 }
 
 // Per (n, f, s): glam[n][f][s] -= sum_l gphi_(n,l)[s + l] / lam^2 (phi = 1 / lambda).
-__global__ void __launch_bounds__(256) k_adj_phi(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_phi(AdjArgs<R> a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int T = a.T, F = a.F;
   if (i >= (size_t)a.N * F * T) return;
   const int sv = (int)(i % T), f = (int)((i / T) % F), n = (int)(i / ((size_t)F * T));
-  const double* gp = a.gphi + (size_t)f * a.Mb * T;
-  const double il = a.ilam[i];
-  double g = 0.0;
+  const R* gp = a.gphi + (size_t)f * a.Mb * T;
+  const R il = a.ilam[i];
+  R g = R(0.0);
   for (int l = 0; l < a.rm.L[n] && sv + l < T; ++l) g += gp[(a.rm.r0[n] + l) * T + sv + l];
   a.glam[i] -= g * il * il;
 }
@@ -824,20 +844,21 @@ __global__ void __launch_bounds__(256) k_adj_phi(AdjArgs a) {
 // Row bound of the register-column instance for Mbar (0: none; beyond 12 rows
 // the columns no longer fit 256 VGPRs).
 int adj_reg_rows(int Mb) { return Mb <= 4 ? 4 : Mb <= 8 ? 8 : Mb <= 12 ? 12 : 0; }
-size_t adj_reg_lds(int MB, int nthr) {
-  return (size_t)(3 * MB * MB + 2 * MB) * 16 + (size_t)(MB * MB + MB) * 8 + (size_t)(nthr / 64) * 3 * MB * 8;
+size_t adj_reg_lds(int MB, int nthr, int rs) {
+  return (size_t)(3 * MB * MB + 2 * MB) * 2 * rs + (size_t)(MB * MB + MB) * rs + (size_t)(nthr / 64) * 3 * MB * rs;
 }
 
 // ------------------------------------------------------------------ lambda
 // One wave per (n, f, k), lanes over s: gB += sum_s glam Vk.
-__global__ void __launch_bounds__(256) k_adj_l1(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_l1(AdjArgs<R> a) {
   const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= (size_t)a.N * a.F * a.K) return;
   const int k = (int)(i % a.K), f = (int)((i / a.K) % a.F), n = (int)(i / ((size_t)a.F * a.K));
-  const double* g = a.glam + ((size_t)n * a.F + f) * a.T;
-  const double* v = a.Vk + ((size_t)n * a.K + k) * a.T;
-  double s = 0.0;
+  const R* g = a.glam + ((size_t)n * a.F + f) * a.T;
+  const R* v = a.Vk + ((size_t)n * a.K + k) * a.T;
+  R s = R(0.0);
   for (int t = lane; t < a.T; t += 64) s += g[t] * v[t];
   s = wave_sum(s);
   if (lane == 0) a.gB[i] += s;
@@ -845,16 +866,17 @@ __global__ void __launch_bounds__(256) k_adj_l1(AdjArgs a) {
 
 // One wave per (n, k, s), lanes over f:
 // gV += sum_f (B^ glamh + H1 P / lam^2 + H2 c / lam + Bk glam).
-__global__ void __launch_bounds__(256) k_adj_l2(AdjArgs a) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_l2(AdjArgs<R> a) {
   const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= (size_t)a.N * a.K * a.T) return;
   const int s = (int)(i % a.T), k = (int)((i / a.T) % a.K), n = (int)(i / ((size_t)a.K * a.T));
-  const double c = tapc(a.rm, n, s, a.T);
-  double acc = 0.0;
+  const R c = tapc<R>(a.rm, n, s, a.T);
+  R acc = R(0.0);
   for (int f = lane; f < a.F; f += 64) {
     const size_t fk = ((size_t)n * a.F + f) * a.K + k, fs = ((size_t)n * a.F + f) * a.T + s;
-    const double il = a.ilam[fs];
+    const R il = a.ilam[fs];
     acc += a.Bh[fk] * a.glamh[fs] + a.H1[fk] * a.P[fs] * il * il + a.H2[fk] * c * il + a.Bk[fk] * a.glam[fs];
   }
   acc = wave_sum(acc);
@@ -863,54 +885,60 @@ __global__ void __launch_bounds__(256) k_adj_l2(AdjArgs a) {
 
 }  // namespace
 
-size_t adj_images_lds(int Mb, int M) { return (size_t)(3 * Mb * Mb + 2 * M * Mb + Mb) * 16 + 64; }
-size_t adj_iss_lds_base(int Mb, int T) { return (size_t)(2 * Mb * Mb + 3 * Mb) * 16 + 2 * Mb * 8 + (size_t)T * 16; }
+// LDS of the per-bin adjoint kernels for real size rs (complex 2 rs).
+size_t adj_images_lds(int Mb, int M, int rs) { return (size_t)(3 * Mb * Mb + 2 * M * Mb + Mb) * 2 * rs + 64; }
+size_t adj_iss_lds_base(int Mb, int T, int rs) {
+  return (size_t)(2 * Mb * Mb + 3 * Mb) * 2 * rs + 2 * Mb * rs + (size_t)T * 2 * rs;
+}
 // gY and gphi in LDS only while three workgroups still fit a CU: a launch has
 // one workgroup per bin, and with fewer per CU the bins of a typical F (513)
 // need several rounds, which costs more than the global-memory traffic saved.
-bool adj_sweep_in_lds(int Mb, int T) { return adj_iss_lds_base(Mb, T) + (size_t)Mb * T * 24 <= kMaxLdsBytes / 3; }
-size_t adj_iss_lds(int Mb, int T) {
-  return adj_iss_lds_base(Mb, T) + (adj_sweep_in_lds(Mb, T) ? (size_t)Mb * T * 24 : 0);
+bool adj_sweep_in_lds(int Mb, int T, int rs) {
+  return adj_iss_lds_base(Mb, T, rs) + (size_t)Mb * T * 3 * rs <= kMaxLdsBytes / 3;
+}
+size_t adj_iss_lds(int Mb, int T, int rs) {
+  return adj_iss_lds_base(Mb, T, rs) + (adj_sweep_in_lds(Mb, T, rs) ? (size_t)Mb * T * 3 * rs : 0);
 }
 
 namespace {
-AdjArgs make_adj(const AdjPtrs& p, const Dims& d, double floor) {
-  AdjArgs a{};
-  a.X = static_cast<const Cd*>(p.X);
-  a.Wk = static_cast<const Cd*>(p.Wk);
-  a.Bk = p.Bk;
-  a.Vk = p.Vk;
-  a.Ws = static_cast<const Cd*>(p.Ws);
-  a.Bh = p.Bh;
-  a.Vh = p.Vh;
-  a.ilam = p.ilam;
-  a.P = p.P;
-  a.mu = p.mu;
-  a.gW = static_cast<Cd*>(p.gW);
-  a.gB = p.gB;
-  a.gV = p.gV;
-  a.gBh = p.gBh;
-  a.gVh = p.gVh;
-  a.gP = p.gP;
-  a.glam = p.glam;
-  a.glamh = p.glamh;
-  a.lamh = p.lamh;
-  a.q1 = p.q1;
-  a.q2 = p.q2;
-  a.G1 = p.G1;
-  a.G2 = p.G2;
-  a.H1 = p.H1;
-  a.H2 = p.H2;
-  a.part = p.part;
-  a.gS = p.gS;
-  a.gX = static_cast<Cd*>(p.gX);
+template <typename R>
+AdjArgs<R> make_adj(const AdjPtrs& p, const Dims& d, double floor) {
+  AdjArgs<R> a{};
+  a.X = static_cast<const Cx<R>*>(p.X);
+  a.Wk = static_cast<const Cx<R>*>(p.Wk);
+  a.Bk = static_cast<const R*>(p.Bk);
+  a.Vk = static_cast<const R*>(p.Vk);
+  a.Ws = static_cast<const Cx<R>*>(p.Ws);
+  a.Bh = static_cast<const R*>(p.Bh);
+  a.Vh = static_cast<const R*>(p.Vh);
+  a.ilam = static_cast<const R*>(p.ilam);
+  a.P = static_cast<const R*>(p.P);
+  a.mu = static_cast<const R*>(p.mu);
+  a.gW = static_cast<Cx<R>*>(p.gW);
+  a.gB = static_cast<R*>(p.gB);
+  a.gV = static_cast<R*>(p.gV);
+  a.gBh = static_cast<R*>(p.gBh);
+  a.gVh = static_cast<R*>(p.gVh);
+  a.gP = static_cast<R*>(p.gP);
+  a.glam = static_cast<R*>(p.glam);
+  a.glamh = static_cast<R*>(p.glamh);
+  a.lamh = static_cast<R*>(p.lamh);
+  a.q1 = static_cast<R*>(p.q1);
+  a.q2 = static_cast<R*>(p.q2);
+  a.G1 = static_cast<R*>(p.G1);
+  a.G2 = static_cast<R*>(p.G2);
+  a.H1 = static_cast<R*>(p.H1);
+  a.H2 = static_cast<R*>(p.H2);
+  a.part = static_cast<R*>(p.part);
+  a.gS = static_cast<R*>(p.gS);
+  a.gX = static_cast<Cx<R>*>(p.gX);
   a.status = p.status;
-  a.Y = static_cast<Cd*>(p.Y);
-  a.gY = static_cast<Cd*>(p.gY);
-  a.gphi = p.gphi;
-  a.ztape = static_cast<Cd*>(p.ztape);
-  a.dtape = p.dtape;
-  a.floor = floor;
+  a.Y = static_cast<Cx<R>*>(p.Y);
+  a.gY = static_cast<Cx<R>*>(p.gY);
+  a.gphi = static_cast<R*>(p.gphi);
+  a.ztape = static_cast<Cx<R>*>(p.ztape);
+  a.dtape = static_cast<R*>(p.dtape);
+  a.floor = (R)floor;
   a.F = d.F;
   a.T = d.T;
   a.M = d.M;
@@ -918,58 +946,71 @@ AdjArgs make_adj(const AdjPtrs& p, const Dims& d, double floor) {
   a.N = d.N;
   a.K = d.K;
   a.Mb = d.Mb;
-  a.sweep_lds = adj_sweep_in_lds(d.Mb, d.T) ? 1 : 0;
+  a.sweep_lds = adj_sweep_in_lds(d.Mb, d.T, (int)sizeof(R)) ? 1 : 0;
   a.rm = d.rm;
   return a;
 }
-}  // namespace
 
-// Host side: the images stage and one reverse iteration; launches go to stream s.
-hipError_t adj_images(const AdjPtrs& p, const Dims& d, const void* W, const void* gC, hipStream_t s) {
-  const AdjArgs a = make_adj(p, d, 0.0);
-  const size_t lds = adj_images_lds(d.Mb, d.M);
+template <typename R>
+hipError_t adj_images_t(const AdjPtrs& p, const Dims& d, const void* W, const void* gC, hipStream_t s) {
+  const AdjArgs<R> a = make_adj<R>(p, d, 0.0);
+  const size_t lds = adj_images_lds(d.Mb, d.M, (int)sizeof(R));
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_adj_images, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k_adj_images<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_adj_images, dim3(d.F), dim3(256), lds, s, a, static_cast<const Cd*>(W), static_cast<const Cd*>(gC));
+  hipLaunchKernelGGL(k_adj_images<R>, dim3(d.F), dim3(256), lds, s, a, static_cast<const Cx<R>*>(W),
+                     static_cast<const Cx<R>*>(gC));
   return hipGetLastError();
 }
 
-hipError_t adj_iteration(const AdjPtrs& p, const Dims& d, double floor, hipStream_t s) {
-  const AdjArgs a = make_adj(p, d, floor);
+template <typename R>
+hipError_t adj_iteration_t(const AdjPtrs& p, const Dims& d, double floor, hipStream_t s) {
+  const AdjArgs<R> a = make_adj<R>(p, d, floor);
+  const int rs = (int)sizeof(R);
   auto blocks = [](size_t n) { return dim3((unsigned)((n + 255) / 256)); };
   const size_t nkt = (size_t)d.N * d.K * d.T, nft = (size_t)d.N * d.F * d.T, nfk = (size_t)d.N * d.F * d.K;
   const size_t napply = (size_t)d.F * d.Mb * d.Mb + nfk + nkt;
-  hipLaunchKernelGGL(k_adj_rescale_part, dim3(d.F), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_rescale_final, dim3(d.Mb), dim3(64), 0, s, a);
-  hipLaunchKernelGGL(k_adj_rescale_apply, blocks(napply), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_v0, blocks(nft), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_v1, blocks(nkt * 64), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_v2, blocks(nft), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_b1, blocks(nfk * 64), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_b2, blocks(nft), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_rescale_part<R>, dim3(d.F), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_rescale_final<R>, dim3(d.Mb), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_adj_rescale_apply<R>, blocks(napply), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_v0<R>, blocks(nft), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_v1<R>, blocks(nkt * 64), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_v2<R>, blocks(nft), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_b1<R>, blocks(nfk * 64), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_b2<R>, blocks(nft), dim3(256), 0, s, a);
   const int MB = adj_reg_rows(d.Mb);
   if (MB > 0 && d.T <= 512) {  // register columns: one thread per frame
     const int nthr = (d.T + 63) / 64 * 64;
-    const size_t lds = adj_reg_lds(MB, nthr);
-    if (MB == 4) hipLaunchKernelGGL(k_adj_iss_reg<4>, dim3(d.F), dim3(nthr), lds, s, a);
-    if (MB == 8) hipLaunchKernelGGL(k_adj_iss_reg<8>, dim3(d.F), dim3(nthr), lds, s, a);
-    if (MB == 12) hipLaunchKernelGGL(k_adj_iss_reg<12>, dim3(d.F), dim3(nthr), lds, s, a);
-    hipLaunchKernelGGL(k_adj_demix_w, blocks((size_t)d.F * d.Mb * d.Mb * 64), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_adj_demix_x, blocks((size_t)d.M * d.F * d.T), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_adj_phi, blocks(nft), dim3(256), 0, s, a);
+    const size_t lds = adj_reg_lds(MB, nthr, rs);
+    if (MB == 4) hipLaunchKernelGGL((k_adj_iss_reg<R, 4>), dim3(d.F), dim3(nthr), lds, s, a);
+    if (MB == 8) hipLaunchKernelGGL((k_adj_iss_reg<R, 8>), dim3(d.F), dim3(nthr), lds, s, a);
+    if (MB == 12) hipLaunchKernelGGL((k_adj_iss_reg<R, 12>), dim3(d.F), dim3(nthr), lds, s, a);
+    hipLaunchKernelGGL(k_adj_demix_w<R>, blocks((size_t)d.F * d.Mb * d.Mb * 64), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_adj_demix_x<R>, blocks((size_t)d.M * d.F * d.T), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_adj_phi<R>, blocks(nft), dim3(256), 0, s, a);
   } else {
-    const size_t lds = adj_iss_lds(d.Mb, d.T);
+    const size_t lds = adj_iss_lds(d.Mb, d.T, rs);
     if (lds > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_adj_iss, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipError_t e = hipFuncSetAttribute((const void*)k_adj_iss<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_adj_iss, dim3(d.F), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_adj_iss<R>, dim3(d.F), dim3(256), lds, s, a);
   }
-  hipLaunchKernelGGL(k_adj_l1, blocks(nfk * 64), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_l2, blocks(nkt * 64), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_l1<R>, blocks(nfk * 64), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_l2<R>, blocks(nkt * 64), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+}  // namespace
+
+// Host side: the images stage and one reverse iteration (rs = 4: FP32, 8: FP64);
+// launches go to stream s.
+hipError_t adj_images(const AdjPtrs& p, const Dims& d, const void* W, const void* gC, int rs, hipStream_t s) {
+  return rs == 4 ? adj_images_t<float>(p, d, W, gC, s) : adj_images_t<double>(p, d, W, gC, s);
+}
+
+hipError_t adj_iteration(const AdjPtrs& p, const Dims& d, double floor, int rs, hipStream_t s) {
+  return rs == 4 ? adj_iteration_t<float>(p, d, floor, s) : adj_iteration_t<double>(p, d, floor, s);
 }
 
 }  // namespace ctfiss

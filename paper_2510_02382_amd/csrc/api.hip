@@ -695,7 +695,7 @@ struct AdjLayout {
       zt, dt, total;
 };
 
-AdjLayout adj_layout(const Dims& d, int n_iter) {
+AdjLayout adj_layout(const Dims& d, int n_iter, size_t rs) {
   AdjLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -703,8 +703,9 @@ AdjLayout adj_layout(const Dims& d, int n_iter) {
     off = align_up(off + bytes, kAlign);
     return o;
   };
-  const size_t w = (size_t)d.F * d.Mb * d.Mb * 16, b = (size_t)d.N * d.F * d.K * 8, v = (size_t)d.N * d.K * d.T * 8;
-  const size_t ft = (size_t)d.N * d.F * d.T * 8, yt = (size_t)d.F * d.Mb * d.T;
+  const size_t cs = 2 * rs;
+  const size_t w = (size_t)d.F * d.Mb * d.Mb * cs, b = (size_t)d.N * d.F * d.K * rs, v = (size_t)d.N * d.K * d.T * rs;
+  const size_t ft = (size_t)d.N * d.F * d.T * rs, yt = (size_t)d.F * d.Mb * d.T;
   L.ckW = take((n_iter + 1) * w);
   L.ckB = take((n_iter + 1) * b);
   L.ckV = take((n_iter + 1) * v);
@@ -723,53 +724,58 @@ AdjLayout adj_layout(const Dims& d, int n_iter) {
   L.G2 = take(v);
   L.H1 = take(b);
   L.H2 = take(b);
-  L.part = take((size_t)d.F * (d.Mb + d.N) * 8);
-  L.gS = take((size_t)d.Mb * 8);
-  L.Y = take(yt * 16);
-  L.gY = take(yt * 16);
-  L.gphi = take(yt * 8);
+  L.part = take((size_t)d.F * (d.Mb + d.N) * rs);
+  L.gS = take((size_t)d.Mb * rs);
+  L.Y = take(yt * cs);
+  L.gY = take(yt * cs);
+  L.gphi = take(yt * rs);
   L.zt = take(w);
-  L.dt = take((size_t)d.F * d.Mb * d.Mb * 8);
+  L.dt = take((size_t)d.F * d.Mb * d.Mb * rs);
   L.total = off;
   return L;
 }
 
-// Reverse mode is built for FP64 ISS contexts with the all-taps activation
-// rule, Mbar <= 32 and LDS for the per-bin adjoint kernels.
-bool adj_supported(const Dims& d) {
-  return d.Mb <= 32 && adj_iss_lds(d.Mb, d.T) <= kMaxLdsBytes && adj_images_lds(d.Mb, d.M) <= kMaxLdsBytes;
+// Reverse mode is built for FP32 and FP64 ISS contexts with the all-taps
+// activation rule, Mbar <= 32 and LDS for the per-bin adjoint kernels.
+bool adj_supported(const Dims& d, int rs) {
+  return d.Mb <= 32 && adj_iss_lds(d.Mb, d.T, rs) <= kMaxLdsBytes && adj_images_lds(d.Mb, d.M, rs) <= kMaxLdsBytes;
 }
 
 }  // namespace
 
 extern "C" {
 
-int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int32_t n_iter, size_t* bytes) {
+int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int precision, int32_t n_iter, size_t* bytes) {
   if (!bytes || n_iter < 1) return CTFISS_E_ARG;
+  if (precision != CTFISS_FP32 && precision != CTFISS_FP64) return CTFISS_E_UNSUPPORTED;
   Dims d;
-  const int st = validate_shape(shape, CTFISS_FP64, &d);
+  const int st = validate_shape(shape, precision, &d);
   if (st != CTFISS_OK) return st;
-  if (!adj_supported(d)) return CTFISS_E_UNSUPPORTED;
-  *bytes = adj_layout(d, n_iter).total;
+  const int rs = precision == CTFISS_FP32 ? 4 : 8;
+  if (!adj_supported(d, rs)) return CTFISS_E_UNSUPPORTED;
+  *bytes = adj_layout(d, n_iter, rs).total;
   return CTFISS_OK;
 }
 
 int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V0, const void* gC, void* gX,
                     void* gB0, void* gV0, void* aws, size_t aws_bytes) {
   if (!c || !B0 || !V0 || !gC || !gX || !aws || n_iter < 1) return CTFISS_E_ARG;
-  if (c->prec != CTFISS_FP64 || c->rule != CTFISS_RULE_ISS || c->vrule != CTFISS_VRULE_ALL_TAPS)
+  if (c->prec == CTFISS_MIXED || c->rule != CTFISS_RULE_ISS || c->vrule != CTFISS_VRULE_ALL_TAPS)
     return CTFISS_E_UNSUPPORTED;
   const Dims& d = c->d;
-  if (!adj_supported(d)) return CTFISS_E_UNSUPPORTED;
+  const bool f32 = c->prec == CTFISS_FP32;
+  const int rs = f32 ? 4 : 8;
+  if (!adj_supported(d, rs)) return CTFISS_E_UNSUPPORTED;
   if (!c->have_input) return CTFISS_E_ORDER;
-  const AdjLayout L = adj_layout(d, n_iter);
+  const AdjLayout L = adj_layout(d, n_iter, (size_t)rs);
   if (aws_bytes < L.total || (reinterpret_cast<uintptr_t>(aws) % kAlign) != 0) return CTFISS_E_WORKSPACE;
   char* ws = static_cast<char*>(aws);
   hipStream_t s = c->stream;
-  const size_t wb = (size_t)d.F * d.Mb * d.Mb * 16, bb = (size_t)d.N * d.F * d.K * 8, vb = (size_t)d.N * d.K * d.T * 8;
+  const size_t wb = (size_t)d.F * d.Mb * d.Mb * 2 * rs, bb = (size_t)d.N * d.F * d.K * rs,
+               vb = (size_t)d.N * d.K * d.T * rs;
   auto cp = [&](void* dst, const void* src, size_t n) { return hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, s); };
   // forward from (I, B0, V0) with the state saved before every iteration and after the last
-  hipError_t e = identity_t<double>(d, c->ptr.W, s);
+  hipError_t e = f32 ? identity_t<float>(d, c->ptr.W, s) : identity_t<double>(d, c->ptr.W, s);
   if (e == hipSuccess) e = cp(c->ptr.B, B0, bb);
   if (e == hipSuccess) e = cp(c->ptr.V, V0, vb);
   if (e == hipSuccess) e = launch_zero_status(c->ptr.status, s);
@@ -789,31 +795,31 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
   AdjPtrs p{};
   p.X = c->ptr.X;
   p.gW = ws + L.gW;
-  p.gB = reinterpret_cast<double*>(ws + L.gB);
-  p.gV = reinterpret_cast<double*>(ws + L.gV);
-  p.gBh = reinterpret_cast<double*>(ws + L.gBh);
-  p.gVh = reinterpret_cast<double*>(ws + L.gVh);
-  p.gP = reinterpret_cast<double*>(ws + L.gP);
-  p.glam = reinterpret_cast<double*>(ws + L.glam);
-  p.glamh = reinterpret_cast<double*>(ws + L.glamh);
-  p.lamh = reinterpret_cast<double*>(ws + L.lamh);
-  p.q1 = reinterpret_cast<double*>(ws + L.q1);
-  p.q2 = reinterpret_cast<double*>(ws + L.q2);
-  p.G1 = reinterpret_cast<double*>(ws + L.G1);
-  p.G2 = reinterpret_cast<double*>(ws + L.G2);
-  p.H1 = reinterpret_cast<double*>(ws + L.H1);
-  p.H2 = reinterpret_cast<double*>(ws + L.H2);
-  p.part = reinterpret_cast<double*>(ws + L.part);
-  p.gS = reinterpret_cast<double*>(ws + L.gS);
+  p.gB = ws + L.gB;
+  p.gV = ws + L.gV;
+  p.gBh = ws + L.gBh;
+  p.gVh = ws + L.gVh;
+  p.gP = ws + L.gP;
+  p.glam = ws + L.glam;
+  p.glamh = ws + L.glamh;
+  p.lamh = ws + L.lamh;
+  p.q1 = ws + L.q1;
+  p.q2 = ws + L.q2;
+  p.G1 = ws + L.G1;
+  p.G2 = ws + L.G2;
+  p.H1 = ws + L.H1;
+  p.H2 = ws + L.H2;
+  p.part = ws + L.part;
+  p.gS = ws + L.gS;
   p.gX = gX;
   p.status = c->ptr.status;
   p.Y = ws + L.Y;
   p.gY = ws + L.gY;
-  p.gphi = reinterpret_cast<double*>(ws + L.gphi);
+  p.gphi = ws + L.gphi;
   p.ztape = ws + L.zt;
-  p.dtape = reinterpret_cast<double*>(ws + L.dt);
+  p.dtape = ws + L.dt;
   // images: the first contributions to gW and gX
-  e = adj_images(p, d, c->ptr.W, gC, s);
+  e = adj_images(p, d, c->ptr.W, gC, rs, s);
   if (e == hipSuccess) e = hipMemsetAsync(p.gB, 0, bb, s);
   if (e == hipSuccess) e = hipMemsetAsync(p.gV, 0, vb, s);
   for (int k = n_iter - 1; k >= 0 && e == hipSuccess; --k) {
@@ -823,22 +829,30 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
     if (e == hipSuccess) e = cp(c->ptr.B, ws + L.ckB + k * bb, bb);
     if (e == hipSuccess) e = cp(c->ptr.V, ws + L.ckV + k * vb, vb);
     c->epoch = c->epoch % 0x1FFFFFFu + 1u;
-    if (e == hipSuccess) e = lambda_t<double>(d, c->ptr, false, s);
-    if (e == hipSuccess) e = wupdate_t<double>(c->rule, c->plan, d, c->ptr, false, false, c->epoch, s);
-    if (e == hipSuccess) e = nmfb_t<double>(d, c->ptr, c->floor, false, s);
-    if (e == hipSuccess) e = vpart_t<double>(d, c->vs, c->ptr, false, s);
-    if (e == hipSuccess) e = vfinal_t<double>(d, c->vs, c->ptr, c->floor, false, s);
+    if (f32) {
+      if (e == hipSuccess) e = lambda_t<float>(d, c->ptr, false, s);
+      if (e == hipSuccess) e = wupdate_t<float>(c->rule, c->plan, d, c->ptr, false, false, c->epoch, s);
+      if (e == hipSuccess) e = nmfb_t<float>(d, c->ptr, c->floor, false, s);
+      if (e == hipSuccess) e = vpart_t<float>(d, c->vs, c->ptr, false, s);
+      if (e == hipSuccess) e = vfinal_t<float>(d, c->vs, c->ptr, c->floor, false, s);
+    } else {
+      if (e == hipSuccess) e = lambda_t<double>(d, c->ptr, false, s);
+      if (e == hipSuccess) e = wupdate_t<double>(c->rule, c->plan, d, c->ptr, false, false, c->epoch, s);
+      if (e == hipSuccess) e = nmfb_t<double>(d, c->ptr, c->floor, false, s);
+      if (e == hipSuccess) e = vpart_t<double>(d, c->vs, c->ptr, false, s);
+      if (e == hipSuccess) e = vfinal_t<double>(d, c->vs, c->ptr, c->floor, false, s);
+    }
     if (e != hipSuccess) break;
     p.Wk = ws + L.ckW + k * wb;
-    p.Bk = reinterpret_cast<const double*>(ws + L.ckB + k * bb);
-    p.Vk = reinterpret_cast<const double*>(ws + L.ckV + k * vb);
+    p.Bk = ws + L.ckB + k * bb;
+    p.Vk = ws + L.ckV + k * vb;
     p.Ws = c->ptr.W;
-    p.Bh = static_cast<const double*>(c->ptr.B);
-    p.Vh = static_cast<const double*>(c->ptr.V);
-    p.ilam = static_cast<const double*>(c->ptr.ilam);
-    p.P = static_cast<const double*>(c->ptr.P);
-    p.mu = static_cast<const double*>(c->ptr.mu);
-    e = adj_iteration(p, d, c->floor, s);
+    p.Bh = c->ptr.B;
+    p.Vh = c->ptr.V;
+    p.ilam = c->ptr.ilam;
+    p.P = c->ptr.P;
+    p.mu = c->ptr.mu;
+    e = adj_iteration(p, d, c->floor, rs, s);
   }
   if (e == hipSuccess && gB0) e = cp(gB0, p.gB, bb);
   if (e == hipSuccess && gV0) e = cp(gV0, p.gV, vb);

@@ -104,34 +104,35 @@ hipError_t nmf_batch_t(int kind, const void* desc, const int* start, int nprob, 
                        int nzero, hipStream_t s);
 hipError_t launch_zero_status(int* status, hipStream_t s);
 
-// Reverse mode of the unrolled iterations (FP64; see adjoint.hip).
+// Reverse mode of the unrolled iterations (FP32 or FP64; see adjoint.hip).
+// Real arrays are of the context's real type, complex ones of its complex type.
 struct AdjPtrs {
   const void* X;                     // [M][F][T]
   const void* Wk;                    // state at the start of the iteration being reversed
-  const double* Bk;
-  const double* Vk;
+  const void* Bk;
+  const void* Vk;
   const void* Ws;                    // W after the sweep (before the rescale)
-  const double* Bh;                  // B after the basis update (before the rescale)
-  const double* Vh;                  // V after the activation update
-  const double* ilam;                // 1 / (Bk Vk)
-  const double* P;                   // tap-aligned powers of the swept rows
-  const double* mu;                  // row scales of the iteration
+  const void* Bh;                    // B after the basis update (before the rescale)
+  const void* Vh;                    // V after the activation update
+  const void* ilam;                  // 1 / (Bk Vk)
+  const void* P;                     // tap-aligned powers of the swept rows
+  const void* mu;                    // row scales of the iteration
   void* gW;                          // adjoints of the state: in, of the next state; out, of this one
-  double* gB;
-  double* gV;
-  double *gBh, *gVh, *gP, *glam, *glamh, *lamh, *q1, *q2, *G1, *G2, *H1, *H2, *part, *gS;  // scratch
+  void* gB;
+  void* gV;
+  void *gBh, *gVh, *gP, *glam, *glamh, *lamh, *q1, *q2, *G1, *G2, *H1, *H2, *part, *gS;  // scratch
   void* gX;                          // [M][F][T] accumulated
   int* status;
   void* Y;                           // [F][Mb][T] sweep scratch
   void* gY;
-  double* gphi;
+  void* gphi;
   void* ztape;                       // [F][Mb][Mb]
-  double* dtape;
+  void* dtape;
 };
-size_t adj_images_lds(int Mb, int M);
-size_t adj_iss_lds(int Mb, int T);
-hipError_t adj_images(const AdjPtrs& p, const Dims& d, const void* W, const void* gC, hipStream_t s);
-hipError_t adj_iteration(const AdjPtrs& p, const Dims& d, double floor, hipStream_t s);
+size_t adj_images_lds(int Mb, int M, int rs);
+size_t adj_iss_lds(int Mb, int T, int rs);
+hipError_t adj_images(const AdjPtrs& p, const Dims& d, const void* W, const void* gC, int rs, hipStream_t s);
+hipError_t adj_iteration(const AdjPtrs& p, const Dims& d, double floor, int rs, hipStream_t s);
 size_t images_lds(const Dims& d);
 size_t nll_lds(const Dims& d);
 

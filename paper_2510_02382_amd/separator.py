@@ -105,12 +105,12 @@ class Separator:
 
     def backward(self, n_iter: int, B0: torch.Tensor, V0: torch.Tensor, gC: torch.Tensor):
         """Gradients (gX, gB0, gV0) of a real loss through W = I, (B0, V0), n_iter
-        iterations and the source images, given gC = dL/dC (ctfiss_backward; FP64,
-        ISS, all-taps rule).  The input bound by set_input is X."""
+        iterations and the source images, given gC = dL/dC (ctfiss_backward; FP32 or
+        FP64, ISS, all-taps rule).  The input bound by set_input is X."""
         self._check(B0, (self.N, self.F, self.K), self.rdtype, "B0")
         self._check(V0, (self.N, self.K, self.T), self.rdtype, "V0")
         self._check(gC, (self.N, self.M, self.F, self.T), self.cdtype, "gC")
-        nbytes = b.ctfiss_adjoint_workspace_size(self._shape, n_iter)
+        nbytes = b.ctfiss_adjoint_workspace_size(self._shape, _PREC[self.precision], n_iter)
         aws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         if aws.data_ptr() % 256:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
