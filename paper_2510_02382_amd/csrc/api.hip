@@ -157,8 +157,16 @@ bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
   // Against a 16-lane group: half the frames per lane (fewer registers), and
   // for Mbar = 24 three waves per SIMD (a 16-lane group has 2 on two SIMDs and
   // 1 on the others); at <= 10 frames per lane two such workgroups share a CU.
+  // Mbar <= 8 (no or little frame stacking): 64-lane groups, a workgroup of at
+  // most 8 waves whose bin latency is the frame loop of each ISS step; half
+  // the frames per lane of a 32-lane group shortens it (measured at Mbar =
+  // 4, 6, 8 with T = 501: 25-30 us per launch against 30-33 us).
   if (rule == 0 && f32) {
     Plan p;
+    if (d.Mb <= 8 && plan_for(prec, rule, d, max_lds, 64, 1, 0, &p)) {
+      *out = p;
+      return true;
+    }
     if (plan_for(prec, rule, d, max_lds, 32, 1, 0, &p) && p.CPL <= 20) {
       *out = p;
       return true;

@@ -12,6 +12,7 @@ namespace ctfiss {
 constexpr int kMaxRows = 64;   // Mbar
 constexpr int kMaxSrc = 8;     // N
 constexpr int kMaxK = 64;      // K
+constexpr int kMaxNmfWaves = 16;  // waves of a basis-update workgroup
 constexpr int kMaxTeam = 8;    // workgroups sharing the frames of one bin
 
 // Device fault codes latched in the status word (first one wins).
@@ -68,8 +69,10 @@ struct RowMap {
 // ------------------------------------------------------------------ reductions
 // Sum over aligned groups of G lanes (G = 16, 32 or 64); every lane of the
 // group receives the total.  Within 16 lanes the butterfly uses DPP
-// (quad_perm xor1, quad_perm xor2, row_half_mirror, row_mirror), across rows
-// the LDS crossbar (ds_swizzle / bpermute, no LDS memory traffic).
+// (quad_perm xor1, quad_perm xor2, row_half_mirror, row_mirror); across rows
+// the gfx950 lane swaps (v_permlane16_swap: rows 0<->1 and 2<->3;
+// v_permlane32_swap: the two halves of the wave), plain VALU operations with
+// no trip through the LDS crossbar.
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
@@ -86,8 +89,35 @@ __device__ __forceinline__ float dpp(float v) { return dpp_f<CTRL>(v); }
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) { return dpp_d<CTRL>(v); }
 
-template <typename R>
-__device__ __forceinline__ R xor_lane(R v, int mask) { return __shfl_xor(v, mask, 64); }
+// v of this lane plus v of the same lane in the partner row (W = 16: the other
+// row of the row pair) or half (W = 32).  Swapping a register with itself
+// leaves the lower row's (half's) value in the first result and the upper
+// one's in the second on both sides, so both lanes form the same sum.
+template <int W>
+__device__ __forceinline__ unsigned swap_rows(unsigned& hi, unsigned v) {
+  if constexpr (W == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    hi = r[1];
+    return r[0];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    hi = r[1];
+    return r[0];
+  }
+}
+template <int W>
+__device__ __forceinline__ float add_rows(float v) {
+  unsigned hi;
+  const unsigned lo = swap_rows<W>(hi, __float_as_uint(v));
+  return __uint_as_float(lo) + __uint_as_float(hi);
+}
+template <int W>
+__device__ __forceinline__ double add_rows(double v) {
+  unsigned hl, hh;
+  const unsigned ll = swap_rows<W>(hl, (unsigned)__double2loint(v));
+  const unsigned lh = swap_rows<W>(hh, (unsigned)__double2hiint(v));
+  return __hiloint2double((int)lh, (int)ll) + __hiloint2double((int)hh, (int)hl);
+}
 
 template <int G, typename R>
 __device__ __forceinline__ R group_sum(R v) {
@@ -96,8 +126,8 @@ __device__ __forceinline__ R group_sum(R v) {
   v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp<0x141>(v);  // row_half_mirror
   v += dpp<0x140>(v);  // row_mirror
-  if constexpr (G >= 32) v += xor_lane(v, 16);
-  if constexpr (G >= 64) v += xor_lane(v, 32);
+  if constexpr (G >= 32) v = add_rows<16>(v);
+  if constexpr (G >= 64) v = add_rows<32>(v);
   return v;
 }
 

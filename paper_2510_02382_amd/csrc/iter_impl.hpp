@@ -100,32 +100,68 @@ __device__ __forceinline__ int per_bin(int v) {
   return v;
 }
 
+// Copies n elements from global memory into LDS.  Where a thread has several
+// elements, U loads are in flight per thread before their stores: a workgroup
+// then waits for one memory round trip per U elements per thread instead of
+// one per element, which is what bounds a bin's start-up when a workgroup
+// holds few rows and long weight rows.  (n and nthr are uniform.)
+template <int U, typename V, typename Ld, typename St>
+__device__ __forceinline__ void stage_lds(int n, int tid, int nthr, Ld ld, St st) {
+  if (U > 1 && n > nthr) {
+    for (int i0 = tid; i0 < n; i0 += nthr * U) {
+      V v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * nthr;
+        if (i < n) v[u] = ld(i);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * nthr;
+        if (i < n) st(i, v[u]);
+      }
+    }
+  } else {
+    for (int i = tid; i < n; i += nthr) st(i, ld(i));
+  }
+}
+
 // Stage 1: scaled W_f, zero-padded observation block and inverse variances into LDS.
 // The frames staged start at t0 (a team member's first frame; 0 otherwise).
-template <typename R>
+// U: loads in flight per thread (1 where the caller's registers are scarce).
+template <int U, typename R>
 __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid,
                          bool need_x, int t0 = 0) {
   const int nthr = blockDim.x;
   const int T = a.T, M = a.M, F = a.F, Mb = per_bin(a.rm.Mb), N = a.rm.N;
   const int LX = per_bin(L.lx), LP = per_bin(L.lp), Dm1 = a.D - 1, Lm1 = L.lmax - 1;
   const Cx<R>* Wf = a.W + (size_t)f * Mb * Mb;
-  for (int i = tid; i < Mb * Mb; i += nthr) {
-    Cx<R> w = Wf[i];
-    if (a.mu) {
-      const R m = a.mu[i / Mb];
-      w.x = w.x / m;
-      w.y = w.y / m;
-    }
-    s.w[i] = w;
-  }
-  for (int i = tid; i < (need_x ? M * LX : 0); i += nthr) {
-    const int m = i / LX, t = i - m * LX - Dm1 + t0;
-    s.x[i] = (t >= 0 && t < T) ? a.X[((size_t)m * F + f) * T + t] : Cx<R>{R(0), R(0)};
-  }
-  for (int i = tid; i < N * LP; i += nthr) {
-    const int n = i / LP, t = i - n * LP - Lm1 + t0;
-    s.phi[i] = (t >= 0 && t < T) ? a.ilam[((size_t)n * F + f) * T + t] : R(0);
-  }
+  stage_lds<U, Cx<R>>(
+      Mb * Mb, tid, nthr,
+      [&](int i) {
+        Cx<R> w = Wf[i];
+        if (a.mu) {
+          const R m = a.mu[i / Mb];
+          w.x = w.x / m;
+          w.y = w.y / m;
+        }
+        return w;
+      },
+      [&](int i, Cx<R> w) { s.w[i] = w; });
+  stage_lds<U, Cx<R>>(
+      need_x ? M * LX : 0, tid, nthr,
+      [&](int i) {
+        const int m = i / LX, t = i - m * LX - Dm1 + t0;
+        return (t >= 0 && t < T) ? a.X[((size_t)m * F + f) * T + t] : Cx<R>{R(0), R(0)};
+      },
+      [&](int i, Cx<R> v) { s.x[i] = v; });
+  stage_lds<U, R>(
+      N * LP, tid, nthr,
+      [&](int i) {
+        const int n = i / LP, t = i - n * LP - Lm1 + t0;
+        return (t >= 0 && t < T) ? a.ilam[((size_t)n * F + f) * T + t] : R(0);
+      },
+      [&](int i, R v) { s.phi[i] = v; });
   __syncthreads();
 }
 
@@ -461,17 +497,20 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
   unsigned long long* xb = TEAM ? a.xch + (size_t)f * team_words(Mb, L.lmax, L.team, sizeof(R)) : nullptr;
   bool wait_ok = true;
 
-  load_bin(a, s, L, f, tid, !a.yload, t0);
-
   // Y = W xbar equals the previous iteration's Y with rows divided by mu: the
   // sweep applies the same rank-1 steps to W and Y, and the rescale divides the
   // rows of both.  Carrying it replaces the demix contraction (Mbar^2 complex
-  // MACs per frame) by one read and one write of Y.
+  // MACs per frame) by one read and one write of Y.  A workgroup of at most
+  // four waves (a few rows: its bin's latency is not hidden by other waves)
+  // requests its rows before the staging loads, so that both share one round
+  // trip, where the rows are short enough to stay in registers meanwhile.
+  constexpr bool kRowsFirst = CPL * RPL * sizeof(R) <= 80;
+  const bool rows_first = kRowsFirst && a.yload && blockDim.x <= 256;
   Cx<R> y[RPL][CPL];
-  if (a.yload)
-    load_rows<R, G, CPL, RPL>(a, f, g, q, y, t0, nloc);
-  else
-    demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y, nloc);
+  if (rows_first) load_rows<R, G, CPL, RPL>(a, f, g, q, y, t0, nloc);
+  load_bin<kRowsFirst ? 32 / sizeof(R) : 1>(a, s, L, f, tid, !a.yload, t0);
+  if (a.yload && !rows_first) load_rows<R, G, CPL, RPL>(a, f, g, q, y, t0, nloc);
+  if (!a.yload) demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y, nloc);
 
   Cx<WR> wreg[RPL][WPL];
   R ph[RPL][CPL];  // weights of the lane's rows and frames, phi[n][t - l]
@@ -853,7 +892,7 @@ __device__ void ip_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& 
   Cx<R>* colw = s.fac + wave * Mb;  // this wave's column scratch
   bool bad = false;
 
-  load_bin(a, s, L, f, tid, true);
+  load_bin<1>(a, s, L, f, tid, true);
   // H = W^{-1} (one wave, partial pivoting); the pivot order goes to the q region
   if (wave == 0) {
     for (int e = lane; e < Mb * Mb; e += 64) H[e] = s.w[e];

@@ -203,7 +203,7 @@ hipError_t nmfb_t(const Dims& d, const Ptrs& ptr, double floor, bool apply_mu, h
   // one wave per 32 (FP32) or 16 (FP64) frames, at most 16 waves (they loop over longer signals)
   const int fpw = sizeof(R) == 4 ? 32 : 16;
   int waves = (d.T + fpw - 1) / fpw;
-  if (waves > 16) waves = 16;
+  if (waves > kMaxNmfWaves) waves = kMaxNmfWaves;
   dim3 grid((d.F + 15) / 16, d.N);
   hipLaunchKernelGGL(k_nmf_b<R>, grid, dim3(64 * waves), 0, s, a);
   return hipGetLastError();
@@ -345,7 +345,7 @@ int fill_ndesc(void* dst, int kind, const Dims& d, const VSplit& vs, const Ptrs&
     n.a = make_nargs<R>(d, VSplit{1, d.F}, ptr, floor, false, apply_mu);
     const int fpw = sizeof(R) == 4 ? 32 : 16;
     int waves = (d.T + fpw - 1) / fpw;
-    if (waves > 16) waves = 16;
+    if (waves > kMaxNmfWaves) waves = kMaxNmfWaves;
     n.gx = (d.F + 15) / 16;
     n.gy = d.N;
     n.extra = waves;

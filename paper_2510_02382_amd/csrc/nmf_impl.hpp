@@ -72,6 +72,37 @@ __device__ __forceinline__ typename Acc4<R>::type acc_zero() {
   return z;
 }
 
+// Sums the 16x16 accumulator tiles (num, den per K tile) of the workgroup's
+// first nwave waves in wave order into red[c][kt] (red[c][kt][v][l]: register
+// v of lane l).  Each wave writes its tile of one (kt, c) to LDS once, then
+// thread e adds element e of every wave's tile, wave 0 first: the same sums as
+// adding the tiles wave after wave, with two barriers per tile instead of one
+// per wave.  Every thread of the workgroup must call it.
+template <typename R, int KT, int NW>
+__device__ __forceinline__ void sum_wave_tiles(const typename Acc4<R>::type (&num)[KT],
+                                               const typename Acc4<R>::type (&den)[KT], int nkt, int nwave,
+                                               R (&tiles)[NW][4][64], R (&red)[2][KT][4][64]) {
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt) {
+    if (kt >= nkt) break;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (wave < nwave) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tiles[wave][v][l] = c ? den[kt][v] : num[kt][v];
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        R acc = R(0);
+        for (int w = 0; w < nwave; ++w) acc += tiles[w][e >> 6][e & 63];
+        red[c][kt][e >> 6][e & 63] = acc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // 1/lambda_{n,f,t} with lambda = (b / mu^2) v: one 16 (bins) x 16 (frames) tile
 // per wave, K/4 MFMA steps.  Grid (ceil(T/64), ceil(F/16), N), 4 waves per
 // workgroup covering 64 frames.
@@ -119,13 +150,14 @@ __global__ void __launch_bounds__(256) k_lambda(NmfArgs<R> a) { lambda_block<R>(
 // Basis update, Eq. (17), with t' = t - l:
 //   num_{f,k} = sum_t' P_{f,t'} v_{k,t'} / lambda_{f,t'}^2,  den_{f,k} = sum_t' C_{t'} v_{k,t'} / lambda_{f,t'},
 //   C_{t'} = #{l < L_n : t' + l < T};  b <- max((b / mu^2) sqrt(num / den), floor).
-// (F x T)(T x K) contractions on MFMA: one workgroup per 16 bins, its 4 waves
+// (F x T)(T x K) contractions on MFMA: one workgroup per 16 bins, its waves
 // split the frames, partial tiles are summed in LDS in wave order.
 template <typename R>
 __device__ __forceinline__ void nmfb_block(const NmfArgs<R>& a, const int bx, const int by, const int nwe) {
   constexpr int KT = kMaxK / 16;
   constexpr int ST = sizeof(R) == 4 ? 8 : 4;  // MFMA steps (4 frames each) per wave and round
   __shared__ R red[2][KT][4][64];
+  __shared__ R tiles[kMaxNmfWaves][4][64];
   const int T = a.T, K = a.K, F = a.F;
   // nwe: waves that share the frames (a batched launch may carry more, which stay idle)
   const int wave = threadIdx.x >> 6, nwave = nwe, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
@@ -168,19 +200,7 @@ __device__ __forceinline__ void nmfb_block(const NmfArgs<R>& a, const int bx, co
       }
     }
   }
-  // sum the per-wave tiles in wave order
-  for (int w = 0; w < nwave; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          red[0][kt][v][l] = (w == 0 ? R(0) : red[0][kt][v][l]) + num[kt][v];
-          red[1][kt][v][l] = (w == 0 ? R(0) : red[1][kt][v][l]) + den[kt][v];
-        }
-    }
-    __syncthreads();
-  }
+  sum_wave_tiles<R, KT, kMaxNmfWaves>(num, den, nkt, nwave, tiles, red);
   if (wave != 0) return;
   const R sc = pending_scale(a, n);
   bool bad = false;
@@ -215,6 +235,7 @@ __device__ __forceinline__ void vpart_block(const NmfArgs<R>& a, const int bx, c
   constexpr int KT = kMaxK / 16;
   constexpr int KS = kMaxK / 4;
   __shared__ R red[2][KT][4][64];
+  __shared__ R tiles[4][4][64];
   const int T = a.T, K = a.K, F = a.F;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
   const int n = bz, ch = by, t0 = bx * 16;
@@ -271,18 +292,7 @@ __device__ __forceinline__ void vpart_block(const NmfArgs<R>& a, const int bx, c
       }
     }
   }
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          red[0][kt][v][l] = (w == 0 ? R(0) : red[0][kt][v][l]) + num[kt][v];
-          red[1][kt][v][l] = (w == 0 ? R(0) : red[1][kt][v][l]) + den[kt][v];
-        }
-    }
-    __syncthreads();
-  }
+  sum_wave_tiles<R, KT, 4>(num, den, nkt, 4, tiles, red);
   if (wave != 0 || tb >= T) return;
 #pragma unroll
   for (int kt = 0; kt < KT; ++kt) {
