@@ -235,7 +235,6 @@ __device__ __forceinline__ void vpart_block(const NmfArgs<R>& a, const int bx, c
   constexpr int KT = kMaxK / 16;
   constexpr int KS = kMaxK / 4;
   __shared__ R red[2][KT][4][64];
-  __shared__ R tiles[4][4][64];
   const int T = a.T, K = a.K, F = a.F;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
   const int n = bz, ch = by, t0 = bx * 16;
@@ -292,7 +291,21 @@ __device__ __forceinline__ void vpart_block(const NmfArgs<R>& a, const int bx, c
       }
     }
   }
-  sum_wave_tiles<R, KT, 4>(num, den, nkt, 4, tiles, red);
+  // the four waves' tiles in wave order (K tiles in use only)
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        if (kt >= nkt) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          red[0][kt][v][l] = (w == 0 ? R(0) : red[0][kt][v][l]) + num[kt][v];
+          red[1][kt][v][l] = (w == 0 ? R(0) : red[1][kt][v][l]) + den[kt][v];
+        }
+      }
+    }
+    __syncthreads();
+  }
   if (wave != 0 || tb >= T) return;
 #pragma unroll
   for (int kt = 0; kt < KT; ++kt) {
