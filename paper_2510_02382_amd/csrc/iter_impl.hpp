@@ -656,7 +656,13 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_mi
     k_iss(IterArgs<R> a, IterLds L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
-  for (int f = next_bin(a, s); f < a.F; f = next_bin(a, s)) iss_bin<R, G, CPL, RPL, false, WX>(a, s, L, f);
+  // Bins dealt out round-robin over the resident workgroups: every bin costs
+  // the same, so this balances as well as a shared counter would, without a
+  // device-scope atomic round trip per bin.
+  for (int f = blockIdx.x; f < a.F; f += gridDim.x) {
+    if (f != (int)blockIdx.x) __syncthreads();  // the previous bin's LDS traffic is over
+    iss_bin<R, G, CPL, RPL, false, WX>(a, s, L, f);
+  }
 }
 
 // Team launch: the persistent workgroups take (bin, member) items in order,
