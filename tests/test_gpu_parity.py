@@ -126,6 +126,24 @@ def test_one_iteration_matches_oracle(case, rule, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fewer_workgroups_than_bins(precision, monkeypatch):
+    """With fewer persistent W-update workgroups than bins (CTFISS_WBLOCKS=2 for
+    9 bins) each workgroup takes several bins in turn.  A bin's arithmetic does
+    not depend on which workgroup runs it, so the results equal the default
+    launch's (one bin per workgroup) bit for bit, and the oracle's."""
+    X, B0, V0, W0, D, taps = make_case("c0_like", seed=6)
+    ref = gpu_run(X, D, taps, B0, V0, W0, 2, precision)
+    monkeypatch.setenv("CTFISS_WBLOCKS", "2")
+    g = gpu_run(X, D, taps, B0, V0, W0, 2, precision)
+    assert g["status"] == 0 and ref["status"] == 0
+    for k in ("W", "B", "V", "C"):
+        assert np.array_equal(g[k], ref[k]), k
+    r = oracle_run(X, D, taps, B0, V0, W0, 2, precision)
+    for k in ("W", "B", "V", "C"):
+        assert rel(g[k], r[k]) < 10 * TOL1[precision], (k, rel(g[k], r[k]))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", ["c0_like", "three_src", "ragged"])
 def test_paper_tap0_rule_matches_oracle(case, precision):
     X, B0, V0, W0, D, taps = make_case(case, seed=4)
