@@ -8,10 +8,11 @@ initialisation, 100 iterations (ISS sweep, basis and activation updates,
 rescale) and the source images, with every input already in HBM.
 
 value = F*T*iterations / second of the FP32 ISS path.  Alongside, the same
-mixture is separated by the FP64 ISS path and by the IP baseline; the FP32
-ISS images are checked against the FP64 ISS images (the FP64 path itself is
-checked against the CPU oracle by the test-suite).  The CPU oracle is timed
-on a bounded sample for the cpu_baseline field.
+mixture is separated by the mixed-precision and FP64 ISS paths and by the IP
+baseline.  The FP64 CPU oracle then runs all 100 iterations of the same
+mixture (its W update over bin chunks on a pool of host threads): every GPU
+path's images are compared with it per source (the accuracy field; the FP32
+target is 1e-4), and its wall time is the cpu_baseline.
 """
 from __future__ import annotations
 
@@ -26,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_FP64_TFLOPS = 78.6         # MI355X published FP64 vector and matrix peak
+PEAK_HBM_TBS = 8.0              # MI355X published HBM3E bandwidth
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iss_c1_traffic.json")
 KERNEL_SOURCES = ["paper_2510_02382_amd/csrc/iter_impl.hpp", "paper_2510_02382_amd/csrc/common.hpp"]
 
@@ -38,13 +41,36 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def iss_flops_per_unit(Mbar: int, n_iter: int) -> float:
-    """Algorithmic flops of the W-update kernel per bin and frame, averaged over
-    the launches of one n_iter-iteration run: the ISS sweep 20 Mbar^2 every
-    iteration (per row pair and step: a_p 10, d_p 2, rank-1 update 8) and the
-    demix Y = W xbar, 8 Mbar^2, on the first iteration only (later iterations
-    carry Y, whose rows get the same operations as W's)."""
+def iss_flops_per_unit(Mbar: int) -> float:
+    """Algorithmic flops of the ISS W update per bin, frame and iteration: the demix
+    y = W xbar, 8 Mbar^2, and the sweep, 20 Mbar^2 (per row pair and step: a_p 10, d_p 2,
+    rank-1 update 8) -- 28 Mbar^2 in all."""
+    return 28 * Mbar * Mbar
+
+
+def iss_executed_flops_per_unit(Mbar: int, n_iter: int) -> float:
+    """Flops the kernel executes per unit, averaged over the launches of one n_iter-iteration
+    run: the sweep every iteration, the demix on the first only (later iterations carry Y,
+    whose rows get the same operations as W's)."""
     return 20 * Mbar * Mbar + 8 * Mbar * Mbar / n_iter
+
+
+def iss_bytes_per_unit(M: int, N: int, Mbar: int, T: int) -> float:
+    """HBM bytes the FP32 ISS W update must move per bin, frame and iteration with a bin's
+    rows resident on chip: X read (8 M), 1/lambda in and P out (8 N), W in and out
+    (16 Mbar^2 / T)."""
+    return 8 * M + 8 * N + 16 * Mbar * Mbar / T
+
+
+def cpu_info() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def log(msg: str) -> None:
@@ -81,17 +107,27 @@ def time_path(torch, Separator, wl, Xc, B0, V0, precision, rule, steps, warmup, 
     return dt, C, status, stats
 
 
-def cpu_baseline(wl, X, B0, V0, n_iter=10):
+def oracle_reference(wl, X, B0, V0, rule="iss"):
+    """The FP64 oracle's whole run of the workload (all iterations, original FP64 data), the W
+    update of bin chunks over a pool of host threads with BLAS pinned to one thread each.
+    Returns (images, wall seconds, threads)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import ctf_iss as o
+    from oracle import threaded as oth
+    workers = oth.default_workers()
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        o.run(X, wl.D, wl.row_taps, B0, V0, n_iter)
+        W, _, _ = oth.run(X, wl.D, wl.row_taps, B0, V0, wl.n_iter, rule=o.ISS if rule == "iss" else o.IP,
+                          workers=workers)
         dt = time.perf_counter() - t0
-    return {"value": wl.F * wl.T * n_iter / dt, "unit": "F·T·iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_iter} ISS iterations of the full mixture (F={wl.F}, T={wl.T}, Mbar={wl.mbar}) "
-                      f"in FP64 NumPy on 1 thread, {dt:.1f} s"}
+    return o.source_images(W, X, wl.D, wl.row_taps), dt, workers
+
+
+def per_source_err(C, Cref):
+    import numpy as np
+    C = np.asarray(C, dtype=np.complex128)
+    return [float(np.linalg.norm(C[n] - Cref[n]) / np.linalg.norm(Cref[n])) for n in range(Cref.shape[0])]
 
 
 def batched_bench(args) -> int:
@@ -283,7 +319,7 @@ def precision_bench(args) -> int:
     value = units * args.steps / dt
     n_iss, ms_iss = stats[0]
     avg_iss_ms = ms_iss / max(n_iss, 1)
-    flops_launch = wl.F * wl.T * iss_flops_per_unit(wl.mbar, wl.n_iter)
+    flops_launch = wl.F * wl.T * iss_flops_per_unit(wl.mbar)
     achieved = flops_launch / (avg_iss_ms * 1e-3) / 1e12
     _, _, _, allstats = time_path(torch, Separator, wl, Xc, B0, V0, "mixed", "iss", 1, 0, profile=-1)
     names = ["w_update_iss", "v_partial", "v_final_mu", "final_rescale", "images", "lambda", "basis_update"]
@@ -366,7 +402,7 @@ def adjoint_bench(args) -> int:
     typed = {cd: [(X.to(cd), B0.to(rd), V0.to(rd), img.to(cd)) for X, B0, V0, img in mixes]
              for cd, rd in ((torch.complex64, torch.float32), (torch.complex128, torch.float64))}
 
-    def step(cd=torch.complex128, sample=None):
+    def step(cd=torch.complex128, sample=None, check=False):
         out = None
         cur = torch.cuda.current_stream(dev)
         for st in streams:
@@ -376,7 +412,7 @@ def adjoint_bench(args) -> int:
             with torch.cuda.stream(st):
                 Xg = X.clone().requires_grad_(True)
                 Bg = B0.clone().requires_grad_(True)
-                C = separate(Xg, Bg, V0, wl.D, wl.row_taps, wl.n_iter)
+                C = separate(Xg, Bg, V0, wl.D, wl.row_taps, wl.n_iter, check=check)
                 loss = ((C - img).abs() ** 2).mean()
                 loss.backward()
                 if i == 0:
@@ -397,6 +433,11 @@ def adjoint_bench(args) -> int:
 
     dt, first = timed_steps(torch.complex64)
     dt64, first64 = timed_steps(torch.complex128)
+    # the timed steps leave the device status unread (a read synchronises); one more step
+    # per precision reads it after every forward and reverse pass and raises on a fault
+    step(torch.complex64, check=True)
+    step(torch.complex128, check=True)
+    torch.cuda.synchronize()
     units = nmix * wl.F * wl.T * wl.n_iter
     value = units / dt
     # forward alone, for the split
@@ -513,7 +554,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--side-steps", type=int, default=2, help="timed steps of the FP64 and IP paths")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle (then no accuracy against the oracle either)")
+    ap.add_argument("--no-ip-oracle", action="store_true", help="skip the IP oracle run (c1)")
     ap.add_argument("--no-side", action="store_true", help="time only the FP32 ISS path")
     ap.add_argument("--batched", action="store_true",
                     help="time the batch of uneven mixtures instead of the single long mixture")
@@ -575,7 +618,10 @@ def main() -> int:
     value = units * args.steps / dt
     n_iss, ms_iss = stats[0]
     avg_iss_ms = ms_iss / max(n_iss, 1)
-    flops_launch = wl.F * wl.T * iss_flops_per_unit(wl.mbar, wl.n_iter)
+    units_launch = wl.F * wl.T
+    flops_launch = units_launch * iss_flops_per_unit(wl.mbar)
+    exec_flops_launch = units_launch * iss_executed_flops_per_unit(wl.mbar, wl.n_iter)
+    bytes_launch = units_launch * iss_bytes_per_unit(wl.M, wl.N, wl.mbar, wl.T)
     achieved = flops_launch / (avg_iss_ms * 1e-3) / 1e12
     log("per-kernel breakdown (separate profiled steps, every kernel timed)")
     _, _, _, allstats = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", 1, 0, profile=-1)
@@ -590,26 +636,35 @@ def main() -> int:
             tr = json.load(f)
         if tr.get("kernel_hash") == kernel_hash():
             traffic = tr.get("bytes_per_launch")
+    hbm_bytes = traffic if traffic is not None else bytes_launch
+    hbm_gbs = hbm_bytes / (avg_iss_ms * 1e-3) / 1e9
 
     side = {}
+    images = {"iss_fp32": C32}
     if not args.no_side:
         log("timing FP64 ISS")
         dt64, C64, st64, _ = time_path(torch, Separator, wl, Xc, B0, V0, "fp64", "iss", args.side_steps, 1)
-        rel = float(torch.linalg.norm((C32.to(torch.complex128) - C64).flatten()) / torch.linalg.norm(C64.flatten()))
         side["iss_fp64"] = {"value": units * args.side_steps / dt64, "ms_per_step": dt64 / args.side_steps * 1e3,
                             "status": st64}
-        side["iss_fp32_images_rel_err_vs_fp64"] = rel
-        log(f"FP64 ISS: {dt64 / args.side_steps * 1e3:.3f} ms/step; FP32 vs FP64 images rel {rel:.2e}")
+        images["iss_fp64"] = C64
+        log(f"FP64 ISS: {dt64 / args.side_steps * 1e3:.3f} ms/step")
         log("timing mixed-precision ISS")
         dtm, Cm, stm, _ = time_path(torch, Separator, wl, Xc, B0, V0, "mixed", "iss", args.side_steps, 1)
-        relm = float(torch.linalg.norm((Cm.to(torch.complex128) - C64).flatten()) / torch.linalg.norm(C64.flatten()))
         side["iss_mixed"] = {"value": units * args.side_steps / dtm, "ms_per_step": dtm / args.side_steps * 1e3,
-                             "status": stm, "images_rel_err_vs_fp64": relm}
-        log(f"mixed ISS: {dtm / args.side_steps * 1e3:.3f} ms/step; images rel {relm:.2e} vs FP64")
+                             "status": stm}
+        images["iss_mixed"] = Cm
+        log(f"mixed ISS: {dtm / args.side_steps * 1e3:.3f} ms/step")
         log("timing FP64 IP")
-        dtip, Cip, stip, _ = time_path(torch, Separator, wl, Xc, B0, V0, "fp64", "ip", args.side_steps, 1)
+        dtip, Cip, stip, ipstats = time_path(torch, Separator, wl, Xc, B0, V0, "fp64", "ip", args.side_steps, 1,
+                                             profile=1)
+        n_ip, ms_ip = ipstats[0]
+        avg_ip_ms = ms_ip / max(n_ip, 1)
+        ip_flops_launch = units_launch * wl.mbar * (4 * wl.mbar ** 2 + 11 * wl.mbar ** 3 / wl.T + 8 * wl.mbar)
         side["ip_fp64"] = {"value": units * args.side_steps / dtip, "ms_per_step": dtip / args.side_steps * 1e3,
-                           "status": stip}
+                           "status": stip, "k_ip_avg_us": avg_ip_ms * 1e3,
+                           "k_ip_tflops": ip_flops_launch / (avg_ip_ms * 1e-3) / 1e12,
+                           "k_ip_frac_fp64_peak": ip_flops_launch / (avg_ip_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+        images["ip_fp64"] = Cip
         log(f"FP64 IP: {dtip / args.side_steps * 1e3:.3f} ms/step, status {stip}")
         log("timing FP32 IP")
         dtip32, _, stip32, _ = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "ip", 1, 0)
@@ -620,9 +675,29 @@ def main() -> int:
         side["speedup_iss_fp64_vs_ip_fp64"] = side["iss_fp64"]["value"] / side["ip_fp64"]["value"]
 
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(wl, mix.X, B0n, V0n)
+        log("FP64 oracle (ISS), all iterations of the full mixture, bin chunks over host threads")
+        Cref, dto, workers = oracle_reference(wl, mix.X, B0n, V0n, "iss")
+        log(f"  oracle ISS: {dto:.1f} s on {workers} threads")
+        accuracy = {"reference": f"FP64 oracle, {wl.n_iter} ISS iterations of the full mixture on the original FP64 "
+                                 f"data", "target": 1e-4, "per_source_rel_err": {}}
+        for k in ("iss_fp32", "iss_mixed", "iss_fp64"):
+            if k in images:
+                accuracy["per_source_rel_err"][k] = per_source_err(images[k].cpu().numpy(), Cref)
+        accuracy["iss_fp32_meets_target"] = max(accuracy["per_source_rel_err"]["iss_fp32"]) <= 1e-4
+        cpu = {"value": units / dto, "unit": "F·T·iters/s", "cores": workers, "kind": "oracle",
+               "sample": f"all {wl.n_iter} ISS iterations of the full mixture (F={wl.F}, T={wl.T}, Mbar={wl.mbar}) "
+                         f"in FP64 NumPy: the oracle's functions, the W update of bin chunks on a pool of {workers} "
+                         f"threads, BLAS on 1 thread each; {dto:.1f} s",
+               "cpu_model": cpu_info(), "os_cpu_count": os.cpu_count()}
+        if "ip_fp64" in images and not args.no_ip_oracle:
+            log("FP64 oracle (IP), all iterations of the full mixture")
+            Cref_ip, dtoi, _ = oracle_reference(wl, mix.X, B0n, V0n, "ip")
+            log(f"  oracle IP: {dtoi:.1f} s")
+            accuracy["per_source_rel_err"]["ip_fp64_vs_ip_oracle"] = per_source_err(images["ip_fp64"].cpu().numpy(),
+                                                                                    Cref_ip)
+            cpu["ip_oracle_value"] = units / dtoi
 
     out = {
         "metric": "F·T·iters/s ISS vs IP vs FP64-ISS at rel err ≤1e-4; HBM GB/s fraction",
@@ -642,10 +717,19 @@ def main() -> int:
                    "F": wl.F, "T": wl.T, "Mbar": wl.mbar, "K": wl.K, "iterations": wl.n_iter},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
-                     "kernel": "k_iss (W update: ISS sweep on the carried Y + tap-aligned powers, one launch per iteration)",
-                     "avg_launch_us": avg_iss_ms * 1e3, "flops_per_launch": flops_launch},
+                     "kernel": "k_iss (W update: ISS sweep on the carried Y + tap-aligned powers, one launch per "
+                               "iteration)",
+                     "avg_launch_us": avg_iss_ms * 1e3, "flops_per_launch": flops_launch,
+                     "flops_per_unit": iss_flops_per_unit(wl.mbar), "units_per_launch": units_launch,
+                     "executed_flops_per_launch": exec_flops_launch,
+                     "frac_executed": exec_flops_launch / (avg_iss_ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "hbm_gbs": hbm_gbs, "hbm_frac": hbm_gbs / (PEAK_HBM_TBS * 1e3),
+                     "hbm_bytes_source": "rocprofv3 counters (FETCH_SIZE, WRITE_SIZE)" if traffic is not None
+                     else "algorithmic bytes"},
         "kernel_avg_ms": kernel_ms,
         "status": st32,
+        "accuracy": accuracy,
         "side_by_side": side,
         "cpu_baseline": cpu,
     }

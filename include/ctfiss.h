@@ -41,9 +41,14 @@
  * W_f in the output stage, a non-finite multiplicative update) are latched in
  * a device status word and reported by ctfiss_sync_status(); so is a team of
  * workgroups sharing a bin whose members did not all publish their partial
- * sums within the wait bound (code 6; the launch still completes).  No exceptions
- * cross this interface.  One context per stream; calls on one context must
- * not overlap from several host threads.
+ * sums within the wait bound (code 6; the launch still completes, its results
+ * are not valid).  Team launches (ctfiss_get_plan reports team > 1) size their
+ * grid so that all members of a bin are resident at once on an otherwise idle
+ * device; kernels of other streams occupying the device meanwhile can delay
+ * members past that bound, so run team contexts where they do not share the
+ * device with long-running work, or check the status.  No exceptions cross
+ * this interface.  One context per stream; calls on one context must not
+ * overlap from several host threads.
  */
 #ifndef CTFISS_H
 #define CTFISS_H
@@ -126,8 +131,14 @@ int ctfiss_set_state(ctfiss_ctx* ctx, const void* W, const void* B, const void* 
 /* Enqueue n_iter >= 0 iterations.  One iteration is: W update for every row r
  * in ascending order (ISS or IP), multiplicative update of b (Eq. (17)), of v
  * (Eq. (18) or ALL_TAPS), each followed by the floor clamp, and the scale
- * normalisation of Eqs. (19)-(21).  Requires set_input and set_state. */
-int ctfiss_iterate(ctfiss_ctx* ctx, int32_t n_iter);
+ * normalisation of Eqs. (19)-(21).  Requires set_input and set_state.
+ * nll_host: NULL, or a host array of n_iter doubles that receives the
+ * negative log-likelihood of Eq. (5) (constant dropped, as ctfiss_nll) at the
+ * state each iteration leaves, rescale applied; computed on the device in
+ * FP64.  A traced call synchronises the stream (once per 256 iterations and
+ * at its end), runs eagerly in graph mode, and leaves the same state, bit for
+ * bit, as an untraced call. */
+int ctfiss_iterate(ctfiss_ctx* ctx, int32_t n_iter, double* nll_host);
 
 /* Graph mode (enable != 0): ctfiss_iterate captures the launches of an
  * n_iter-iteration call once into a HIP graph (one per n_iter and per
@@ -149,11 +160,16 @@ int ctfiss_get_plan(ctfiss_ctx* ctx, int32_t* G, int32_t* cpl, int32_t* rpl, int
  * one warm-up run), timed with events; the fastest becomes the context's plan
  * and is cached for the process, per (precision, rule, Mbar, M, D, N, largest
  * tap count, T rounded up to 32), so that contexts created later for such a
- * shape start with it (CTFISS_PLAN in the environment still overrides).  The
- * state is restored afterwards and the status word cleared.  Synchronises;
- * allocates a state-sized stream-ordered buffer for the duration of the call.
- * Not in graph mode (CTFISS_E_UNSUPPORTED). */
-int ctfiss_autotune(ctfiss_ctx* ctx, int32_t trials);
+ * shape start with it (CTFISS_PLAN in the environment still overrides).
+ * scratch: caller-owned device buffer of ctfiss_autotune_scratch_size() bytes
+ * (256-byte aligned) that holds a copy of the state (W, B, V) during the call;
+ * the state is restored from it afterwards.  Synchronises; allocates nothing.
+ * If a device fault is already latched when it is called, it returns
+ * CTFISS_E_NUMERIC, times nothing and leaves the fault latched; a candidate
+ * whose runs latch a fault is skipped (and that fault cleared).  Not in graph
+ * mode (CTFISS_E_UNSUPPORTED). */
+int ctfiss_autotune_scratch_size(ctfiss_ctx* ctx, size_t* bytes);
+int ctfiss_autotune(ctfiss_ctx* ctx, int32_t trials, void* scratch, size_t scratch_bytes);
 
 /* Forget every plan ctfiss_autotune cached (contexts created afterwards take
  * the built-in rule again; existing contexts keep their plans). */
@@ -189,7 +205,11 @@ int ctfiss_nll(ctfiss_ctx* ctx, double* out);
  * CTFISS_E_UNSUPPORTED).  aws: device workspace of
  * ctfiss_adjoint_workspace_size() bytes (256-byte aligned), scratch for the
  * call.  The context ends in the forward's final state, as after
- * ctfiss_iterate.  Enqueued on the context's stream. */
+ * ctfiss_iterate.  Enqueued on the context's stream without waiting (so that
+ * the reverse passes of several contexts on several streams overlap): the
+ * status word is cleared where the forward restarts from (I, B0, V0), and a
+ * numeric fault of the forward or the reverse pass stays latched for
+ * ctfiss_sync_status, which the caller must read before using gX, gB0, gV0. */
 int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int precision, int32_t n_iter, size_t* bytes);
 int ctfiss_backward(ctfiss_ctx* ctx, int32_t n_iter, const void* B0, const void* V0, const void* gC, void* gX,
                     void* gB0, void* gV0, void* aws, size_t aws_bytes);

@@ -17,7 +17,7 @@ from .separator import Separator
 
 class _Separate(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, X, B0, V0, D, taps, n_iter, floor):
+    def forward(ctx, X, B0, V0, D, taps, n_iter, floor, check):
         M, F, T = X.shape
         N, _, K = B0.shape
         precision = "fp32" if X.dtype == torch.complex64 else "fp64"
@@ -27,8 +27,11 @@ class _Separate(torch.autograd.Function):
         sep.set_state(B=Bc, V=Vc)
         sep.iterate(n_iter)
         C = sep.source_images()
+        if check:
+            sep.check()
         ctx.sep = sep
         ctx.n_iter = n_iter
+        ctx.check = check
         ctx.save_for_backward(Xc, Bc, Vc)
         return C
 
@@ -38,12 +41,18 @@ class _Separate(torch.autograd.Function):
         sep = ctx.sep
         sep.set_input(Xc)
         gX, gB0, gV0 = sep.backward(ctx.n_iter, Bc, Vc, gC.contiguous())
-        sep.close()
-        return gX, gB0, gV0, None, None, None, None
+        try:
+            if ctx.check:
+                sep.check()
+        finally:
+            sep.close()
+        return gX, gB0, gV0, None, None, None, None, None
 
 
 def separate(X: torch.Tensor, B0: torch.Tensor, V0: torch.Tensor, D: int, taps, n_iter: int,
-             floor: float = 1e-8) -> torch.Tensor:
+             floor: float = 1e-8, check: bool = True) -> torch.Tensor:
     """Source images [N, M, F, T] after n_iter iterations, differentiable in X, B0, V0 (complex128 /
-    float64 tensors run in FP64, complex64 / float32 in FP32)."""
-    return _Separate.apply(X, B0, V0, int(D), tuple(int(t) for t in taps), int(n_iter), float(floor))
+    float64 tensors run in FP64, complex64 / float32 in FP32).  check=True: the forward and the
+    backward each read the device status word and raise CtfissError on a latched numeric fault
+    (a synchronisation each); check=False leaves both asynchronous (faults then go unreported)."""
+    return _Separate.apply(X, B0, V0, int(D), tuple(int(t) for t in taps), int(n_iter), float(floor), bool(check))

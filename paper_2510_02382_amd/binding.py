@@ -34,7 +34,7 @@ EXPORTS = (
     "ctfiss_batch_workspace_size", "ctfiss_batch_create", "ctfiss_batch_set_input", "ctfiss_batch_set_state",
     "ctfiss_batch_iterate", "ctfiss_batch_source_images", "ctfiss_batch_sync_status", "ctfiss_batch_destroy",
     "ctfiss_adjoint_workspace_size", "ctfiss_backward", "ctfiss_set_graph", "ctfiss_get_plan", "ctfiss_autotune",
-    "ctfiss_clear_tuned_plans",
+    "ctfiss_autotune_scratch_size", "ctfiss_clear_tuned_plans",
 )
 
 
@@ -60,7 +60,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
                            ctypes.POINTER(vp)], i32),
         "ctfiss_set_input": ([vp, vp], i32),
         "ctfiss_set_state": ([vp, vp, vp, vp], i32),
-        "ctfiss_iterate": ([vp, i32], i32),
+        "ctfiss_iterate": ([vp, i32, ctypes.POINTER(ctypes.c_double)], i32),
         "ctfiss_get_state": ([vp, vp, vp, vp], i32),
         "ctfiss_source_images": ([vp, vp], i32),
         "ctfiss_nll": ([vp, ctypes.POINTER(ctypes.c_double)], i32),
@@ -83,7 +83,8 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "ctfiss_set_graph": ([vp, i32], i32),
         "ctfiss_get_plan": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                             i32),
-        "ctfiss_autotune": ([vp, i32], i32),
+        "ctfiss_autotune_scratch_size": ([vp, ctypes.POINTER(sz)], i32),
+        "ctfiss_autotune": ([vp, i32, vp, sz], i32),
         "ctfiss_clear_tuned_plans": ([], i32),
     }
     for name, (args, res) in sig.items():
@@ -145,8 +146,15 @@ def ctfiss_set_state(ctx, W, B, V) -> None:
     _check(_lib.ctfiss_set_state(ctx, _ptr(W), _ptr(B), _ptr(V)), "ctfiss_set_state")
 
 
-def ctfiss_iterate(ctx, n_iter: int) -> None:
-    _check(_lib.ctfiss_iterate(ctx, int(n_iter)), "ctfiss_iterate")
+def ctfiss_iterate(ctx, n_iter: int, nll_host=None) -> None:
+    """nll_host: None, or a C-contiguous float64 NumPy array of n_iter entries that receives the
+    objective after every iteration."""
+    ptr = None
+    if nll_host is not None:
+        if nll_host.dtype.name != "float64" or not nll_host.flags.c_contiguous or nll_host.size < int(n_iter):
+            raise ValueError("nll_host: expected a C-contiguous float64 array of n_iter entries")
+        ptr = nll_host.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(_lib.ctfiss_iterate(ctx, int(n_iter), ptr), "ctfiss_iterate")
 
 
 def ctfiss_get_state(ctx, W, B, V) -> None:
@@ -193,8 +201,15 @@ def ctfiss_get_plan(ctx) -> tuple[int, int, int, int]:
     return tuple(int(x.value) for x in v)
 
 
-def ctfiss_autotune(ctx, trials: int) -> None:
-    _check(_lib.ctfiss_autotune(ctx, int(trials)), "ctfiss_autotune")
+def ctfiss_autotune_scratch_size(ctx) -> int:
+    out = ctypes.c_size_t(0)
+    _check(_lib.ctfiss_autotune_scratch_size(ctx, ctypes.byref(out)), "ctfiss_autotune_scratch_size")
+    return int(out.value)
+
+
+def ctfiss_autotune(ctx, trials: int, scratch: torch.Tensor) -> None:
+    _check(_lib.ctfiss_autotune(ctx, int(trials), _ptr(scratch), scratch.numel() * scratch.element_size()),
+           "ctfiss_autotune")
 
 
 def ctfiss_clear_tuned_plans() -> None:

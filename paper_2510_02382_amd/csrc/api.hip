@@ -221,6 +221,24 @@ hipError_t launch_zero_status(int* status, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, s, status);
   return hipGetLastError();
 }
+// Sum of n per-bin partials into *out by one workgroup in a fixed order
+// (thread i adds elements i, i + 256, ...; then a tree over the threads).
+__global__ void __launch_bounds__(256) k_sum_parts(const double* part, int n, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+hipError_t launch_sum_parts(const double* part, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, n, out);
+  return hipGetLastError();
+}
 size_t images_lds(const Dims& d) { return out_lds_bytes(d.Mb, d.M, d.N); }
 size_t nll_lds(const Dims& d) { return nll_lds_bytes(d.Mb); }
 
@@ -232,9 +250,10 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kClasses = 7;
+constexpr int kTraceCap = 256;  // NLL values one readback of ctfiss_iterate carries
 
 struct Layout {
-  size_t W, B, V, ilam, P, P0, musq, mu, vnum, vden, nllpart, status, work, Y, xch, total;
+  size_t W, B, V, ilam, P, P0, musq, mu, vnum, vden, nllpart, trace, status, work, Y, xch, total;
   int team;  // members per bin the exchange words are sized for (0: none)
 };
 
@@ -303,6 +322,7 @@ Layout make_layout(const Dims& d, int precision) {
   L.vnum = take((size_t)d.N * vs.nch * d.K * d.T * rs);
   L.vden = take((size_t)d.N * vs.nch * d.K * d.T * rs);
   L.nllpart = take((size_t)d.F * sizeof(double));
+  L.trace = take((size_t)kTraceCap * sizeof(double));
   L.status = take(kAlign);
   L.work = take(kAlign);
   L.Y = take((size_t)d.F * d.Mb * d.T * cs);
@@ -328,6 +348,7 @@ struct ctfiss_ctx {
   char* ws;
   Layout lay;
   Ptrs ptr;
+  double* trace;  // [kTraceCap] NLL after each iteration of a traced call
   Plan plan;
   VSplit vs;
   bool have_input, have_state;
@@ -437,10 +458,17 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   plan.blocks = precision == CTFISS_MIXED ? resident_wblocks<float, true>(rule, plan, d)
                 : precision == CTFISS_FP32 ? resident_wblocks<float>(rule, plan, d)
                                            : resident_wblocks<double>(rule, plan, d);
+  // A team's waits end only once all its members run together: a team plan
+  // needs at least `team` resident workgroups.
+  const int items = d.F * (plan.team > 1 ? plan.team : 1);
   if (const char* wb = std::getenv("CTFISS_WBLOCKS")) {
-    const int n = std::atoi(wb);
-    if (n > 0) plan.blocks = n < d.F ? n : d.F;
+    int n = std::atoi(wb);
+    if (n > 0) {
+      if (n < plan.team) n = plan.team;
+      plan.blocks = n < items ? n : items;
+    }
   }
+  if (plan.team > 1 && plan.blocks < plan.team) return CTFISS_E_UNSUPPORTED;
   ctfiss_ctx* c = new (std::nothrow) ctfiss_ctx();
   if (!c) return CTFISS_E_ARG;
   c->d = d;
@@ -465,6 +493,7 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
   c->ptr.vnum = c->ws + lay.vnum;
   c->ptr.vden = c->ws + lay.vden;
   c->ptr.nllpart = reinterpret_cast<double*>(c->ws + lay.nllpart);
+  c->trace = reinterpret_cast<double*>(c->ws + lay.trace);
   c->ptr.status = reinterpret_cast<int*>(c->ws + lay.status);
   c->ptr.work = reinterpret_cast<int*>(c->ws + lay.work);
   c->ptr.Y = c->ws + lay.Y;
@@ -565,14 +594,39 @@ int enqueue_iterations(ctfiss_ctx* c, int32_t n_iter) {
   return CTFISS_OK;
 }
 
+// Iterations one at a time, each followed by the objective of Eq. (5) at the
+// state it leaves (its rescale applied, as at the end of any call): per-bin
+// parts by k_nll, summed on the device into the trace; read back every
+// kTraceCap iterations.  A run of one-iteration calls gives the same state,
+// bit for bit, as one call of n_iter iterations.
+int iterate_traced(ctfiss_ctx* c, int32_t n_iter, double* out) {
+  const bool f32 = c->prec != CTFISS_FP64;
+  for (int done = 0; done < n_iter;) {
+    const int chunk = n_iter - done < kTraceCap ? n_iter - done : kTraceCap;
+    for (int i = 0; i < chunk; ++i) {
+      const int st = enqueue_iterations(c, 1);
+      if (st != CTFISS_OK) return st;
+      hipError_t e = f32 ? nll_t<float>(c->d, c->ptr, c->stream) : nll_t<double>(c->d, c->ptr, c->stream);
+      if (e == hipSuccess) e = launch_sum_parts(c->ptr.nllpart, c->d.F, c->trace + i, c->stream);
+      if (e != hipSuccess) return CTFISS_E_HIP;
+    }
+    hipError_t e = hipMemcpyAsync(out + done, c->trace, (size_t)chunk * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return CTFISS_E_HIP;
+    done += chunk;
+  }
+  return CTFISS_OK;
+}
 
 }  // namespace
 
 extern "C" {
 
-int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter) {
+int ctfiss_iterate(ctfiss_ctx* c, int32_t n_iter, double* nll_host) {
   if (!c || n_iter < 0) return CTFISS_E_ARG;
   if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
+  if (nll_host) return iterate_traced(c, n_iter, nll_host);
   if (!c->graph || n_iter == 0 || c->prof != 0) return enqueue_iterations(c, n_iter);
   // graph mode: one captured graph per (n_iter, carried Y valid at the start);
   // every argument of the launches is fixed per context, so a replay is the
@@ -796,7 +850,7 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
     if (e == hipSuccess) e = cp(ws + L.ckV + k * vb, c->ptr.V, vb);
     if (e != hipSuccess) return CTFISS_E_HIP;
     if (k < n_iter) {
-      const int st = ctfiss_iterate(c, 1);
+      const int st = ctfiss_iterate(c, 1, nullptr);
       if (st != CTFISS_OK) return st;
     }
   }
@@ -887,15 +941,46 @@ int ctfiss_clear_tuned_plans(void) {
   return CTFISS_OK;
 }
 
-int ctfiss_autotune(ctfiss_ctx* c, int32_t trials) {
-  if (!c || trials < 1) return CTFISS_E_ARG;
+int ctfiss_autotune_scratch_size(ctfiss_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return CTFISS_E_ARG;
+  const Dims& d = c->d;
+  const size_t rs = c->prec != CTFISS_FP64 ? 4 : 8;
+  *bytes = align_up((size_t)d.F * d.Mb * d.Mb * 2 * rs, kAlign) + align_up((size_t)d.N * d.F * d.K * rs, kAlign) +
+           align_up((size_t)d.N * d.K * d.T * rs, kAlign);
+  return CTFISS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device status word of a context (synchronises the stream).
+hipError_t read_status(ctfiss_ctx* c, int* code) {
+  hipError_t e = hipMemcpyAsync(code, c->ptr.status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctfiss_autotune(ctfiss_ctx* c, int32_t trials, void* scratch, size_t scratch_bytes) {
+  if (!c || trials < 1 || !scratch) return CTFISS_E_ARG;
   if (!c->have_input || !c->have_state) return CTFISS_E_ORDER;
   if (c->graph) return CTFISS_E_UNSUPPORTED;  // captured graphs hold the current plan
+  size_t need = 0;
+  (void)ctfiss_autotune_scratch_size(c, &need);
+  if (scratch_bytes < need || (reinterpret_cast<uintptr_t>(scratch) % kAlign) != 0) return CTFISS_E_WORKSPACE;
   const Dims& d = c->d;
   int dev = 0, max_lds = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return CTFISS_E_HIP;
+  // a fault latched before the call stays latched (and nothing is timed on faulted data)
+  int code = 0;
+  if (read_status(c, &code) != hipSuccess) return CTFISS_E_HIP;
+  if (code != 0) return CTFISS_E_NUMERIC;
   // candidates: every instantiated (G, RPL) with its smallest fitting frames per lane; team
   // shapes only where the default plan is a team plan (the workspace holds their exchange words)
   std::vector<Plan> cand;
@@ -911,14 +996,16 @@ int ctfiss_autotune(ctfiss_ctx* c, int32_t trials) {
       }
     }
   if (cand.empty()) return CTFISS_OK;
-  // time the W update on the context's own data; the state is restored afterwards
+  // time the W update on the context's own data; the state is restored from
+  // the caller's scratch afterwards
   const size_t rs = c->prec != CTFISS_FP64 ? 4 : 8;
   const size_t wb = (size_t)d.F * d.Mb * d.Mb * 2 * rs, bb = (size_t)d.N * d.F * d.K * rs, vb = (size_t)d.N * d.K * d.T * rs;
-  char* save = nullptr;
-  if (hipMallocAsync(reinterpret_cast<void**>(&save), wb + bb + vb, c->stream) != hipSuccess) return CTFISS_E_HIP;
+  char* save = static_cast<char*>(scratch);
+  char* saveB = save + align_up(wb, kAlign);
+  char* saveV = saveB + align_up(bb, kAlign);
   hipError_t e = hipMemcpyAsync(save, c->ptr.W, wb, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(save + wb, c->ptr.B, bb, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(save + wb + bb, c->ptr.V, vb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(saveB, c->ptr.B, bb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(saveV, c->ptr.V, vb, hipMemcpyDeviceToDevice, c->stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -931,7 +1018,7 @@ int ctfiss_autotune(ctfiss_ctx* c, int32_t trials) {
     p.blocks = c->prec == CTFISS_MIXED ? resident_wblocks<float, true>(c->rule, p, d)
                : f32                   ? resident_wblocks<float>(c->rule, p, d)
                                        : resident_wblocks<double>(c->rule, p, d);
-    if (p.blocks < 1) continue;
+    if (p.blocks < 1 || (p.team > 1 && p.blocks < p.team)) continue;
     float total = 0.f;
     for (int t = 0; t <= trials && e == hipSuccess; ++t) {  // the first run warms up
       e = f32 ? lambda_t<float>(d, c->ptr, false, c->stream) : lambda_t<double>(d, c->ptr, false, c->stream);
@@ -953,19 +1040,25 @@ int ctfiss_autotune(ctfiss_ctx* c, int32_t trials) {
       // back to the saved state for the next run
       if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.W, save, wb, hipMemcpyDeviceToDevice, c->stream);
     }
+    // a candidate whose runs latched a fault (e.g. a team wait that ran out) is not taken
+    int fc = 0;
+    if (e == hipSuccess) e = read_status(c, &fc);
+    if (e == hipSuccess && fc != 0) {
+      e = launch_zero_status(c->ptr.status, c->stream);
+      continue;
+    }
     if (e == hipSuccess && (best_ms < 0.f || total < best_ms)) {
       best_ms = total;
       best = p;
     }
   }
   if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.W, save, wb, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.B, save + wb, bb, hipMemcpyDeviceToDevice, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.V, save + wb + bb, vb, hipMemcpyDeviceToDevice, c->stream);
-  (void)hipFreeAsync(save, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.B, saveB, bb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.V, saveV, vb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the scratch is the caller's again on return
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   c->y_valid = false;
-  (void)launch_zero_status(c->ptr.status, c->stream);
   if (e != hipSuccess) {
     c->plan = keep;
     return CTFISS_E_HIP;
@@ -1229,7 +1322,7 @@ int ctfiss_batch_iterate(ctfiss_batch* b, int32_t n_iter) {
   if (!b->have_input || !b->have_state) return CTFISS_E_ORDER;
   if (b->rule != CTFISS_RULE_ISS) {
     for (ctfiss_ctx* c : b->ctx) {
-      const int st = ctfiss_iterate(c, n_iter);
+      const int st = ctfiss_iterate(c, n_iter, nullptr);
       if (st != CTFISS_OK) return st;
     }
     return CTFISS_OK;

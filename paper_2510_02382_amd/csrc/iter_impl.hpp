@@ -318,10 +318,12 @@ __device__ __forceinline__ R xval(const unsigned* v, int k) {
 
 // Wave-wide wait: word k (< KW) of a lane is src[idx[k]] (idx < 0: none);
 // once it carries `tag`, its payload goes to *dst[k].  Every lane of the wave
-// must call it.  Returns false if it stopped before all words arrived.
+// must call it.  Returns false if it stopped before all words arrived: past
+// kTeamSpin polls (then it latches kFaultTeamWait itself) or once another
+// fault is latched.
 template <int KW>
 __device__ bool xgather(const unsigned long long* src, const int (&idx)[KW], unsigned* const (&dst)[KW],
-                        unsigned tag, const int* status) {
+                        unsigned tag, int* status) {
   unsigned pend = 0;
 #pragma unroll
   for (int k = 0; k < KW; ++k)
@@ -338,7 +340,10 @@ __device__ bool xgather(const unsigned long long* src, const int (&idx)[KW], uns
       }
     }
     if (!__any(pend != 0)) return true;
-    if (spin >= kTeamSpin) return false;
+    if (spin >= kTeamSpin) {  // latched at once: the team's other waits then stop within 64 polls
+      if ((threadIdx.x & 63) == 0) latch(status, kFaultTeamWait);
+      return false;
+    }
     if ((spin & 63) == 63 && __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     __builtin_amdgcn_s_sleep(2);
   }
@@ -640,9 +645,10 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
   }
 }
 
-// Persistent workgroups: each pulls bins from a.work until all F are taken,
-// so every CU keeps its resident workgroups busy regardless of how the
-// dispatcher first placed them.
+// Work counter of the persistent launches that claim their items in order:
+// the team launch (a bin's members must be claimed together) and the IP
+// sweep.  (k_iss deals its bins round-robin; the batched launch has its own
+// counter.)
 template <typename R>
 __device__ __forceinline__ int next_bin(const IterArgs<R>& a, const BinLds<R>& s) {
   __syncthreads();  // the previous bin's LDS traffic is over

@@ -1,6 +1,7 @@
 """Tensor-level wrapper over the C ABI: one context, its workspace and bound buffers."""
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import binding as b
@@ -56,8 +57,15 @@ class Separator:
             self._check(W, (self.F, self.Mbar, self.Mbar), self.cdtype, "W")
         b.ctfiss_set_state(self.ctx, W, B, V)
 
-    def iterate(self, n_iter: int) -> None:
-        b.ctfiss_iterate(self.ctx, n_iter)
+    def iterate(self, n_iter: int, trace: bool = False):
+        """Enqueue n_iter iterations.  trace=True: returns the objective of Eq. (5) after every
+        iteration (a float64 NumPy array; the call then synchronises)."""
+        if not trace:
+            b.ctfiss_iterate(self.ctx, n_iter)
+            return None
+        out = np.empty(int(n_iter), dtype=np.float64)
+        b.ctfiss_iterate(self.ctx, n_iter, out)
+        return out
 
     def plan(self):
         """(G, frames per lane, rows per group, workgroups per bin) of the W update."""
@@ -66,7 +74,10 @@ class Separator:
     def autotune(self, trials: int = 3):
         """Time every fitting launch shape of the W update on this context's data and keep the
         fastest (ctfiss_autotune; cached for later contexts of the shape).  Returns plan()."""
-        b.ctfiss_autotune(self.ctx, trials)
+        scratch = torch.empty(b.ctfiss_autotune_scratch_size(self.ctx), dtype=torch.uint8, device=self.device)
+        if scratch.data_ptr() % 256:
+            raise RuntimeError("scratch allocation is not 256-byte aligned")
+        b.ctfiss_autotune(self.ctx, trials, scratch)
         return self.plan()
 
     def set_graph(self, enable: bool = True) -> None:
@@ -103,10 +114,17 @@ class Separator:
     def kernel_stats(self, which: int):
         return b.ctfiss_kernel_stats(self.ctx, which)
 
+    def check(self) -> None:
+        """Raise CtfissError(CTFISS_E_NUMERIC) if a device fault is latched (synchronises)."""
+        st, code = b.ctfiss_sync_status(self.ctx)
+        if st != b.CTFISS_OK:
+            raise b.CtfissError(st, f"device fault {code}")
+
     def backward(self, n_iter: int, B0: torch.Tensor, V0: torch.Tensor, gC: torch.Tensor):
         """Gradients (gX, gB0, gV0) of a real loss through W = I, (B0, V0), n_iter
         iterations and the source images, given gC = dL/dC (ctfiss_backward; FP32 or
-        FP64, ISS, all-taps rule).  The input bound by set_input is X."""
+        FP64, ISS, all-taps rule).  The input bound by set_input is X.  Enqueued without
+        waiting: a numeric fault stays latched for status() / check()."""
         self._check(B0, (self.N, self.F, self.K), self.rdtype, "B0")
         self._check(V0, (self.N, self.K, self.T), self.rdtype, "V0")
         self._check(gC, (self.N, self.M, self.F, self.T), self.cdtype, "gC")

@@ -82,7 +82,7 @@ def test_create_rejects_bad_arguments_before_hip(binding):
     bad = b.make_shape(8, 20, 2, 1, 2, 3, (2, 1))
     assert lib.ctfiss_create(ctypes.byref(bad), 0, 0, 0, 1e-8, fake, 1 << 20, None, ctypes.byref(ctx)) == b.CTFISS_E_SHAPE
     for fn in ("ctfiss_iterate", "ctfiss_destroy", "ctfiss_sync_status"):
-        args = {"ctfiss_iterate": (None, 1), "ctfiss_destroy": (None,), "ctfiss_sync_status": (None, None)}[fn]
+        args = {"ctfiss_iterate": (None, 1, None), "ctfiss_destroy": (None,), "ctfiss_sync_status": (None, None)}[fn]
         assert getattr(lib, fn)(*args) == b.CTFISS_E_ARG
     for code in range(-7, 1):
         assert b.ctfiss_status_string(code) != "unknown status"

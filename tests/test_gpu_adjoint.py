@@ -148,3 +148,17 @@ def test_backward_rejects_mixed_precision_and_tap0_rule():
         sep.backward(n, torch.from_numpy(B0).cuda(), torch.from_numpy(V0).cuda(), gC.to(torch.complex128))
     assert e.value.status == b.CTFISS_E_UNSUPPORTED
     sep.close()
+
+
+def test_fault_in_forward_raises_through_separate():
+    """A NaN in the mixture latches a device fault in the forward; separate() reads the status
+    word and raises instead of returning images and later gradients built on it."""
+    from paper_2510_02382_amd import binding as b
+    from paper_2510_02382_amd.autograd import separate
+    X, B0, V0, target, D, taps, n = problem("small", seed=2)
+    X = X.copy()
+    X[0, 1, 4] = np.nan
+    Xg = torch.from_numpy(X).to("cuda").requires_grad_(True)
+    with pytest.raises(b.CtfissError) as e:
+        separate(Xg, torch.from_numpy(B0).to("cuda"), torch.from_numpy(V0).to("cuda"), D, taps, n)
+    assert e.value.status == b.CTFISS_E_NUMERIC

@@ -106,3 +106,60 @@ def test_batch_rejects_wrong_tensors():
     with pytest.raises(ValueError):
         bs.set_input([p[0].to(torch.complex128) for p in probs])
     bs.close()
+
+
+# ------------------------------------------------------------------ against the oracle
+# Mixtures drawn as the batched workload (3-12 s, N in {2, 3}, M = N + 1, D in {4, 8},
+# RT60 0.3-1.0 s, STFT 1024/256, K = 10, 50 iterations); draws 0-4 and 9 (Mbar = 32,
+# 12, 24, 16, 16, 32; T = 540, 315, 191, 451, 331, 704), each cut to 10 bins so that the
+# oracle finishes in seconds.
+BATCH_DRAWS = (0, 1, 2, 3, 4, 9)
+
+
+def _workload_slices(draws, f0=60, nf=10):
+    from datagen import batched_workloads, init_nmf, make_mixture
+    wls = batched_workloads(max(draws) + 1, 7)
+    out = []
+    for i in draws:
+        w = wls[i]
+        X = np.ascontiguousarray(make_mixture(w, 1000 + i).X[:, f0:f0 + nf, :])
+        B0, V0 = init_nmf(w.N, nf, w.K, w.T, 1000 + i)
+        out.append((w, X, B0, V0))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_of_workload_mixtures_matches_oracle(precision):
+    """A batch of uneven mixtures against the FP64 oracle run mixture by mixture on the
+    original FP64 data: every source image within 1e-4 (FP32; the accuracy target) or 1e-9
+    (FP64) after the workload's 50 iterations."""
+    from oracle import ctf_iss as o
+    from oracle import threaded as oth
+    from paper_2510_02382_amd import BatchSeparator
+    from parity import elem_err, record, rel
+    # FP64 batches take one workgroup per bin: the Mbar = 32 draws (T = 540, 704) need a team in FP64
+    draws = BATCH_DRAWS if precision == "fp32" else (1, 2, 3, 4)
+    items = _workload_slices(draws)
+    rd = torch.float32 if precision == "fp32" else torch.float64
+    cd = torch.complex64 if precision == "fp32" else torch.complex128
+    shapes = [(X.shape[1], w.T, w.M, w.D, w.N, w.K, w.row_taps) for w, X, B0, V0 in items]
+    bs = BatchSeparator(shapes, precision=precision)
+    Xs = [torch.from_numpy(X).to("cuda", cd) for w, X, B0, V0 in items]
+    bs.set_input(Xs)
+    bs.set_state(B=[torch.from_numpy(B0).to("cuda", rd) for w, X, B0, V0 in items],
+                 V=[torch.from_numpy(V0).to("cuda", rd) for w, X, B0, V0 in items])
+    n_iter = items[0][0].n_iter
+    bs.iterate(n_iter)
+    C = [c.cpu().numpy() for c in bs.source_images()]
+    assert bs.status() == (-1, 0)
+    bs.close()
+    tol = 1e-4 if precision == "fp32" else 1e-9
+    for i, (w, X, B0, V0) in zip(draws, items):
+        W, _, _ = oth.run(X, w.D, w.row_taps, B0, V0, n_iter)
+        Cr = o.source_images(W, X, w.D, w.row_taps)
+        Cg = C[draws.index(i)]
+        for n in range(w.N):
+            e = rel(Cg[n], Cr[n])
+            record(f"batch_vs_oracle[{precision}]", draw=i, source=n, rel=e,
+                   elem=elem_err(Cg[n:n + 1], Cr[n:n + 1], "C"))
+            assert e < tol, (i, n, e)

@@ -1,20 +1,29 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
 Every input is seeded and synthetic; the oracle sees exactly the values the
-GPU sees (the FP32 path's inputs rounded to complex64/float32 first).
+GPU sees (the FP32 path's inputs rounded to complex64/float32 first), except
+where a test holds the FP32 path to the oracle on the original FP64 data.
 
-Tolerances (relative Frobenius norm per output array):
-  * FP64 path, one iteration: 1e-11; 30 iterations: 1e-9.  Both sides are
-    FP64 and differ only in summation order (~1e-15 per reduction), which the
-    fixed-point dynamics amplify by at most ~10x per 10 iterations.
-  * FP32 path: 1e-4, the accuracy target for separated STFTs of the FP32
-    path.  One iteration accumulates O(Mbar + log T) roundings of 6e-8 each
-    (ISS steps and reductions), i.e. ~1e-6; 100 ISS iterations amplify that by
-    ~10x (a 1e-14 input perturbation of the c1 mixture grows to 2e-13).
-  * IP trajectories amplify rounding far more: the same 1e-14 perturbation
-    grows to 3e-7 after 100 IP iterations (~3e7x), so FP64 IP over 100
-    iterations is held to 1e-5, and FP32 IP is not numerically usable on the
-    stacked-frame workloads (it latches the singular-system fault).
+Each output is checked twice (tests/parity.py): by the relative Frobenius
+norm of the whole array, and element by element, the largest error within
+each bin (W), (source, bin) (B), (source, basis) (V) or (source, microphone,
+bin) (C) divided by the RMS of the reference over that group.
+
+Tolerances:
+  * FP64 path, one iteration: 1e-11 (norm and element-wise); 30
+    iterations: 1e-9.  Both sides are FP64 and differ only in summation order
+    (~1e-15 per reduction), which the fixed-point dynamics amplify by at most
+    ~10x per 10 iterations.
+  * FP32 path, one teacher-forced iteration: 1e-5 (norm), 5e-5 (element-wise).
+    One iteration accumulates O(Mbar + log T) roundings of 6e-8 each (ISS
+    steps and reductions), ~1e-6; the element-wise bounds are set from the
+    measured maxima (recorded with CTFISS_PARITY_LOG) with a margin of 2-3x.
+    Over a run the target is 1e-4 per source image against the oracle on the
+    original data.
+  * IP trajectories amplify rounding far more: a 1e-14 perturbation of the
+    c1 mixture grows to 3e-7 after 100 IP iterations (~3e7x), so FP64 IP over
+    100 iterations is held to 1e-5, and FP32 IP is not numerically usable on
+    the stacked-frame workloads (it latches the singular-system fault).
 """
 import numpy as np
 import pytest
@@ -22,6 +31,8 @@ import torch
 
 from datagen import WORKLOADS, init_nmf, make_mixture, random_problem, rng_for
 from oracle import ctf_iss as o
+from oracle import threaded as oth
+from parity import check_outputs, elem_err, record, rel  # noqa: F401  (rel is imported from here elsewhere)
 
 pytestmark = pytest.mark.gpu
 
@@ -39,13 +50,15 @@ CASES = {
     "max_rows": (3, 100, 4, 16, (22, 21, 21), 4),
 }
 
-TOL1 = {"fp32": 1e-4, "fp64": 1e-11}
-
-
-def rel(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+# One iteration from the same (rounded) inputs.  Measured maxima over every case and both
+# rules (MI355X): FP32 ISS 5.0e-6 (norm) / 1.5e-5 (element-wise), team launches 2.1e-5
+# element-wise, mixed 1.8e-6 / 1.6e-5; FP64 1.2e-14 / 2.0e-13.
+TOL1 = {"fp32": 1e-5, "fp64": 1e-11}     # relative norm
+ELEM1 = {"fp32": 5e-5, "fp64": 1e-11}    # element-wise per group
+# FP32 IP inverts an Mbar x Mbar weighted covariance per row; at Mbar = 64 its conditioning
+# puts one iteration at 1.2e-5 (norm) / 1.0e-4 (element-wise, measured), elsewhere <= 2.7e-6 /
+# 1.5e-5.
+TOL1_IP32 = (3e-5, 3e-4)
 
 
 def as_device(x, precision):
@@ -121,8 +134,8 @@ def test_one_iteration_matches_oracle(case, rule, precision):
     g = gpu_run(X, D, taps, B0, V0, W0, 1, precision, rule)
     r = oracle_run(X, D, taps, B0, V0, W0, 1, precision, rule)
     assert g["status"] == 0
-    for k in ("W", "B", "V", "C"):
-        assert rel(g[k], r[k]) < TOL1[precision], (k, rel(g[k], r[k]))
+    tn, te = TOL1_IP32 if (rule, precision) == ("ip", "fp32") else (TOL1[precision], ELEM1[precision])
+    check_outputs(f"one_iteration[{case}-{rule}-{precision}]", g, r, tn, te)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -139,8 +152,7 @@ def test_fewer_workgroups_than_bins(precision, monkeypatch):
     for k in ("W", "B", "V", "C"):
         assert np.array_equal(g[k], ref[k]), k
     r = oracle_run(X, D, taps, B0, V0, W0, 2, precision)
-    for k in ("W", "B", "V", "C"):
-        assert rel(g[k], r[k]) < 10 * TOL1[precision], (k, rel(g[k], r[k]))
+    check_outputs(f"fewer_workgroups[{precision}]", g, r, 10 * TOL1[precision], 10 * ELEM1[precision])
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -149,8 +161,7 @@ def test_paper_tap0_rule_matches_oracle(case, precision):
     X, B0, V0, W0, D, taps = make_case(case, seed=4)
     g = gpu_run(X, D, taps, B0, V0, W0, 2, precision, "iss", "paper_tap0")
     r = oracle_run(X, D, taps, B0, V0, W0, 2, precision, "iss", "paper_tap0")
-    for k in ("W", "B", "V"):
-        assert rel(g[k], r[k]) < 10 * TOL1[precision], (k, rel(g[k], r[k]))
+    check_outputs(f"paper_tap0[{case}-{precision}]", g, r, 10 * TOL1[precision], 10 * ELEM1[precision])
 
 
 def test_identity_initialisation_and_zero_iterations():
@@ -162,8 +173,7 @@ def test_identity_initialisation_and_zero_iterations():
     assert rel(g["C"], r) < 1e-13
     g = gpu_run(X, D, taps, B0, V0, None, 3, "fp64")
     r = oracle_run(X, D, taps, B0, V0, None, 3, "fp64")
-    for k in ("W", "B", "V", "C"):
-        assert rel(g[k], r[k]) < 1e-10, k
+    check_outputs("identity_init_3_iterations", g, r, 1e-10, 1e-9)
 
 
 # ------------------------------------------------------------------ trajectories on mixtures
@@ -179,8 +189,7 @@ def test_fp64_trajectory_c0_slice():
     g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp64")
     r = oracle_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp64")
     assert g["status"] == 0
-    for k in ("W", "B", "V", "C"):
-        assert rel(g[k], r[k]) < 1e-9, (k, rel(g[k], r[k]))
+    check_outputs("fp64_trajectory_c0_slice", g, r, 1e-9, 1e-8)
 
 
 def test_fp32_iss_trajectory_c1_slice_100_iterations():
@@ -191,6 +200,8 @@ def test_fp32_iss_trajectory_c1_slice_100_iterations():
     C = o.source_images(W, X, wl.D, wl.row_taps)
     assert g["status"] == 0
     for n in range(wl.N):
+        record("fp32_iss_trajectory_c1_slice", source=n, rel=rel(g["C"][n], C[n]),
+               elem=elem_err(g["C"][n:n + 1], C[n:n + 1], "C"))
         assert rel(g["C"][n], C[n]) < 1e-4, (n, rel(g["C"][n], C[n]))
 
 
@@ -199,8 +210,7 @@ def test_fp64_ip_trajectory_c1_slice_100_iterations():
     g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp64", "ip")
     r = oracle_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp64", "ip")
     assert g["status"] == 0
-    for k in ("W", "B", "V", "C"):
-        assert rel(g[k], r[k]) < 1e-5, (k, rel(g[k], r[k]))
+    check_outputs("fp64_ip_trajectory_c1_slice", g, r, 1e-5, 1e-3)
 
 
 def test_fp32_ip_instability_is_reported_not_hidden():
@@ -223,10 +233,11 @@ def c1_full():
 def test_full_size_c1_two_iterations(c1_full):
     X, B0, V0, wl = c1_full
     g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, 2, "fp32")
-    r = oracle_run(X, wl.D, wl.row_taps, B0, V0, None, 2, "fp32")
+    Xr, Br, Vr = rounded(X, "fp32"), rounded(B0, "fp32"), rounded(V0, "fp32")
+    W, B, V = oth.run(Xr, wl.D, wl.row_taps, Br, Vr, 2)
+    r = dict(W=W, B=B, V=V, C=o.source_images(W, Xr, wl.D, wl.row_taps))
     assert g["status"] == 0
-    for k in ("W", "B", "V", "C"):
-        assert rel(g[k], r[k]) < TOL1["fp32"], (k, rel(g[k], r[k]))
+    check_outputs("full_size_c1_two_iterations", g, r, 10 * TOL1["fp32"], 10 * ELEM1["fp32"])
 
 
 def test_full_size_c1_100_iterations_properties(c1_full):
@@ -288,3 +299,153 @@ def test_call_order_is_checked():
     with pytest.raises(ValueError):
         sep.set_input(torch.zeros((2, 4, 20), dtype=torch.complex128, device="cuda"))
     sep.close()
+
+
+# ------------------------------------------------------------------ full-size trajectories
+def test_full_size_c0_fp64_30_iterations():
+    """The 4 s mixture at full size (F = 513, T = 251, Mbar = 12), 30 FP64 iterations from the
+    identity, against the oracle run over host threads (the same per-bin arithmetic)."""
+    wl = WORKLOADS["c0"]
+    X = make_mixture(wl, 0).X
+    B0, V0 = init_nmf(wl.N, wl.F, wl.K, wl.T, 0)
+    g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, "fp64")
+    W, B, V = oth.run(X, wl.D, wl.row_taps, B0, V0, wl.n_iter)
+    r = dict(W=W, B=B, V=V, C=o.source_images(W, X, wl.D, wl.row_taps))
+    assert g["status"] == 0
+    check_outputs("full_size_c0_fp64_30_iterations", g, r, 1e-9, 1e-8)
+
+
+@pytest.fixture(scope="module")
+def c1_oracle_100(c1_full):
+    """The FP64 oracle's 100 iterations of the full 10 s mixture (original FP64 data)."""
+    X, B0, V0, wl = c1_full
+    W, B, V = oth.run(X, wl.D, wl.row_taps, B0, V0, wl.n_iter)
+    return dict(W=W, B=B, V=V, C=o.source_images(W, X, wl.D, wl.row_taps))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed", "fp64"])
+def test_full_size_c1_100_iterations_against_oracle(c1_full, c1_oracle_100, precision):
+    """The benchmark's configuration as the benchmark runs it (F = 1025, T = 313, Mbar = 24, 100
+    iterations from the identity), each precision held to the FP64 oracle on the original data:
+    every source image within 1e-4 (FP32 and mixed; the accuracy target of the FP32 path) or
+    1e-9 (FP64)."""
+    X, B0, V0, wl = c1_full
+    g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, precision)
+    r = c1_oracle_100
+    assert g["status"] == 0
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    for n in range(wl.N):
+        e = rel(g["C"][n], r["C"][n])
+        record(f"full_size_c1_100[{precision}]", source=n, rel=e, elem=elem_err(g["C"][n:n + 1], r["C"][n:n + 1], "C"))
+        assert e < tol, (n, e)
+    for k in ("W", "B", "V"):
+        record(f"full_size_c1_100[{precision}]", output=k, rel=rel(g[k], r[k]), elem=elem_err(g[k], r[k], k))
+    if precision == "fp64":
+        check_outputs("full_size_c1_100[fp64]", g, r, 1e-9, 1e-7)
+
+
+# ------------------------------------------------------------------ objective trace
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_nll_trace_matches_oracle_after_every_iteration(precision):
+    """ctfiss_iterate's per-iteration objective (Eq. (5), computed on the device) equals the
+    oracle's objective at the state after each oracle iteration; the traced call leaves the
+    same state, bit for bit, as an untraced one."""
+    from paper_2510_02382_amd import Separator
+    X, B0, V0, W0, D, taps = make_case("c0_like", seed=9)
+    M, F, T = X.shape
+    n_iter = 6
+    sep = Separator(F, T, M, D, len(taps), B0.shape[-1], taps, precision=precision)
+    sep.set_input(as_device(X, precision))
+    sep.set_state(B=as_device(B0, precision), V=as_device(V0, precision), W=as_device(W0, precision))
+    trace = sep.iterate(n_iter, trace=True)
+    Wt, Bt, Vt = (t.cpu().numpy() for t in sep.state())
+    assert sep.status() == 0
+    sep.close()
+    plain = gpu_run(X, D, taps, B0, V0, W0, n_iter, precision, images=False)
+    np.testing.assert_array_equal(Wt, plain["W"])
+    np.testing.assert_array_equal(Bt, plain["B"])
+    np.testing.assert_array_equal(Vt, plain["V"])
+    Xr = rounded(X, precision)
+    Xb = o.stacked_view(Xr, D)
+    ref = []
+    o.run(Xr, D, taps, rounded(B0, precision), rounded(V0, precision), n_iter, W0=rounded(W0, precision),
+          callback=lambda it, W, B, V: ref.append(o.nll(W, Xb, B, V, taps)))
+    ref = np.array(ref)
+    err = np.abs(trace - ref) / np.abs(ref)
+    record(f"nll_trace[{precision}]", max_rel=float(err.max()))
+    assert trace.shape == (n_iter,)
+    assert err.max() <= (1e-11 if precision == "fp64" else 1e-6), err
+
+
+# ------------------------------------------------------------------ latched numeric faults
+FAULT_ISS_DENOMINATOR, FAULT_IP_SINGULAR, FAULT_MU, FAULT_OUT_SINGULAR = 1, 2, 3, 4
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_zero_basis_row_latches_mu_fault(precision):
+    """A bin whose bases are all zero has lambda = 0 there: 1/lambda is not finite, and the
+    source-variance step latches its fault (the first fault of the iteration wins)."""
+    X, B0, V0, W0, D, taps = make_case("d1_tiny", seed=3)
+    B0 = B0.copy()
+    B0[1, 2, :] = 0.0
+    g = gpu_run(X, D, taps, B0, V0, W0, 1, precision, images=False)
+    assert g["status"] == FAULT_MU
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_zero_mixture_latches_iss_denominator_fault(precision):
+    """All-zero observations give all-zero demixed rows, so d_r = 0 in the first ISS step."""
+    X, B0, V0, W0, D, taps = make_case("ragged", seed=3)
+    g = gpu_run(np.zeros_like(X), D, taps, B0, V0, W0, 1, precision, images=False)
+    assert g["status"] == FAULT_ISS_DENOMINATOR
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_silent_channel_latches_ip_singular_fault(precision):
+    """A microphone that records nothing gives weighted covariances Q_r with a zero row and
+    column (exactly, in any arithmetic): the IP system is singular and its fault is latched."""
+    X, B0, V0, W0, D, taps = make_case("d1_tiny", seed=5)
+    X = X.copy()
+    X[1] = 0.0
+    g = gpu_run(X, D, taps, B0, V0, W0, 1, precision, rule="ip", images=False)
+    assert g["status"] == FAULT_IP_SINGULAR
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_singular_demixing_matrix_latches_image_fault(precision):
+    """Source images of a state whose W_f has a zero row (not invertible): the FP64 LU of the
+    image stage meets a zero pivot and latches its fault."""
+    from paper_2510_02382_amd import Separator
+    X, B0, V0, W0, D, taps = make_case("three_src", seed=5)
+    W0 = W0.copy()
+    W0[2, 3, :] = 0.0
+    M, F, T = X.shape
+    sep = Separator(F, T, M, D, len(taps), B0.shape[-1], taps, precision=precision)
+    sep.set_input(as_device(X, precision))
+    sep.set_state(B=as_device(B0, precision), V=as_device(V0, precision), W=as_device(W0, precision))
+    sep.source_images()
+    assert sep.status() == FAULT_OUT_SINGULAR
+    sep.close()
+
+
+def test_autotune_keeps_a_fault_latched_before_it():
+    """A fault latched by an earlier iterate() is not erased by ctfiss_autotune: the call
+    returns CTFISS_E_NUMERIC, tunes nothing and the status still reports the fault."""
+    from paper_2510_02382_amd import Separator
+    from paper_2510_02382_amd import binding as b
+    X, B0, V0, W0, D, taps = make_case("d1_tiny", seed=1)
+    X = X.copy()
+    X[0, 2, 5] = np.nan
+    M, F, T = X.shape
+    sep = Separator(F, T, M, D, len(taps), B0.shape[-1], taps, precision="fp32")
+    sep.set_input(as_device(X, "fp32"))
+    sep.set_state(B=as_device(B0, "fp32"), V=as_device(V0, "fp32"), W=as_device(W0, "fp32"))
+    sep.iterate(1)
+    plan = sep.plan()
+    with pytest.raises(b.CtfissError) as e:
+        sep.autotune(trials=1)
+    assert e.value.status == b.CTFISS_E_NUMERIC
+    assert sep.status() != 0
+    assert sep.plan() == plan
+    sep.close()
+    b.ctfiss_clear_tuned_plans()

@@ -9,13 +9,14 @@ across calls are covered at sizes the oracle finishes in seconds; the long
 Mbar = 64 shape takes the team path by itself.
 
 Tolerances are those of the single-workgroup parity tests (relative Frobenius
-norm per output): 1e-4 for FP32, 1e-11 for FP64 after one iteration, ten
-times that after three.
+norm and element-wise per group, tests/parity.py) after one iteration, ten
+times those after three.
 """
 import numpy as np
 import pytest
 
-from test_gpu_parity import TOL1, gpu_run, make_case, oracle_run, rel
+from parity import check_outputs, elem_err, record
+from test_gpu_parity import ELEM1, TOL1, gpu_run, make_case, oracle_run, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -42,8 +43,7 @@ def test_forced_team_matches_oracle(case, precision, monkeypatch):
     g = gpu_run(X, D, taps, B0, V0, W0, 1, precision)
     r = oracle_run(X, D, taps, B0, V0, W0, 1, precision)
     assert g["status"] == 0
-    for k in ("W", "B", "V", "C"):
-        assert rel(g[k], r[k]) < TOL1[precision], (k, rel(g[k], r[k]))
+    check_outputs(None, g, r, TOL1[precision], ELEM1[precision])
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -56,8 +56,7 @@ def test_forced_team_carried_rows_across_calls(case, precision, monkeypatch):
     g = gpu_run(X, D, taps, B0, V0, W0, 3, precision, splits=[2, 1])
     r = oracle_run(X, D, taps, B0, V0, W0, 3, precision)
     assert g["status"] == 0
-    for k in ("W", "B", "V", "C"):
-        assert rel(g[k], r[k]) < 10 * TOL1[precision], (k, rel(g[k], r[k]))
+    check_outputs(None, g, r, 10 * TOL1[precision], 10 * ELEM1[precision])
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -66,8 +65,7 @@ def test_forced_team_paper_tap0_rule(precision, monkeypatch):
     X, B0, V0, W0, D, taps = make_case("three_src", seed=13)
     g = gpu_run(X, D, taps, B0, V0, W0, 2, precision, "iss", "paper_tap0")
     r = oracle_run(X, D, taps, B0, V0, W0, 2, precision, "iss", "paper_tap0")
-    for k in ("W", "B", "V"):
-        assert rel(g[k], r[k]) < 10 * TOL1[precision], (k, rel(g[k], r[k]))
+    check_outputs(None, g, r, 10 * TOL1[precision], 10 * ELEM1[precision], keys=("W", "B", "V"))
 
 
 def test_team_and_single_workgroup_agree(monkeypatch):
@@ -95,8 +93,7 @@ def test_long_signal_mbar64_matches_oracle(precision, monkeypatch):
     g = gpu_run(X, D, taps, B0, V0, W0, 1, precision)
     r = oracle_run(X, D, taps, B0, V0, W0, 1, precision)
     assert g["status"] == 0
-    for k in ("W", "B", "V", "C"):
-        assert rel(g[k], r[k]) < TOL1[precision], (k, rel(g[k], r[k]))
+    check_outputs(None, g, r, TOL1[precision], ELEM1[precision])
 
 
 def test_team_plans_are_iss_only_and_not_batched(monkeypatch):
@@ -112,3 +109,36 @@ def test_team_plans_are_iss_only_and_not_batched(monkeypatch):
     with pytest.raises(b.CtfissError) as e:
         BatchSeparator([(F, T, M, D_, len(tp_), K, tp_)], precision="fp32")
     assert e.value.status == b.CTFISS_E_UNSUPPORTED
+
+
+# ------------------------------------------------------------------ 100 iterations at Mbar = 64
+@pytest.fixture(scope="module")
+def c3_slice():
+    """Four bins of the 60 s precision-workload mixture (N = 3, M = 4, D = 16: Mbar = 64, taps
+    22 + 21 + 21, T = 938, K = 30) and the FP64 oracle's 100 iterations on them."""
+    from datagen import WORKLOADS, init_nmf, make_mixture
+    from oracle import ctf_iss as o
+    from oracle import threaded as oth
+    wl = WORKLOADS["c3"]
+    f0, nf = 600, 4
+    X = np.ascontiguousarray(make_mixture(wl, 0).X[:, f0:f0 + nf, :])
+    B0, V0 = init_nmf(wl.N, nf, wl.K, wl.T, 0)
+    W, B, V = oth.run(X, wl.D, wl.row_taps, B0, V0, wl.n_iter)
+    return X, B0, V0, wl, dict(W=W, B=B, V=V, C=o.source_images(W, X, wl.D, wl.row_taps))
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32", "fp64"])
+def test_mbar64_slice_100_iterations_against_oracle(c3_slice, precision, monkeypatch):
+    """The team launch over a whole run of the precision workload's shape (four bins): every
+    source image against the FP64 oracle on the original data.  Mixed precision meets the 1e-4
+    target; plain FP32 is held to what it measures (its W takes 64 FP32-rounded rank-one
+    updates per iteration); FP64 to 1e-9."""
+    monkeypatch.delenv("CTFISS_PLAN", raising=False)
+    X, B0, V0, wl, r = c3_slice
+    g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, precision)
+    assert g["status"] == 0
+    tol = {"mixed": 1e-4, "fp32": 1e-3, "fp64": 1e-9}[precision]
+    for n in range(wl.N):
+        e = rel(g["C"][n], r["C"][n])
+        record(source=n, rel=e, elem=elem_err(g["C"][n:n + 1], r["C"][n:n + 1], "C"))
+        assert e < tol, (n, e)

@@ -382,3 +382,15 @@ def test_noiseless_known_mixing_is_separated(rule):
         assert np.median(dom) > 0.98 and dom.min() > 0.5
         for f in range(6):
             assert sorted(np.argmax(P[f], -1)) == [0, 1, 2]
+
+
+def test_threaded_driver_equals_serial_oracle():
+    """oracle.threaded runs the W update of bin chunks on a thread pool and the rest of each
+    iteration on the whole arrays; per bin it is ctf_iss.run's arithmetic (both rules)."""
+    from oracle import threaded as th
+    X, B0, V0 = random_problem(7, 40, 2, 2, 3, 5, scale_spread=0.5)
+    for rule in (o.ISS, o.IP):
+        W1, B1, V1 = o.run(X, 2, (2, 2), B0, V0, 4, rule=rule)
+        W2, B2, V2 = th.run(X, 2, (2, 2), B0, V0, 4, rule=rule, workers=3, chunk=2)
+        for a, b in ((W1, W2), (B1, B2), (V1, V2)):
+            assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
