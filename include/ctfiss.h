@@ -69,6 +69,7 @@ extern "C" {
 #define CTFISS_E_ORDER (-5)        /* input or state not set before use            */
 #define CTFISS_E_HIP (-6)          /* a HIP runtime call failed                    */
 #define CTFISS_E_NUMERIC (-7)      /* a device numeric fault was latched           */
+#define CTFISS_E_TOO_LARGE (-8)    /* workspace beyond the static scratch (noalloc) */
 
 /* Limits of this build (CTFISS_E_UNSUPPORTED beyond them). */
 #define CTFISS_MAX_ROWS 64         /* Mbar = M * D                                  */
@@ -225,6 +226,27 @@ int ctfiss_sync_status(ctfiss_ctx* ctx, int32_t* fault_code);
  * used must stay allocated until that work has completed, e.g. freed in
  * stream order or after a synchronisation. */
 int ctfiss_destroy(ctfiss_ctx* ctx);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * separation -- ctfiss_create, set_input(X), set_state(W0, B0, V0),
+ * iterate(n_iter), source_images(C) and get_state(W, B, V) -- with the
+ * context's workspace in the library's own static device scratch of 96 MiB
+ * instead of a caller buffer (enough for FP32 at F = 1025, T = 313, Mbar = 24,
+ * 72.5 MiB).  Arguments as in those calls; W0 may be NULL (identity); C, W, B,
+ * V may each be NULL to skip that output; status (device int32, nullable)
+ * receives the latched device fault code (0 = none) by a stream-ordered copy.
+ * Results equal those of the calls above on a caller workspace, bit for bit.
+ * Enqueued on `stream` without waiting; allocates nothing (no device memory;
+ * the context lives on the call's stack).  A shape whose workspace
+ * (ctfiss_workspace_size) exceeds the scratch returns CTFISS_E_TOO_LARGE
+ * before any HIP call.  The scratch is one per GPU and keeps the last call's
+ * contents (each call clears what must start at zero): calls that overlap on
+ * one GPU, from several streams or host threads, race and must be serialised
+ * by the caller. */
+int ctfiss_separate_noalloc(const ctfiss_shape* shape, int precision, int rule, int vrule, double floor,
+                            const void* X, const void* W0, const void* B0, const void* V0, int32_t n_iter, void* C,
+                            void* W, void* B, void* V, int32_t* status, void* stream);
 
 /* Static description of a status code. */
 const char* ctfiss_status_string(int status);

@@ -22,6 +22,7 @@ CTFISS_E_WORKSPACE = -4
 CTFISS_E_ORDER = -5
 CTFISS_E_HIP = -6
 CTFISS_E_NUMERIC = -7
+CTFISS_E_TOO_LARGE = -8
 
 CTFISS_FP32, CTFISS_FP64, CTFISS_MIXED = 0, 1, 2
 CTFISS_RULE_ISS, CTFISS_RULE_IP = 0, 1
@@ -34,7 +35,7 @@ EXPORTS = (
     "ctfiss_batch_workspace_size", "ctfiss_batch_create", "ctfiss_batch_set_input", "ctfiss_batch_set_state",
     "ctfiss_batch_iterate", "ctfiss_batch_source_images", "ctfiss_batch_sync_status", "ctfiss_batch_destroy",
     "ctfiss_adjoint_workspace_size", "ctfiss_backward", "ctfiss_set_graph", "ctfiss_get_plan", "ctfiss_autotune",
-    "ctfiss_autotune_scratch_size", "ctfiss_clear_tuned_plans",
+    "ctfiss_autotune_scratch_size", "ctfiss_clear_tuned_plans", "ctfiss_separate_noalloc",
 )
 
 
@@ -86,6 +87,8 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "ctfiss_autotune_scratch_size": ([vp, ctypes.POINTER(sz)], i32),
         "ctfiss_autotune": ([vp, i32, vp, sz], i32),
         "ctfiss_clear_tuned_plans": ([], i32),
+        "ctfiss_separate_noalloc": ([ctypes.POINTER(Shape), i32, i32, i32, ctypes.c_double, vp, vp, vp, vp, i32, vp,
+                                     vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -230,6 +233,14 @@ def ctfiss_adjoint_workspace_size(shape: Shape, precision: int, n_iter: int) -> 
 def ctfiss_backward(ctx, n_iter: int, B0, V0, gC, gX, gB0, gV0, aws: torch.Tensor) -> None:
     _check(_lib.ctfiss_backward(ctx, int(n_iter), _ptr(B0), _ptr(V0), _ptr(gC), _ptr(gX), _ptr(gB0), _ptr(gV0),
                                 _ptr(aws), aws.numel() * aws.element_size()), "ctfiss_backward")
+
+
+def ctfiss_separate_noalloc(shape: Shape, precision: int, rule: int, vrule: int, floor: float, X, W0, B0, V0,
+                            n_iter: int, C, W, B, V, status, stream=None) -> None:
+    _check(_lib.ctfiss_separate_noalloc(ctypes.byref(shape), int(precision), int(rule), int(vrule), float(floor),
+                                        _ptr(X), _ptr(W0), _ptr(B0), _ptr(V0), int(n_iter), _ptr(C), _ptr(W),
+                                        _ptr(B), _ptr(V), _ptr(status), _stream(stream)),
+           "ctfiss_separate_noalloc")
 
 
 # ------------------------------------------------------------------ batches

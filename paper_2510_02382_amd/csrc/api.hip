@@ -221,6 +221,15 @@ hipError_t launch_zero_status(int* status, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, s, status);
   return hipGetLastError();
 }
+__global__ void __launch_bounds__(256) k_zero_words(unsigned long long* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+hipError_t launch_zero_words(unsigned long long* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t blocks = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
 // Sum of n per-bin partials into *out by one workgroup in a fixed order
 // (thread i adds elements i, i + 256, ...; then a tree over the threads).
 __global__ void __launch_bounds__(256) k_sum_parts(const double* part, int n, double* out) {
@@ -416,29 +425,24 @@ hipError_t drain_timing(ctfiss_ctx* c) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int ctfiss_workspace_size(const ctfiss_shape* shape, int precision, size_t* bytes) {
-  if (!bytes) return CTFISS_E_ARG;
-  Dims d;
-  const int st = validate_shape(shape, precision, &d);
-  if (st != CTFISS_OK) return st;
-  *bytes = make_layout(d, precision).total;
-  return CTFISS_OK;
-}
-
-int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule, double floor, void* workspace,
-                  size_t workspace_bytes, void* stream, ctfiss_ctx** out) {
-  if (!out || !workspace) return CTFISS_E_ARG;
+// Argument and shape checks of a context (no HIP call).
+int check_create_args(const ctfiss_shape* shape, int precision, int rule, int vrule, double floor, Dims* d,
+                      Layout* lay) {
   if (rule != CTFISS_RULE_ISS && rule != CTFISS_RULE_IP) return CTFISS_E_ARG;
   if (vrule != CTFISS_VRULE_ALL_TAPS && vrule != CTFISS_VRULE_PAPER_TAP0) return CTFISS_E_ARG;
   if (!(floor >= 0.0) || !std::isfinite(floor)) return CTFISS_E_ARG;
-  Dims d;
-  int st = validate_shape(shape, precision, &d);
+  const int st = validate_shape(shape, precision, d);
   if (st != CTFISS_OK) return st;
-  const Layout lay = make_layout(d, precision);
-  if (workspace_bytes < lay.total || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
-    return CTFISS_E_WORKSPACE;
+  *lay = make_layout(*d, precision);
+  return CTFISS_OK;
+}
+
+// Fills a context over `workspace` (checked by the caller): launch plan, pointers into the
+// workspace, cleared status word and exchange words.
+int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int rule, int vrule, double floor,
+             void* workspace, void* stream) {
   int dev = 0, max_lds = 0;
   if (hipGetDevice(&dev) != hipSuccess) return CTFISS_E_HIP;
   if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -469,8 +473,6 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
     }
   }
   if (plan.team > 1 && plan.blocks < plan.team) return CTFISS_E_UNSUPPORTED;
-  ctfiss_ctx* c = new (std::nothrow) ctfiss_ctx();
-  if (!c) return CTFISS_E_ARG;
   c->d = d;
   c->prec = precision;
   c->rule = rule;
@@ -507,13 +509,42 @@ int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule,
     c->ms[i] = 0.0;
   }
   hipError_t ze = launch_zero_status(c->ptr.status, c->stream);
-  // exchange words start untagged (every launch's tags are nonzero)
+  // exchange words start untagged (every launch's tags are nonzero); cleared by a
+  // kernel rather than a memset node, so that a caller may capture the call
   if (ze == hipSuccess && c->ptr.xch)
-    ze = hipMemsetAsync(c->ptr.xch, 0, (size_t)d.F * team_words(d.Mb, d.lmax, lay.team, precision != CTFISS_FP64 ? 4 : 8) * 8,
-                        c->stream);
-  if (ze != hipSuccess) {
+    ze = launch_zero_words(static_cast<unsigned long long*>(c->ptr.xch),
+                           (size_t)d.F * team_words(d.Mb, d.lmax, lay.team, precision != CTFISS_FP64 ? 4 : 8), c->stream);
+  return ze == hipSuccess ? CTFISS_OK : CTFISS_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctfiss_workspace_size(const ctfiss_shape* shape, int precision, size_t* bytes) {
+  if (!bytes) return CTFISS_E_ARG;
+  Dims d;
+  const int st = validate_shape(shape, precision, &d);
+  if (st != CTFISS_OK) return st;
+  *bytes = make_layout(d, precision).total;
+  return CTFISS_OK;
+}
+
+int ctfiss_create(const ctfiss_shape* shape, int precision, int rule, int vrule, double floor, void* workspace,
+                  size_t workspace_bytes, void* stream, ctfiss_ctx** out) {
+  if (!out || !workspace) return CTFISS_E_ARG;
+  Dims d;
+  Layout lay;
+  int st = check_create_args(shape, precision, rule, vrule, floor, &d, &lay);
+  if (st != CTFISS_OK) return st;
+  if (workspace_bytes < lay.total || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+    return CTFISS_E_WORKSPACE;
+  ctfiss_ctx* c = new (std::nothrow) ctfiss_ctx();
+  if (!c) return CTFISS_E_ARG;
+  st = init_ctx(c, d, lay, precision, rule, vrule, floor, workspace, stream);
+  if (st != CTFISS_OK) {
     delete c;
-    return CTFISS_E_HIP;
+    return st;
   }
   *out = c;
   return CTFISS_OK;
@@ -733,6 +764,75 @@ int ctfiss_destroy(ctfiss_ctx* c) {
   return CTFISS_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ static scratch
+// The workspace of ctfiss_separate_noalloc: a fixed device array, one copy per
+// GPU the library runs on, held until the process ends.  Host code never
+// passes `scratch` itself to the device (on the host the name stands for a
+// host-side shadow); it uses the device address hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+namespace {
+constexpr size_t kStaticScratchBytes = (size_t)96 << 20;
+constexpr int kMaxScratchDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex& scratch_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+// Device address of the current device's copy of `scratch`.
+int static_scratch(void** out) {
+  static void* addr[kMaxScratchDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CTFISS_E_HIP;
+  if (dev < 0 || dev >= kMaxScratchDevices) return CTFISS_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mutex());
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CTFISS_E_HIP;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return CTFISS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctfiss_separate_noalloc(const ctfiss_shape* shape, int precision, int rule, int vrule, double floor,
+                            const void* X, const void* W0, const void* B0, const void* V0, int32_t n_iter, void* C,
+                            void* W, void* B, void* V, int32_t* status, void* stream) {
+  if (!X || !B0 || !V0 || n_iter < 0) return CTFISS_E_ARG;
+  Dims d;
+  Layout lay;
+  int st = check_create_args(shape, precision, rule, vrule, floor, &d, &lay);
+  if (st != CTFISS_OK) return st;
+  if (lay.total > kStaticScratchBytes) return CTFISS_E_TOO_LARGE;
+  void* ws = nullptr;
+  st = static_scratch(&ws);
+  if (st != CTFISS_OK) return st;
+  // the calls a caller with its own workspace makes, on a context held on the stack
+  // (no graphs, no profiling events: it owns no resources)
+  ctfiss_ctx c{};
+  st = init_ctx(&c, d, lay, precision, rule, vrule, floor, ws, stream);
+  if (st == CTFISS_OK) st = ctfiss_set_input(&c, X);
+  if (st == CTFISS_OK) st = ctfiss_set_state(&c, W0, B0, V0);
+  if (st == CTFISS_OK) st = ctfiss_iterate(&c, n_iter, nullptr);
+  if (st == CTFISS_OK && C) st = ctfiss_source_images(&c, C);
+  if (st == CTFISS_OK) st = ctfiss_get_state(&c, W, B, V);
+  if (st == CTFISS_OK && status &&
+      hipMemcpyAsync(status, c.ptr.status, sizeof(int32_t), hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+    st = CTFISS_E_HIP;
+  return st;
+}
+
 const char* ctfiss_status_string(int status) {
   switch (status) {
     case CTFISS_OK: return "ok";
@@ -743,6 +843,7 @@ const char* ctfiss_status_string(int status) {
     case CTFISS_E_ORDER: return "input or state not set";
     case CTFISS_E_HIP: return "HIP runtime error";
     case CTFISS_E_NUMERIC: return "device numeric fault latched";
+    case CTFISS_E_TOO_LARGE: return "workspace of this shape exceeds the library's static scratch";
     default: return "unknown status";
   }
 }

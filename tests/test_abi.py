@@ -84,5 +84,26 @@ def test_create_rejects_bad_arguments_before_hip(binding):
     for fn in ("ctfiss_iterate", "ctfiss_destroy", "ctfiss_sync_status"):
         args = {"ctfiss_iterate": (None, 1, None), "ctfiss_destroy": (None,), "ctfiss_sync_status": (None, None)}[fn]
         assert getattr(lib, fn)(*args) == b.CTFISS_E_ARG
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         assert b.ctfiss_status_string(code) != "unknown status"
+
+
+def test_noalloc_rejects_shapes_beyond_its_scratch_before_hip(binding):
+    """ctfiss_separate_noalloc checks the workspace of the shape against its static scratch
+    (96 MiB) before any HIP call: the 60 s, Mbar = 64 shape needs ~1.2 GiB."""
+    b = binding
+    lib = b._lib
+    fake = ctypes.c_void_p(256)  # never dereferenced
+    big = b.make_shape(2049, 938, 4, 16, 3, 30, (22, 21, 21))
+    assert b.ctfiss_workspace_size(big, b.CTFISS_FP32) > (96 << 20)
+    st = lib.ctfiss_separate_noalloc(ctypes.byref(big), 0, 0, 0, 1e-8, fake, None, fake, fake, 1, fake, None, None,
+                                     None, None, None)
+    assert st == b.CTFISS_E_TOO_LARGE
+    small = b.make_shape(8, 20, 2, 1, 2, 3, (1, 1))
+    assert lib.ctfiss_separate_noalloc(ctypes.byref(small), 0, 0, 0, 1e-8, None, None, fake, fake, 1, fake, None, None,
+                                       None, None, None) == b.CTFISS_E_ARG
+    assert lib.ctfiss_separate_noalloc(ctypes.byref(small), 0, 0, 0, 1e-8, fake, None, fake, fake, -1, fake, None,
+                                       None, None, None, None) == b.CTFISS_E_ARG
+    bad = b.make_shape(8, 20, 2, 1, 2, 3, (2, 1))
+    assert lib.ctfiss_separate_noalloc(ctypes.byref(bad), 0, 0, 0, 1e-8, fake, None, fake, fake, 1, fake, None, None,
+                                       None, None, None) == b.CTFISS_E_SHAPE
