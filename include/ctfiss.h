@@ -266,7 +266,10 @@ int ctfiss_kernel_stats(ctfiss_ctx* ctx, int which, int64_t* launches, double* t
 /* ---------------------------------------------------------------- batches
  * Many independent mixtures of uneven shape (T, M, D, N, taps, K may differ)
  * separated together.  Every mixture gets the same iteration as a single
- * context (same results, bit for bit, for the same shape and precision), but
+ * context of the same shape and precision (the same results bit for bit as one
+ * created with CTFISS_UNFUSED_NMF in the environment, whose bins leave lambda
+ * and the basis update to separate launches; the default single context sums
+ * those in another order), but
  * an iteration is a handful of launches over all mixtures: the W update is
  * one persistent launch per launch shape over the (mixture, bin) items of
  * every mixture of that shape, and each NMF step is one launch over the

@@ -249,6 +249,12 @@ hipError_t launch_sum_parts(const double* part, int n, double* out, hipStream_t 
   return hipGetLastError();
 }
 size_t images_lds(const Dims& d) { return out_lds_bytes(d.Mb, d.M, d.N); }
+size_t wupdate_lds(int rule, const Plan& p, const Dims& d, int rsize) {
+  const bool nmf = p.nmf && rule == 0 && p.team <= 1;
+  return iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, rsize, rule != 0, p.team, p.slice,
+                         nmf ? d.K : 0)
+      .total;
+}
 size_t nll_lds(const Dims& d) { return nll_lds_bytes(d.Mb); }
 
 }  // namespace ctfiss
@@ -361,7 +367,7 @@ struct ctfiss_ctx {
   Plan plan;
   VSplit vs;
   bool have_input, have_state;
-  bool y_valid;  // the carried Y holds W xbar of the current W (ISS)
+  bool y_valid;    // the carried Y holds W xbar of the current W (ISS)
   unsigned epoch;  // tag base of the last team launch's exchange words
   bool graph;      // ctfiss_iterate replays captured HIP graphs
   struct GraphEntry {
@@ -459,9 +465,29 @@ int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int
   // Persistent W-update workgroups: as many as fit on the device at once
   // (CTFISS_WBLOCKS in the environment overrides it, for tuning); any count
   // >= 1 gives the same result, since the workgroups share out the bins.
-  plan.blocks = precision == CTFISS_MIXED ? resident_wblocks<float, true>(rule, plan, d)
-                : precision == CTFISS_FP32 ? resident_wblocks<float>(rule, plan, d)
-                                           : resident_wblocks<double>(rule, plan, d);
+  auto resident = [&](const Plan& p) {
+    return precision == CTFISS_MIXED ? resident_wblocks<float, true>(rule, p, d)
+           : precision == CTFISS_FP32 ? resident_wblocks<float>(rule, p, d)
+                                      : resident_wblocks<double>(rule, p, d);
+  };
+  plan.blocks = resident(plan);
+  // Single-workgroup ISS bins form 1/lambda and update b themselves (no separate
+  // lambda and basis-update launches), with the activations in LDS, where that
+  // layout fits without fewer workgroups in flight (e.g. Mbar <= 8, K = 3, where
+  // an iteration is bound by launch latency; not Mbar = 24, K = 20, where the
+  // activations' 50 KB would halve the workgroups per CU).  CTFISS_UNFUSED_NMF in
+  // the environment keeps the separate launches.
+  const bool unfused = std::getenv("CTFISS_UNFUSED_NMF") != nullptr;
+  if (rule == CTFISS_RULE_ISS && plan.team <= 1 && !unfused) {
+    Plan q = plan;
+    q.nmf = 1;
+    q.lds = wupdate_lds(rule, q, d, precision != CTFISS_FP64 ? 4 : 8);
+    if (q.lds <= (size_t)max_lds) {
+      q.blocks = resident(q);
+      const int need = plan.blocks < d.F ? plan.blocks : d.F;
+      if (q.blocks >= need) plan = q;
+    }
+  }
   // A team's waits end only once all its members run together: a team plan
   // needs at least `team` resident workgroups.
   const int items = d.F * (plan.team > 1 ? plan.team : 1);
@@ -596,16 +622,20 @@ int enqueue_iterations(ctfiss_ctx* c, int32_t n_iter) {
   hipStream_t s = c->stream;
   for (int it = 0; it < n_iter; ++it) {
     const bool mu = it > 0;  // the previous iteration's scale is still to be applied
-    hipError_t e = timed(c, 5, [&] { return f32 ? lambda_t<float>(d, p, mu, s) : lambda_t<double>(d, p, mu, s); });
+    // 1/lambda: formed per bin by the W update itself (plan.nmf), else by its own launch
+    const bool nmf = c->plan.nmf != 0;
+    hipError_t e = hipSuccess;
+    if (!nmf) e = timed(c, 5, [&] { return f32 ? lambda_t<float>(d, p, mu, s) : lambda_t<double>(d, p, mu, s); });
     c->epoch = c->epoch % 0x1FFFFFFu + 1u;  // tags epoch * 128 + step stay within 32 bits
     if (e == hipSuccess)
       e = timed(c, 0, [&] {
-        if (c->prec == CTFISS_MIXED) return wupdate_t<float, true>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, s);
-        return f32 ? wupdate_t<float>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, s)
-                   : wupdate_t<double>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, s);
+        if (c->prec == CTFISS_MIXED)
+          return wupdate_t<float, true>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, c->floor, s);
+        return f32 ? wupdate_t<float>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, c->floor, s)
+                   : wupdate_t<double>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, c->floor, s);
       });
     if (e == hipSuccess && c->rule == CTFISS_RULE_ISS) c->y_valid = true;
-    if (e == hipSuccess)
+    if (e == hipSuccess && !nmf)
       e = timed(c, 6, [&] {
         return f32 ? nmfb_t<float>(d, p, c->floor, mu, s) : nmfb_t<double>(d, p, c->floor, mu, s);
       });
@@ -981,6 +1011,13 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
   p.gphi = ws + L.gphi;
   p.ztape = ws + L.zt;
   p.dtape = ws + L.dt;
+  // the iterations re-run below stop before the rescale and need lambda, the basis
+  // update and the activation update from their own launches
+  Plan sep = c->plan;
+  if (sep.nmf) {
+    sep.nmf = 0;
+    sep.lds = wupdate_lds(c->rule, sep, d, rs);
+  }
   // images: the first contributions to gW and gX
   e = adj_images(p, d, c->ptr.W, gC, rs, s);
   if (e == hipSuccess) e = hipMemsetAsync(p.gB, 0, bb, s);
@@ -994,13 +1031,13 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
     c->epoch = c->epoch % 0x1FFFFFFu + 1u;
     if (f32) {
       if (e == hipSuccess) e = lambda_t<float>(d, c->ptr, false, s);
-      if (e == hipSuccess) e = wupdate_t<float>(c->rule, c->plan, d, c->ptr, false, false, c->epoch, s);
+      if (e == hipSuccess) e = wupdate_t<float>(c->rule, sep, d, c->ptr, false, false, c->epoch, c->floor, s);
       if (e == hipSuccess) e = nmfb_t<float>(d, c->ptr, c->floor, false, s);
       if (e == hipSuccess) e = vpart_t<float>(d, c->vs, c->ptr, false, s);
       if (e == hipSuccess) e = vfinal_t<float>(d, c->vs, c->ptr, c->floor, false, s);
     } else {
       if (e == hipSuccess) e = lambda_t<double>(d, c->ptr, false, s);
-      if (e == hipSuccess) e = wupdate_t<double>(c->rule, c->plan, d, c->ptr, false, false, c->epoch, s);
+      if (e == hipSuccess) e = wupdate_t<double>(c->rule, sep, d, c->ptr, false, false, c->epoch, c->floor, s);
       if (e == hipSuccess) e = nmfb_t<double>(d, c->ptr, c->floor, false, s);
       if (e == hipSuccess) e = vpart_t<double>(d, c->vs, c->ptr, false, s);
       if (e == hipSuccess) e = vfinal_t<double>(d, c->vs, c->ptr, c->floor, false, s);
@@ -1116,6 +1153,11 @@ int ctfiss_autotune(ctfiss_ctx* c, int32_t trials, void* scratch, size_t scratch
   const bool f32 = c->prec != CTFISS_FP64;
   for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
     Plan p = cand[i];
+    if (c->plan.nmf && p.team <= 1) {
+      p.nmf = 1;
+      p.lds = wupdate_lds(c->rule, p, d, (int)rs);
+      if (p.lds > (size_t)max_lds) continue;
+    }
     p.blocks = c->prec == CTFISS_MIXED ? resident_wblocks<float, true>(c->rule, p, d)
                : f32                   ? resident_wblocks<float>(c->rule, p, d)
                                        : resident_wblocks<double>(c->rule, p, d);
@@ -1127,19 +1169,21 @@ int ctfiss_autotune(ctfiss_ctx* c, int32_t trials, void* scratch, size_t scratch
       if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
       if (e == hipSuccess) {
         if (c->prec == CTFISS_MIXED)
-          e = wupdate_t<float, true>(c->rule, p, d, c->ptr, false, false, c->epoch, c->stream);
+          e = wupdate_t<float, true>(c->rule, p, d, c->ptr, false, false, c->epoch, c->floor, c->stream);
         else if (f32)
-          e = wupdate_t<float>(c->rule, p, d, c->ptr, false, false, c->epoch, c->stream);
+          e = wupdate_t<float>(c->rule, p, d, c->ptr, false, false, c->epoch, c->floor, c->stream);
         else
-          e = wupdate_t<double>(c->rule, p, d, c->ptr, false, false, c->epoch, c->stream);
+          e = wupdate_t<double>(c->rule, p, d, c->ptr, false, false, c->epoch, c->floor, c->stream);
       }
       if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (t > 0) total += ms;
-      // back to the saved state for the next run
+      // back to the saved state for the next run (a W update with the basis update
+      // folded in also changes B)
       if (e == hipSuccess) e = hipMemcpyAsync(c->ptr.W, save, wb, hipMemcpyDeviceToDevice, c->stream);
+      if (e == hipSuccess && p.nmf) e = hipMemcpyAsync(c->ptr.B, saveB, bb, hipMemcpyDeviceToDevice, c->stream);
     }
     // a candidate whose runs latched a fault (e.g. a team wait that ran out) is not taken
     int fc = 0;

@@ -184,12 +184,13 @@ __device__ __forceinline__ int find_problem(const int* start, int nprob, int ite
 // During the sweep: x, w, phi, yb, wb (+ q, aug, u, fac for IP).  After it the
 // per-row powers |y|^2, a[Mb][TP], reuse the same bytes from offset 0.
 struct IterLds {
-  size_t x, w, phi, yb, wb, q, aug, u, fac, a, xv, misc, total;
+  size_t x, w, phi, yb, wb, q, aug, u, fac, a, xv, bs, pw, vl, misc, total;
   int lx, lp, tp, lmax;
   int rc;     // IP: rows whose inverse weighted covariances are held at once
   int team;   // workgroups per bin (1: a bin is one workgroup)
   int slice;  // frames per team member (T for a single workgroup)
   int ta;     // row stride of a (TP, plus the Lmax - 1 frames of the next member in a team)
+  int kb;     // K when the kernel also forms 1/lambda and updates b per bin (0: it does not)
 };
 
 // Exchange words of one bin in a team launch (64-bit words, one 32-bit
@@ -215,8 +216,12 @@ __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a -
 
 // team > 1: the bin's frames are split over `team` workgroups of `slice`
 // frames each (slice <= G * cpl); the layout is that of one member.
+// kb > 0 (single-workgroup ISS): the kernel also forms 1/lambda from b and v and
+// updates b per bin; then phi, the scaled bases bs [N][kb], the tap-aligned
+// powers pw [N][T] and the activations vl [N][kb][T] (loaded once per launch)
+// outlive the sweep (placed after the shared region).
 __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, int N, int lmax, int G, int cpl,
-                                                   int rsize, bool ip, int team = 1, int slice = 0) {
+                                                   int rsize, bool ip, int team = 1, int slice = 0, int kb = 0) {
   IterLds L{};
   const size_t cs = 2 * (size_t)rsize;
   L.tp = G * cpl;
@@ -226,10 +231,13 @@ __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, 
   L.team = team > 1 ? team : 1;
   L.slice = team > 1 ? slice : T;
   L.ta = team > 1 ? L.tp + lmax - 1 : L.tp;
+  L.kb = (!ip && L.team == 1) ? kb : 0;
   size_t off = 0;
   L.x = off; off += align_up((size_t)M * L.lx * cs, 16);
   L.w = off; off += align_up((size_t)Mb * Mb * cs, 16);
-  L.phi = off; off += align_up((size_t)N * L.lp * rsize, 16);
+  if (!L.kb) {
+    L.phi = off; off += align_up((size_t)N * L.lp * rsize, 16);
+  }
   if (!ip) {  // the ISS broadcasts of y_r and w_r (w_r held in FP64 by the mixed-precision sweep)
     L.yb = off; off += align_up((size_t)2 * L.tp * cs, 16);
     L.wb = off; off += align_up((size_t)2 * Mb * 16, 16);
@@ -259,6 +267,13 @@ __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, 
   L.a = 0;
   const size_t asz = align_up((size_t)Mb * L.ta * rsize, 16);
   if (asz > off) off = asz;
+  L.bs = L.pw = L.vl = 0;
+  if (L.kb) {
+    L.phi = off; off += align_up((size_t)N * L.lp * rsize, 16);
+    L.bs = off; off += align_up((size_t)N * L.kb * rsize, 16);
+    L.pw = off; off += align_up((size_t)N * T * rsize, 16);
+    L.vl = off; off += align_up((size_t)N * L.kb * T * rsize, 16);
+  }
   // team: 32-bit payloads of the exchange words a wave gathers (one step's
   // partial sums of every row; also the row powers of the epilogue)
   L.xv = off;

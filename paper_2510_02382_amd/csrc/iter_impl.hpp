@@ -39,6 +39,12 @@ struct IterArgs {
   int yload;        // 1: start from the carried Y (rows scaled by the pending mu), 0: Y = W xbar
   unsigned long long* xch;  // team launches: [F][team_words] exchange words, else null
   unsigned epoch;           // team launches: tag base of this launch's exchange words
+  // Kernels with the NMF steps folded in (single-workgroup ISS): 1/lambda formed per
+  // bin from b and v instead of read from ilam, and the basis update of Eq. (17) done
+  // per bin after the sweep
+  R* B;             // [N][F][K] bases (in/out there)
+  const R* V;       // [N][K][T] activations (read there)
+  R floor;          // factor floor of the basis update
   int F, T, M, D, K;
   RowMap rm;
 };
@@ -56,6 +62,9 @@ struct BinLds {
   Cx<R>* fac;  // [Mb+1] (IP)
   R* a;        // [Mb][TA] |y|^2 after the sweep (reuses the bytes above)
   unsigned* xv;  // team: gathered exchange payloads
+  R* bs;       // fused: [N][K] b_{n,f,k} of the bin with the pending scale applied
+  R* pw;       // fused: [N][T] tap-aligned powers of the bin
+  R* vl;       // fused: [N][K][T] the activations (loaded once per launch)
   int* misc;
 };
 
@@ -73,6 +82,9 @@ __device__ __forceinline__ BinLds<R> carve(unsigned char* base, const IterLds& L
   s.fac = reinterpret_cast<Cx<R>*>(base + L.fac);
   s.a = reinterpret_cast<R*>(base + L.a);
   s.xv = reinterpret_cast<unsigned*>(base + L.xv);
+  s.bs = reinterpret_cast<R*>(base + L.bs);
+  s.pw = reinterpret_cast<R*>(base + L.pw);
+  s.vl = reinterpret_cast<R*>(base + L.vl);
   s.misc = reinterpret_cast<int*>(base + L.misc);
   return s;
 }
@@ -129,7 +141,7 @@ __device__ __forceinline__ void stage_lds(int n, int tid, int nthr, Ld ld, St st
 // Stage 1: scaled W_f, zero-padded observation block and inverse variances into LDS.
 // The frames staged start at t0 (a team member's first frame; 0 otherwise).
 // U: loads in flight per thread (1 where the caller's registers are scarce).
-template <int U, typename R>
+template <int U, typename R, bool NMF = false>
 __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid,
                          bool need_x, int t0 = 0) {
   const int nthr = blockDim.x;
@@ -155,14 +167,107 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
         return (t >= 0 && t < T) ? a.X[((size_t)m * F + f) * T + t] : Cx<R>{R(0), R(0)};
       },
       [&](int i, Cx<R> v) { s.x[i] = v; });
-  stage_lds<U, R>(
-      N * LP, tid, nthr,
-      [&](int i) {
-        const int n = i / LP, t = i - n * LP - Lm1 + t0;
-        return (t >= 0 && t < T) ? a.ilam[((size_t)n * F + f) * T + t] : R(0);
-      },
-      [&](int i, R v) { s.phi[i] = v; });
+  if constexpr (NMF) {
+    // b of the bin with the pending scale applied (as the basis update and lambda = b v
+    // apply it); phi's frames are formed after the barrier, its padding cleared here
+    const int K = a.K;
+    for (int i = tid; i < N * K; i += nthr) {
+      const int n = i / K;
+      R sc = R(1);
+      if (a.mu) {
+        const R m = a.mu[a.rm.r0[n]];
+        sc = R(1) / (m * m);
+      }
+      s.bs[i] = a.B[((size_t)n * F + f) * K + (i - n * K)] * sc;
+    }
+    for (int i = tid; i < N * LP; i += nthr) {
+      const int n = i / LP, t = i - n * LP - Lm1;
+      if (t < 0 || t >= T) s.phi[i] = R(0);
+    }
+  } else {
+    stage_lds<U, R>(
+        N * LP, tid, nthr,
+        [&](int i) {
+          const int n = i / LP, t = i - n * LP - Lm1 + t0;
+          return (t >= 0 && t < T) ? a.ilam[((size_t)n * F + f) * T + t] : R(0);
+        },
+        [&](int i, R v) { s.phi[i] = v; });
+  }
   __syncthreads();
+}
+
+// Fused: phi[n][Lmax-1 + t] = 1 / lambda_{n,f,t}, lambda = sum_k b v (Sec. II), from the
+// staged b and the activations the workgroup holds in LDS (the same for every bin).
+// Ends with a barrier.
+template <typename R>
+__device__ void form_phi(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int tid) {
+  const int T = a.T, K = a.K, N = a.rm.N, nthr = blockDim.x, LP = L.lp, Lm1 = L.lmax - 1;
+  bool bad = false;
+  for (int i = tid; i < N * T; i += nthr) {
+    const int n = i / T, t = i - n * T;
+    const R* b = s.bs + n * K;
+    const R* v = s.vl + (size_t)n * K * T + t;
+    R lam = R(0);
+    for (int k = 0; k < K; ++k) lam += b[k] * v[k * T];
+    bad |= !finite_pos(lam);
+    s.phi[n * LP + Lm1 + t] = R(1) / lam;
+  }
+  latch_wave(a.status, bad, kFaultMu);
+  __syncthreads();
+}
+
+// Fused: the basis update of Eq. (17) for bin f with t' = t - l,
+//   num_k = sum_t' P_{t'} v_{k,t'} / lambda_{t'}^2,  den_k = sum_t' C_{t'} v_{k,t'} / lambda_{t'},
+//   C_{t'} = #{l < L_n : t' + l < T};  b <- max(b sqrt(num / den), floor)
+// (b with the pending scale, as staged).  Each (n, k) takes a group of S = 64, 32
+// or 16 lanes (the largest with every pair in one pass where possible); lane j adds
+// frames j, j + S, ..., and the group's sums are one DPP butterfly.  Starts with a
+// barrier (pw written).
+template <typename R, int S>
+__device__ __forceinline__ bool b_update_groups(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f,
+                                                int tid) {
+  const int T = a.T, K = a.K, N = a.rm.N, F = a.F, nthr = blockDim.x, LP = L.lp, Lm1 = L.lmax - 1;
+  const int NK = N * K, total = NK * S;
+  bool bad = false;
+  for (int o0 = 0; o0 < total; o0 += nthr) {  // the same trip count for every thread
+    const int o = o0 + tid, nk = o / S, j = o - nk * S;
+    const bool act = o < total;
+    R num = R(0), den = R(0);
+    if (act) {
+      const int n = nk / K, Ln = a.rm.L[n];
+      const R* v = s.vl + (size_t)nk * T;
+      const R* ph = s.phi + n * LP + Lm1;
+      const R* pw = s.pw + n * T;
+      for (int t = j; t < T; t += S) {
+        const R il = ph[t], vv = v[t];
+        num += pw[t] * il * il * vv;
+        den += (R)(Ln < T - t ? Ln : T - t) * il * vv;
+      }
+    }
+    num = group_sum<S>(num);
+    den = group_sum<S>(den);
+    if (act && j == 0) {
+      const int n = nk / K;
+      const R b = s.bs[nk] * sqrt(num / den);
+      bad |= !isfinite(b);
+      a.B[((size_t)n * F + f) * K + (nk - n * K)] = b > a.floor ? b : a.floor;
+    }
+  }
+  return bad;
+}
+
+template <typename R>
+__device__ void b_update(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid) {
+  const int NK = a.rm.N * a.K, nthr = blockDim.x;
+  __syncthreads();
+  bool bad;
+  if (NK * 64 <= nthr)
+    bad = b_update_groups<R, 64>(a, s, L, f, tid);
+  else if (NK * 32 <= nthr)
+    bad = b_update_groups<R, 32>(a, s, L, f, tid);
+  else
+    bad = b_update_groups<R, 16>(a, s, L, f, tid);
+  latch_wave(a.status, bad, kFaultMu);
 }
 
 // Stage 2: y_p[t] = sum_c W[p][c] xbar_c[t] for the lane's rows and frames.
@@ -234,7 +339,7 @@ __device__ __forceinline__ void load_rows(const IterArgs<R>& a, int f, int g, in
 // P_n[t] = sum_{l < L_n, t + l < T} |y_{(n,l)}[t + l]|^2 summed in tap order
 // (bitwise reproducible), P / P0 out.  Starts with a barrier: the |y|^2 rows
 // overwrite the sweep's LDS buffers.
-template <typename R, int G, int CPL, int RPL>
+template <typename R, int G, int CPL, int RPL, bool NMF = false>
 __device__ void epilogue(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid, int g,
                          int q, const Cx<R> (&y)[RPL][CPL]) {
   const int T = per_bin(a.T), Mb = a.rm.Mb, N = a.rm.N, F = a.F, TP = L.tp;
@@ -263,6 +368,7 @@ __device__ void epilogue(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
     const size_t o = ((size_t)n * F + f) * T + t;
     a.P[o] = acc;
     if (a.P0) a.P0[o] = ar[0];
+    if constexpr (NMF) s.pw[i] = acc;
   }
 }
 
@@ -490,7 +596,7 @@ __device__ bool epilogue_team(const IterArgs<R>& a, const BinLds<R>& s, const It
 // WX: the rows of W are updated in FP64 registers during the sweep (R =
 // float): its 64 rank-1 updates per iteration then add no FP32 rounding to W,
 // which is loaded from and stored to the FP32 state once per iteration.
-template <typename R, int G, int CPL, int RPL, bool TEAM = false, bool WX = false>
+template <typename R, int G, int CPL, int RPL, bool TEAM = false, bool WX = false, bool NMF = false>
 __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int mem = 0) {
   using WR = typename std::conditional<WX, double, R>::type;
   const int tid = lane_tid();
@@ -513,7 +619,8 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
   const bool rows_first = kRowsFirst && a.yload && blockDim.x <= 256;
   Cx<R> y[RPL][CPL];
   if (rows_first) load_rows<R, G, CPL, RPL>(a, f, g, q, y, t0, nloc);
-  load_bin<kRowsFirst ? 32 / sizeof(R) : 1>(a, s, L, f, tid, !a.yload, t0);
+  load_bin<kRowsFirst ? 32 / sizeof(R) : 1, R, NMF>(a, s, L, f, tid, !a.yload, t0);
+  if constexpr (NMF) form_phi<R>(a, s, L, tid);
   if (a.yload && !rows_first) load_rows<R, G, CPL, RPL>(a, f, g, q, y, t0, nloc);
   if (!a.yload) demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y, nloc);
 
@@ -641,7 +748,8 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
     wait_ok &= epilogue_team<R, G, CPL, RPL>(a, s, L, f, mem, t0, nloc, tid, g, q, y, xb);
     latch_wave(a.status, !wait_ok, kFaultTeamWait);
   } else {
-    epilogue<R, G, CPL, RPL>(a, s, L, f, tid, g, q, y);
+    epilogue<R, G, CPL, RPL, NMF>(a, s, L, f, tid, g, q, y);
+    if constexpr (NMF) b_update<R>(a, s, L, f, tid);
   }
 }
 
@@ -657,17 +765,23 @@ __device__ __forceinline__ int next_bin(const IterArgs<R>& a, const BinLds<R>& s
   return __builtin_amdgcn_readfirstlane(s.misc[0]);  // uniform: bin addressing stays scalar
 }
 
-template <typename R, int G, int CPL, int RPL, bool WX = false>
+// NMF: the bins also form 1/lambda and update b (single-workgroup plans that fit).
+template <typename R, int G, int CPL, int RPL, bool WX = false, bool NMF = false>
 __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_min_waves(sizeof(R), CPL, RPL))
     k_iss(IterArgs<R> a, IterLds L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
+  // fused: the activations, the same for every bin, into LDS once (the first bin's
+  // staging barrier orders these stores before their first use)
+  if constexpr (NMF)
+    stage_lds<32 / sizeof(R), R>(
+        a.rm.N * a.K * a.T, threadIdx.x, blockDim.x, [&](int i) { return a.V[i]; }, [&](int i, R v) { s.vl[i] = v; });
   // Bins dealt out round-robin over the resident workgroups: every bin costs
   // the same, so this balances as well as a shared counter would, without a
   // device-scope atomic round trip per bin.
   for (int f = blockIdx.x; f < a.F; f += gridDim.x) {
     if (f != (int)blockIdx.x) __syncthreads();  // the previous bin's LDS traffic is over
-    iss_bin<R, G, CPL, RPL, false, WX>(a, s, L, f);
+    iss_bin<R, G, CPL, RPL, false, WX, NMF>(a, s, L, f);
   }
 }
 

@@ -21,6 +21,7 @@ struct Plan {
   int blocks;  // persistent workgroups launched (resident ones; at most F items)
   int team = 1;
   int slice = 0;
+  int nmf = 0;  // single-workgroup ISS: also forms 1/lambda and updates b per bin (lds sized for it)
 };
 
 // Type-erased device pointers of one context.
@@ -60,7 +61,9 @@ VSplit choose_vsplit(const Dims& d);
 // ISS sweep updates the rows of W in FP64 registers (mixed precision).
 template <typename R, bool WX = false>
 hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload,
-                     unsigned epoch, hipStream_t s);
+                     unsigned epoch, double floor, hipStream_t s);
+// LDS of the W-update kernel for a plan (p.nmf included).
+size_t wupdate_lds(int rule, const Plan& p, const Dims& d, int rsize);
 template <typename R>
 hipError_t lambda_t(const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s);
 template <typename R>

@@ -14,58 +14,67 @@ template <typename R>
 using WFn = void (*)(IterArgs<R>, IterLds);
 
 // WX: ISS kernels with FP64 W rows (mixed precision, R = float; no IP kernels).
+// nmf: the ISS kernel with the NMF steps folded in, instantiated for one row per
+// lane group and at most 16 frames per lane (the plans of small Mbar and T ~ 250-500).
 template <typename R, bool WX, int G, int CPL, int RPL>
-WFn<R> wfn(int rule) {
-  if (rule == 0) return &k_iss<R, G, CPL, RPL, WX>;
-  if constexpr (RPL == 1 && !WX) return &k_ip<R, G, CPL, 1>;
+WFn<R> wfn(int rule, bool nmf) {
+  if (rule == 0) {
+    if constexpr (RPL == 1 && CPL <= 16) {
+      if (nmf) return &k_iss<R, G, CPL, RPL, WX, true>;
+    }
+    return nmf ? nullptr : &k_iss<R, G, CPL, RPL, WX>;
+  }
+  if constexpr (RPL == 1 && !WX) {
+    if (!nmf) return &k_ip<R, G, CPL, 1>;
+  }
   return nullptr;
 }
 
 template <typename R, bool WX, int G, int RPL>
-WFn<R> pick_cpl(int rule, int cpl) {
+WFn<R> pick_cpl(int rule, int cpl, bool nmf) {
   if constexpr (sizeof(R) == 4) {
     switch (cpl) {
-      case 4: return wfn<R, WX, G, 4, RPL>(rule);
-      case 8: return wfn<R, WX, G, 8, RPL>(rule);
-      case 10: return wfn<R, WX, G, 10, RPL>(rule);
-      case 12: return wfn<R, WX, G, 12, RPL>(rule);
-      case 16: return wfn<R, WX, G, 16, RPL>(rule);
-      case 20: return wfn<R, WX, G, 20, RPL>(rule);
-      case 24: return wfn<R, WX, G, 24, RPL>(rule);
-      case 28: return wfn<R, WX, G, 28, RPL>(rule);
-      case 32: return wfn<R, WX, G, 32, RPL>(rule);
+      case 4: return wfn<R, WX, G, 4, RPL>(rule, nmf);
+      case 8: return wfn<R, WX, G, 8, RPL>(rule, nmf);
+      case 10: return wfn<R, WX, G, 10, RPL>(rule, nmf);
+      case 12: return wfn<R, WX, G, 12, RPL>(rule, nmf);
+      case 16: return wfn<R, WX, G, 16, RPL>(rule, nmf);
+      case 20: return wfn<R, WX, G, 20, RPL>(rule, nmf);
+      case 24: return wfn<R, WX, G, 24, RPL>(rule, nmf);
+      case 28: return wfn<R, WX, G, 28, RPL>(rule, nmf);
+      case 32: return wfn<R, WX, G, 32, RPL>(rule, nmf);
       default: return nullptr;
     }
   } else {
     switch (cpl) {
-      case 4: return wfn<R, WX, G, 4, RPL>(rule);
-      case 6: return wfn<R, WX, G, 6, RPL>(rule);
-      case 8: return wfn<R, WX, G, 8, RPL>(rule);
-      case 10: return wfn<R, WX, G, 10, RPL>(rule);
-      case 12: return wfn<R, WX, G, 12, RPL>(rule);
-      case 16: return wfn<R, WX, G, 16, RPL>(rule);
+      case 4: return wfn<R, WX, G, 4, RPL>(rule, nmf);
+      case 6: return wfn<R, WX, G, 6, RPL>(rule, nmf);
+      case 8: return wfn<R, WX, G, 8, RPL>(rule, nmf);
+      case 10: return wfn<R, WX, G, 10, RPL>(rule, nmf);
+      case 12: return wfn<R, WX, G, 12, RPL>(rule, nmf);
+      case 16: return wfn<R, WX, G, 16, RPL>(rule, nmf);
       default: return nullptr;
     }
   }
 }
 
 template <typename R, bool WX, int G>
-WFn<R> pick_rpl(int rule, int cpl, int rpl) {
-  if (rpl == 1) return pick_cpl<R, WX, G, 1>(rule, cpl);
-  if (rpl == 2) return pick_cpl<R, WX, G, 2>(rule, cpl);
+WFn<R> pick_rpl(int rule, int cpl, int rpl, bool nmf) {
+  if (rpl == 1) return pick_cpl<R, WX, G, 1>(rule, cpl, nmf);
+  if (rpl == 2) return pick_cpl<R, WX, G, 2>(rule, cpl, nmf);
   return nullptr;
 }
 
 template <typename R, bool WX>
-WFn<R> pick(int rule, int G, int cpl, int rpl) {
+WFn<R> pick(int rule, int G, int cpl, int rpl, bool nmf = false) {
   if constexpr (WX && sizeof(R) != 4) return nullptr;
-  if (G == 16) return pick_rpl<R, WX, 16>(rule, cpl, rpl);
-  if (G == 32) return pick_rpl<R, WX, 32>(rule, cpl, rpl);
+  if (G == 16) return pick_rpl<R, WX, 16>(rule, cpl, rpl, nmf);
+  if (G == 32) return pick_rpl<R, WX, 32>(rule, cpl, rpl, nmf);
   if constexpr (sizeof(R) == 4) {
-    if (G == 64 && rpl == 1) return pick_cpl<R, WX, 64, 1>(rule, cpl);  // long frames, Mbar <= 16
+    if (G == 64 && rpl == 1) return pick_cpl<R, WX, 64, 1>(rule, cpl, nmf);  // long frames, Mbar <= 16
   }
   if constexpr (sizeof(R) == 8) {
-    if (G == 64) return pick_rpl<R, WX, 64>(rule, cpl, rpl);
+    if (G == 64) return pick_rpl<R, WX, 64>(rule, cpl, rpl, nmf);
   }
   return nullptr;
 }
@@ -99,7 +108,8 @@ bool have_tkernel(int G, int cpl, int rpl) {
 
 template <typename R, bool WX>
 WFn<R> pick_plan(int rule, const Plan& p) {
-  return p.team > 1 ? (rule == 0 ? pickt<R, WX>(p.G, p.CPL, p.RPL) : nullptr) : pick<R, WX>(rule, p.G, p.CPL, p.RPL);
+  if (p.team > 1) return (rule == 0 && !p.nmf) ? pickt<R, WX>(p.G, p.CPL, p.RPL) : nullptr;
+  return pick<R, WX>(rule, p.G, p.CPL, p.RPL, p.nmf != 0);
 }
 
 // Workgroups of the W-update kernel that fit on the device at once.
@@ -118,8 +128,11 @@ int resident_wblocks(int rule, const Plan& p, const Dims& d) {
 }
 
 template <typename R>
-IterArgs<R> make_iargs(int rule, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload) {
+IterArgs<R> make_iargs(int rule, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload, double floor = 0.0) {
   IterArgs<R> a;
+  a.B = static_cast<R*>(ptr.B);
+  a.V = static_cast<const R*>(ptr.V);
+  a.floor = (R)floor;
   a.X = static_cast<const Cx<R>*>(ptr.X);
   a.W = static_cast<Cx<R>*>(ptr.W);
   a.ilam = static_cast<const R*>(ptr.ilam);
@@ -143,15 +156,17 @@ IterArgs<R> make_iargs(int rule, const Dims& d, const Ptrs& ptr, bool apply_mu, 
 }
 
 inline IterLds wlayout(int rule, const Plan& p, const Dims& d, int rsize) {
-  return iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, rsize, rule != 0, p.team, p.slice);
+  const bool nmf = p.nmf && rule == 0 && p.team <= 1;
+  return iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, rsize, rule != 0, p.team, p.slice,
+                         nmf ? d.K : 0);
 }
 
 template <typename R, bool WX>
 hipError_t wupdate_t(int rule, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload,
-                     unsigned epoch, hipStream_t s) {
+                     unsigned epoch, double floor, hipStream_t s) {
   WFn<R> fn = pick_plan<R, WX>(rule, p);
   if (!fn || (p.team > 1 && !ptr.xch)) return hipErrorInvalidValue;
-  IterArgs<R> a = make_iargs<R>(rule, d, ptr, apply_mu, yload);
+  IterArgs<R> a = make_iargs<R>(rule, d, ptr, apply_mu, yload, floor);
   a.epoch = epoch;
   const IterLds L = wlayout(rule, p, d, (int)sizeof(R));
   if (L.total > 65536) {
@@ -288,9 +303,11 @@ size_t wdesc_bytes() {
 template <typename R>
 void fill_wdesc(void* dst, const Plan& p, const Dims& d, const Ptrs& ptr, bool apply_mu, bool yload) {
   WDesc<R> w;
-  w.a = make_iargs<R>(0, d, ptr, apply_mu, yload);
+  w.a = make_iargs<R>(0, d, ptr, apply_mu, yload);  // batched bins keep the separate NMF launches
   w.a.xch = nullptr;
-  w.L = wlayout(0, p, d, (int)sizeof(R));
+  Plan q = p;
+  q.nmf = 0;
+  w.L = wlayout(0, q, d, (int)sizeof(R));
   std::memcpy(dst, &w, sizeof(w));
 }
 
@@ -447,7 +464,7 @@ hipError_t identity_t(const Dims& d, void* W, hipStream_t s) {
 // The launchers of the W update for one arithmetic of the W rows (WX).
 #define CTFISS_INSTANTIATE_W(R, WX)                                                                            \
   template hipError_t wupdate_t<R, WX>(int, const Plan&, const Dims&, const Ptrs&, bool, bool, unsigned,       \
-                                       hipStream_t);                                                           \
+                                       double, hipStream_t);                                                   \
   template bool have_wkernel<R, WX>(int, int, int, int);                                                      \
   template bool have_tkernel<R, WX>(int, int, int);                                                           \
   template int resident_wblocks<R, WX>(int, const Plan&, const Dims&);

@@ -224,6 +224,43 @@ __device__ __forceinline__ void nmfb_block(const NmfArgs<R>& a, const int bx, co
 template <typename R>
 __global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) { nmfb_block<R>(a, blockIdx.x, blockIdx.y, blockDim.x >> 6); }
 
+// Scale of row r, Eq. (19): mu_r = sqrt(sum_f musq[r][f] / (F T)).  Thread i adds
+// f = i, i + 256, ...; then a tree over the 256 threads: every caller gets the same
+// value bit for bit.  All 256 threads of the workgroup call it; red: 256 values of LDS.
+template <typename R>
+__device__ __forceinline__ R row_scale(const NmfArgs<R>& a, int r, R* red) {
+  const int tid = threadIdx.x;
+  R acc = 0;
+  for (int f = tid; f < a.F; f += 256) acc += a.musq[(size_t)r * a.F + f];
+  red[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const R m = sqrt(red[0] / (R(a.F) * R(a.T)));
+  __syncthreads();  // red may be reused
+  return m;
+}
+
+// v_{n,k,t} <- max(v sqrt(num / (C' den)), floor) from the chunk partials summed in
+// chunk order; C' = #{l < L_n : t + l < T} (ALL_TAPS) or 1 (PAPER_TAP0).
+template <typename R>
+__device__ __forceinline__ R vfinal_value(const NmfArgs<R>& a, int n, int k, int t, bool& bad) {
+  const int T = a.T, K = a.K;
+  R num = 0, den = 0;
+#pragma unroll 8
+  for (int ch = 0; ch < a.nch; ++ch) {
+    const size_t o = (((size_t)n * a.nch + ch) * K + k) * T + t;
+    num += a.vnum[o];
+    den += a.vden[o];
+  }
+  const R c = a.tap0 ? R(1) : (R)min(a.rm.L[n], T - t);
+  const R v = a.V[((size_t)n * K + k) * T + t] * sqrt(num / (c * den));
+  bad |= !isfinite(v);
+  return v > a.floor ? v : a.floor;
+}
+
 // Partial sums over one chunk of bins of
 //   num[k][t] = sum_f b_{f,k} P'_{f,t} / lambda_{f,t}^2,  den[k][t] = sum_f b_{f,k} / lambda_{f,t},
 // with lambda = b v recomputed from the updated bases.  One wave per 16 frames
@@ -306,17 +343,18 @@ __device__ __forceinline__ void vpart_block(const NmfArgs<R>& a, const int bx, c
     }
     __syncthreads();
   }
-  if (wave != 0 || tb >= T) return;
+  if (wave == 0 && tb < T) {
 #pragma unroll
-  for (int kt = 0; kt < KT; ++kt) {
-    if (kt >= nkt) continue;
+    for (int kt = 0; kt < KT; ++kt) {
+      if (kt >= nkt) continue;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int k = 16 * kt + acc_row<R>(lq, v);
-      if (k < K) {
-        const size_t o = (((size_t)n * a.nch + ch) * K + k) * T + tb;
-        a.vnum[o] = red[0][kt][v][l];
-        a.vden[o] = red[1][kt][v][l];
+      for (int v = 0; v < 4; ++v) {
+        const int k = 16 * kt + acc_row<R>(lq, v);
+        if (k < K) {
+          const size_t o = (((size_t)n * a.nch + ch) * K + k) * T + tb;
+          a.vnum[o] = red[0][kt][v][l];
+          a.vden[o] = red[1][kt][v][l];
+        }
       }
     }
   }
@@ -333,17 +371,9 @@ __device__ __forceinline__ void vfinal_block(const NmfArgs<R>& a, const int nvbl
   const int T = a.T, K = a.K, N = a.rm.N;
   if (bx >= nvblocks) {
     __shared__ R red[256];
-    const int r = bx - nvblocks, F = a.F;
-    R acc = 0;
-    for (int f = threadIdx.x; f < F; f += blockDim.x) acc += a.musq[(size_t)r * F + f];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
+    const int r = bx - nvblocks;
+    const R m = row_scale(a, r, red);
     if (threadIdx.x == 0) {
-      const R m = sqrt(red[0] / (R(F) * R(T)));
       if (!finite_pos(m)) latch(a.status, kFaultScale);
       a.mu[r] = m;
     }
@@ -352,17 +382,10 @@ __device__ __forceinline__ void vfinal_block(const NmfArgs<R>& a, const int nvbl
   const int i = bx * blockDim.x + threadIdx.x;
   if (i >= N * K * T) return;
   const int n = i / (K * T), k = (i / T) % K, t = i % T;
-  R num = 0, den = 0;
-#pragma unroll 8
-  for (int ch = 0; ch < a.nch; ++ch) {
-    const size_t o = (((size_t)n * a.nch + ch) * K + k) * T + t;
-    num += a.vnum[o];
-    den += a.vden[o];
-  }
-  const R c = a.tap0 ? R(1) : (R)min(a.rm.L[n], T - t);
-  R v = a.V[i] * sqrt(num / (c * den));
-  latch_wave(a.status, !isfinite(v), kFaultMu);
-  a.V[i] = v > a.floor ? v : a.floor;
+  bool bad = false;
+  const R v = vfinal_value(a, n, k, t, bad);
+  latch_wave(a.status, bad, kFaultMu);
+  a.V[i] = v;
 }
 
 template <typename R>

@@ -1,10 +1,10 @@
 """Batches of uneven mixtures (ctfiss_batch_*) against single contexts.
 
 A batch runs, per mixture, the iteration a single context runs on the same
-launch shape (the W update per bin, the NMF steps per workgroup in the same
-order), so its images must equal the single-context images bit for bit.  The
-single-context path itself is checked against the FP64 oracle in
-test_gpu_parity.py.
+launch shape with its NMF steps as separate launches (CTFISS_UNFUSED_NMF):
+the W update per bin, the NMF steps per workgroup in the same order, so its
+images must equal those single-context images bit for bit.  Mixtures drawn
+as the batched workload are also checked against the FP64 oracle directly.
 """
 import numpy as np
 import pytest
@@ -54,8 +54,12 @@ def _single(precision, rule, probs, splits):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_batch_equals_single_contexts(precision):
+def test_batch_equals_single_contexts(precision, monkeypatch):
+    """The batch runs each mixture's NMF steps as separate launches over all mixtures; a single
+    context does the same with CTFISS_UNFUSED_NMF (by default its bins form 1/lambda and the
+    basis update themselves, which changes only the order of some sums)."""
     from paper_2510_02382_amd import BatchSeparator
+    monkeypatch.setenv("CTFISS_UNFUSED_NMF", "1")
     probs = _problems(precision)
     ref = _single(precision, "iss", probs, (4, 3))
     bs = BatchSeparator(SHAPES, precision=precision)

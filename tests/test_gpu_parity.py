@@ -449,3 +449,25 @@ def test_autotune_keeps_a_fault_latched_before_it():
     assert sep.plan() == plan
     sep.close()
     b.ctfiss_clear_tuned_plans()
+
+
+# ------------------------------------------------------------------ fused and separate NMF launches
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "mixed"])
+@pytest.mark.parametrize("case,vrule", [("c1_like", "all_taps"), ("three_src", "paper_tap0"), ("ragged", "all_taps"),
+                                        ("long_frames", "all_taps"), ("short_T", "all_taps"), ("max_rows", "all_taps")])
+def test_separate_nmf_launches_match_oracle_and_fused_path(case, vrule, precision, monkeypatch):
+    """By default a single-workgroup ISS bin forms its own 1/lambda and basis update, and one
+    launch finishes the activation update (its last workgroup per source and frame tile).
+    CTFISS_UNFUSED_NMF keeps lambda, the basis update, the activation partials and the
+    activation update as separate launches: both follow the oracle over four iterations split
+    over two calls, and agree with each other to the same bound."""
+    X, B0, V0, W0, D, taps = make_case(case, seed=44)
+    fused = gpu_run(X, D, taps, B0, V0, W0, 4, precision, vrule=vrule, splits=[3, 1])
+    monkeypatch.setenv("CTFISS_UNFUSED_NMF", "1")
+    plain = gpu_run(X, D, taps, B0, V0, W0, 4, precision, vrule=vrule, splits=[3, 1])
+    assert fused["status"] == 0 and plain["status"] == 0
+    r = oracle_run(X, D, taps, B0, V0, W0, 4, "fp32" if precision == "mixed" else precision, vrule=vrule)
+    tol = "fp64" if precision == "fp64" else "fp32"
+    check_outputs(None, plain, r, 10 * TOL1[tol], 10 * ELEM1[tol])
+    check_outputs(None, fused, r, 10 * TOL1[tol], 10 * ELEM1[tol])
+    check_outputs(None, fused, plain, 10 * TOL1[tol], 10 * ELEM1[tol])
