@@ -21,7 +21,11 @@
  * the ISS sweep updates the rows of W in FP64 registers (each row of W_f gets
  * Mbar rank-one updates per iteration; holding them in FP64 leaves one FP32
  * rounding of W per iteration instead of Mbar).  Same layout and workspace as
- * CTFISS_FP32.
+ * CTFISS_FP32.  CTFISS_MIXED_BF16 (also ISS, single contexts) is CTFISS_MIXED
+ * with the contractions of the source model -- lambda = b v and the sums of the
+ * multiplicative updates of Eqs. (17) and (18) -- on bfloat16 matrix cores
+ * (operands rounded to bfloat16, products accumulated in FP32); the weights,
+ * square roots and everything else stay FP32.
  *
  * Rows of W: r = L_0 + ... + L_{n-1} + l is tap l of source n (source-major,
  * tap-minor, the flattened index of Sec. III-A-1).  The observation may stack
@@ -76,7 +80,7 @@ extern "C" {
 #define CTFISS_MAX_SOURCES 8       /* N                                             */
 #define CTFISS_MAX_BASES 64        /* K                                             */
 
-typedef enum { CTFISS_FP32 = 0, CTFISS_FP64 = 1, CTFISS_MIXED = 2 } ctfiss_precision;
+typedef enum { CTFISS_FP32 = 0, CTFISS_FP64 = 1, CTFISS_MIXED = 2, CTFISS_MIXED_BF16 = 3 } ctfiss_precision;
 
 /* Demixing-matrix update: ISS rank-1 steering, Eqs. (11) and (16), or the
  * iterative-projection baseline, Eqs. (9) and (10). */

@@ -24,7 +24,7 @@ CTFISS_E_HIP = -6
 CTFISS_E_NUMERIC = -7
 CTFISS_E_TOO_LARGE = -8
 
-CTFISS_FP32, CTFISS_FP64, CTFISS_MIXED = 0, 1, 2
+CTFISS_FP32, CTFISS_FP64, CTFISS_MIXED, CTFISS_MIXED_BF16 = 0, 1, 2, 3
 CTFISS_RULE_ISS, CTFISS_RULE_IP = 0, 1
 CTFISS_VRULE_ALL_TAPS, CTFISS_VRULE_PAPER_TAP0 = 0, 1
 

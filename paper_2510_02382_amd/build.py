@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libctfiss.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.hip", "kernels_f32.hip", "kernels_f64.hip", "kernels_mixed.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "kernels_f32.hip", "kernels_f64.hip", "kernels_mixed.hip", "adjoint.hip", "nmf_bf16.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -27,13 +27,15 @@ constexpr GR kIp32[] = {{16, 1}, {32, 1}};
 constexpr GR kIp64[] = {{32, 1}, {64, 1}, {16, 1}};
 
 // Precision codes: CTFISS_FP32 (0), CTFISS_FP64 (1), CTFISS_MIXED (2: FP32 data and
-// kernels, FP64 W rows in the ISS sweep).
+// kernels, FP64 W rows in the ISS sweep), CTFISS_MIXED_BF16 (3: CTFISS_MIXED with the
+// NMF contractions on bfloat16 matrix cores).  wx(): the W update keeps FP64 W rows.
+inline bool wx(int prec) { return prec == CTFISS_MIXED || prec == CTFISS_MIXED_BF16; }
 bool have_w(int prec, int rule, int G, int cpl, int rpl) {
-  if (prec == CTFISS_MIXED) return have_wkernel<float, true>(rule, G, cpl, rpl);
+  if (wx(prec)) return have_wkernel<float, true>(rule, G, cpl, rpl);
   return prec == CTFISS_FP32 ? have_wkernel<float>(rule, G, cpl, rpl) : have_wkernel<double>(rule, G, cpl, rpl);
 }
 bool have_t(int prec, int G, int cpl, int rpl) {
-  if (prec == CTFISS_MIXED) return have_tkernel<float, true>(G, cpl, rpl);
+  if (wx(prec)) return have_tkernel<float, true>(G, cpl, rpl);
   return prec == CTFISS_FP32 ? have_tkernel<float>(G, cpl, rpl) : have_tkernel<double>(G, cpl, rpl);
 }
 
@@ -147,7 +149,7 @@ bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
     list = f32 ? kIss32 : kIss64;
     n = f32 ? (int)(sizeof(kIss32) / sizeof(GR)) : (int)(sizeof(kIss64) / sizeof(GR));
   } else {
-    if (prec == CTFISS_MIXED) return false;  // the mixed path is an ISS path
+    if (wx(prec)) return false;  // the mixed paths are ISS paths
     list = f32 ? kIp32 : kIp64;
     n = f32 ? (int)(sizeof(kIp32) / sizeof(GR)) : (int)(sizeof(kIp64) / sizeof(GR));
   }
@@ -209,8 +211,9 @@ int plan_string_team(const char* spec) {
 
 // Split of the bins for the activation partial sums: chunks of 64 bins (four
 // 16-bin MFMA sub-tiles per wave).
-VSplit choose_vsplit(const Dims& d) {
-  const int fchunk = 64;
+VSplit choose_vsplit(const Dims& d, int prec) {
+  // bfloat16 activation partials take 32 bins per wave (the instruction sums 32 values)
+  const int fchunk = prec == CTFISS_MIXED_BF16 ? 128 : 64;
   return VSplit{(d.F + fchunk - 1) / fchunk, fchunk};
 }
 
@@ -279,7 +282,9 @@ struct TimedLaunch {
 
 int validate_shape(const ctfiss_shape* sh, int precision, Dims* d) {
   if (!sh || !d) return CTFISS_E_ARG;
-  if (precision != CTFISS_FP32 && precision != CTFISS_FP64 && precision != CTFISS_MIXED) return CTFISS_E_ARG;
+  if (precision != CTFISS_FP32 && precision != CTFISS_FP64 && precision != CTFISS_MIXED &&
+      precision != CTFISS_MIXED_BF16)
+    return CTFISS_E_ARG;
   if (sh->F < 1 || sh->T < 1 || sh->M < 1 || sh->D < 1 || sh->N < 1 || sh->K < 1) return CTFISS_E_SHAPE;
   if (!sh->taps) return CTFISS_E_ARG;
   if (sh->N > CTFISS_MAX_SOURCES || sh->K > CTFISS_MAX_BASES) return CTFISS_E_UNSUPPORTED;
@@ -318,7 +323,7 @@ int validate_shape(const ctfiss_shape* sh, int precision, Dims* d) {
 
 Layout make_layout(const Dims& d, int precision) {
   const size_t rs = precision != CTFISS_FP64 ? 4 : 8, cs = 2 * rs;
-  const VSplit vs = choose_vsplit(d);
+  const VSplit vs = choose_vsplit(d, precision);
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -466,7 +471,7 @@ int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int
   // (CTFISS_WBLOCKS in the environment overrides it, for tuning); any count
   // >= 1 gives the same result, since the workgroups share out the bins.
   auto resident = [&](const Plan& p) {
-    return precision == CTFISS_MIXED ? resident_wblocks<float, true>(rule, p, d)
+    return wx(precision) ? resident_wblocks<float, true>(rule, p, d)
            : precision == CTFISS_FP32 ? resident_wblocks<float>(rule, p, d)
                                       : resident_wblocks<double>(rule, p, d);
   };
@@ -478,7 +483,7 @@ int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int
   // activations' 50 KB would halve the workgroups per CU).  CTFISS_UNFUSED_NMF in
   // the environment keeps the separate launches.
   const bool unfused = std::getenv("CTFISS_UNFUSED_NMF") != nullptr;
-  if (rule == CTFISS_RULE_ISS && plan.team <= 1 && !unfused) {
+  if (rule == CTFISS_RULE_ISS && plan.team <= 1 && !unfused && precision != CTFISS_MIXED_BF16) {
     Plan q = plan;
     q.nmf = 1;
     q.lds = wupdate_lds(rule, q, d, precision != CTFISS_FP64 ? 4 : 8);
@@ -508,7 +513,7 @@ int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int
   c->ws = static_cast<char*>(workspace);
   c->lay = lay;
   c->plan = plan;
-  c->vs = choose_vsplit(d);
+  c->vs = choose_vsplit(d, precision);
   c->ptr.X = nullptr;
   c->ptr.W = c->ws + lay.W;
   c->ptr.B = c->ws + lay.B;
@@ -625,11 +630,15 @@ int enqueue_iterations(ctfiss_ctx* c, int32_t n_iter) {
     // 1/lambda: formed per bin by the W update itself (plan.nmf), else by its own launch
     const bool nmf = c->plan.nmf != 0;
     hipError_t e = hipSuccess;
-    if (!nmf) e = timed(c, 5, [&] { return f32 ? lambda_t<float>(d, p, mu, s) : lambda_t<double>(d, p, mu, s); });
+    const bool bf = c->prec == CTFISS_MIXED_BF16;
+    if (!nmf)
+      e = timed(c, 5, [&] {
+        return bf ? lambda_bf16_t(d, p, mu, s) : f32 ? lambda_t<float>(d, p, mu, s) : lambda_t<double>(d, p, mu, s);
+      });
     c->epoch = c->epoch % 0x1FFFFFFu + 1u;  // tags epoch * 128 + step stay within 32 bits
     if (e == hipSuccess)
       e = timed(c, 0, [&] {
-        if (c->prec == CTFISS_MIXED)
+        if (wx(c->prec))
           return wupdate_t<float, true>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, c->floor, s);
         return f32 ? wupdate_t<float>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, c->floor, s)
                    : wupdate_t<double>(c->rule, c->plan, d, p, mu, c->y_valid, c->epoch, c->floor, s);
@@ -637,10 +646,14 @@ int enqueue_iterations(ctfiss_ctx* c, int32_t n_iter) {
     if (e == hipSuccess && c->rule == CTFISS_RULE_ISS) c->y_valid = true;
     if (e == hipSuccess && !nmf)
       e = timed(c, 6, [&] {
-        return f32 ? nmfb_t<float>(d, p, c->floor, mu, s) : nmfb_t<double>(d, p, c->floor, mu, s);
+        return bf ? nmfb_bf16_t(d, p, c->floor, mu, s)
+               : f32 ? nmfb_t<float>(d, p, c->floor, mu, s) : nmfb_t<double>(d, p, c->floor, mu, s);
       });
     if (e == hipSuccess)
-      e = timed(c, 1, [&] { return f32 ? vpart_t<float>(d, c->vs, p, tap0, s) : vpart_t<double>(d, c->vs, p, tap0, s); });
+      e = timed(c, 1, [&] {
+        return bf ? vpart_bf16_t(d, c->vs, p, tap0, s)
+               : f32 ? vpart_t<float>(d, c->vs, p, tap0, s) : vpart_t<double>(d, c->vs, p, tap0, s);
+      });
     if (e == hipSuccess)
       e = timed(c, 2, [&] {
         return f32 ? vfinal_t<float>(d, c->vs, p, c->floor, tap0, s) : vfinal_t<double>(d, c->vs, p, c->floor, tap0, s);
@@ -953,7 +966,7 @@ int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int precision, int3
 int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V0, const void* gC, void* gX,
                     void* gB0, void* gV0, void* aws, size_t aws_bytes) {
   if (!c || !B0 || !V0 || !gC || !gX || !aws || n_iter < 1) return CTFISS_E_ARG;
-  if (c->prec == CTFISS_MIXED || c->rule != CTFISS_RULE_ISS || c->vrule != CTFISS_VRULE_ALL_TAPS)
+  if (wx(c->prec) || c->rule != CTFISS_RULE_ISS || c->vrule != CTFISS_VRULE_ALL_TAPS)
     return CTFISS_E_UNSUPPORTED;
   const Dims& d = c->d;
   const bool f32 = c->prec == CTFISS_FP32;
@@ -1158,7 +1171,7 @@ int ctfiss_autotune(ctfiss_ctx* c, int32_t trials, void* scratch, size_t scratch
       p.lds = wupdate_lds(c->rule, p, d, (int)rs);
       if (p.lds > (size_t)max_lds) continue;
     }
-    p.blocks = c->prec == CTFISS_MIXED ? resident_wblocks<float, true>(c->rule, p, d)
+    p.blocks = wx(c->prec) ? resident_wblocks<float, true>(c->rule, p, d)
                : f32                   ? resident_wblocks<float>(c->rule, p, d)
                                        : resident_wblocks<double>(c->rule, p, d);
     if (p.blocks < 1 || (p.team > 1 && p.blocks < p.team)) continue;
@@ -1168,7 +1181,7 @@ int ctfiss_autotune(ctfiss_ctx* c, int32_t trials, void* scratch, size_t scratch
       c->epoch = c->epoch % 0x1FFFFFFu + 1u;
       if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
       if (e == hipSuccess) {
-        if (c->prec == CTFISS_MIXED)
+        if (wx(c->prec))
           e = wupdate_t<float, true>(c->rule, p, d, c->ptr, false, false, c->epoch, c->floor, c->stream);
         else if (f32)
           e = wupdate_t<float>(c->rule, p, d, c->ptr, false, false, c->epoch, c->floor, c->stream);
@@ -1316,7 +1329,7 @@ int ctfiss_batch_create(const ctfiss_shape* shapes, int32_t n, int precision, in
   int st = ctfiss_batch_workspace_size(shapes, n, precision, &need);
   if (st != CTFISS_OK) return st;
   if (workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return CTFISS_E_WORKSPACE;
-  if (precision == CTFISS_MIXED) return CTFISS_E_UNSUPPORTED;  // batched W updates run FP32 or FP64 rows
+  if (wx(precision)) return CTFISS_E_UNSUPPORTED;  // batched W updates run FP32 or FP64 rows
   ctfiss_batch* b = new (std::nothrow) ctfiss_batch();
   if (!b) return CTFISS_E_ARG;
   b->n = n;

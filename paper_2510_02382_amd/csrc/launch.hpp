@@ -55,7 +55,7 @@ constexpr int kCpl64[] = {4, 6, 8, 10, 12, 16};
 bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out);
 int plan_string_team(const char* spec);
 bool plan_from_string(const char* spec, int prec, int rule, const Dims& d, size_t max_lds, Plan* out);
-VSplit choose_vsplit(const Dims& d);
+VSplit choose_vsplit(const Dims& d, int prec);
 
 // Typed launchers, defined once per precision.  WX (R = float only): the
 // ISS sweep updates the rows of W in FP64 registers (mixed precision).
@@ -74,6 +74,10 @@ template <typename R>
 hipError_t vfinal_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0, hipStream_t s);
 template <typename R>
 hipError_t apply_mu_t(const Dims& d, const Ptrs& ptr, bool scale_y, hipStream_t s);
+// bfloat16 matrix-core variants of the NMF contractions (FP32 data; nmf_bf16.hip).
+hipError_t lambda_bf16_t(const Dims& d, const Ptrs& ptr, bool apply_mu, hipStream_t s);
+hipError_t nmfb_bf16_t(const Dims& d, const Ptrs& ptr, double floor, bool apply_mu, hipStream_t s);
+hipError_t vpart_bf16_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, bool tap0, hipStream_t s);
 template <typename R>
 hipError_t images_t(const Dims& d, const Ptrs& ptr, void* C, hipStream_t s);
 template <typename R>

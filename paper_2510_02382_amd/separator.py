@@ -6,7 +6,7 @@ import torch
 
 from . import binding as b
 
-_PREC = {"fp32": b.CTFISS_FP32, "fp64": b.CTFISS_FP64, "mixed": b.CTFISS_MIXED}
+_PREC = {"fp32": b.CTFISS_FP32, "fp64": b.CTFISS_FP64, "mixed": b.CTFISS_MIXED, "mixed_bf16": b.CTFISS_MIXED_BF16}
 _RULE = {"iss": b.CTFISS_RULE_ISS, "ip": b.CTFISS_RULE_IP}
 _VRULE = {"all_taps": b.CTFISS_VRULE_ALL_TAPS, "paper_tap0": b.CTFISS_VRULE_PAPER_TAP0}
 

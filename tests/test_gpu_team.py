@@ -127,17 +127,18 @@ def c3_slice():
     return X, B0, V0, wl, dict(W=W, B=B, V=V, C=o.source_images(W, X, wl.D, wl.row_taps))
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["mixed", "fp32", "fp64", "mixed_bf16"])
 def test_mbar64_slice_100_iterations_against_oracle(c3_slice, precision, monkeypatch):
     """The team launch over a whole run of the precision workload's shape (four bins): every
     source image against the FP64 oracle on the original data.  Mixed precision meets the 1e-4
-    target; plain FP32 is held to what it measures (its W takes 64 FP32-rounded rank-one
-    updates per iteration); FP64 to 1e-9."""
+    target, mixed precision with bfloat16 NMF contractions the 1e-2 target; plain FP32 is held
+    to what it measures (1.8e-4: its W takes 64 FP32-rounded rank-one updates per iteration);
+    FP64 to 1e-9."""
     monkeypatch.delenv("CTFISS_PLAN", raising=False)
     X, B0, V0, wl, r = c3_slice
     g = gpu_run(X, wl.D, wl.row_taps, B0, V0, None, wl.n_iter, precision)
     assert g["status"] == 0
-    tol = {"mixed": 1e-4, "fp32": 1e-3, "fp64": 1e-9}[precision]
+    tol = {"mixed": 1e-4, "fp32": 1e-3, "fp64": 1e-9, "mixed_bf16": 1e-2}[precision]
     for n in range(wl.N):
         e = rel(g["C"][n], r["C"][n])
         record(source=n, rel=e, elem=elem_err(g["C"][n:n + 1], r["C"][n:n + 1], "C"))
