@@ -160,10 +160,14 @@ def batched_bench(args) -> int:
     n_iter = wls[0].n_iter
     units = sum(w.F * w.T for w in wls) * n_iter
 
-    def run_batch():
-        bs = BatchSeparator(shapes, precision="fp32")
+    stream = torch.cuda.Stream(device=dev)
+
+    def run_batch(graph=False):
+        bs = BatchSeparator(shapes, precision="fp32", stream=stream)
+        if graph:
+            bs.set_graph(True)  # the first iterate() captures, the others replay
         bs.set_input(X32)
-        for _ in range(args.warmup):
+        for _ in range(max(args.warmup, 1 if graph else 0)):
             bs.set_state(B=B32, V=V32)
             bs.iterate(n_iter)
         torch.cuda.synchronize()
@@ -180,9 +184,13 @@ def batched_bench(args) -> int:
 
     from paper_2510_02382_amd import binding as _b
     _b.ctfiss_clear_tuned_plans()
-    dt, C32, st = run_batch()
+    with torch.cuda.stream(stream):
+        dt_eager, C32e, st_e = run_batch(graph=False)
+        dt, C32, st = run_batch(graph=True)
+    graph_equals_eager = all(torch.equal(a, b) for a, b in zip(C32, C32e))
     value = units / dt
-    log(f"batched FP32 ISS: {dt * 1e3:.1f} ms per batch, {value:.4e} F*T*it/s, status {st}")
+    log(f"batched FP32 ISS: eager {dt_eager * 1e3:.1f} ms, graph replay {dt * 1e3:.1f} ms per batch, "
+        f"{value:.4e} F*T*it/s, status {st}, replay == eager: {graph_equals_eager}")
     tuned = None
     if args.autotune:
         # one context per distinct tuning key (Mbar, M, D, N, largest tap count, T rounded up to 32),
@@ -199,7 +207,8 @@ def batched_bench(args) -> int:
             seen[key] = sp.autotune(trials=3)
             sp.close()
         t_tune = time.perf_counter() - t0
-        dtt, _, stt = run_batch()
+        with torch.cuda.stream(stream):
+            dtt, _, stt = run_batch(graph=True)
         tuned = {"ms": dtt * 1e3, "value": units / dtt, "keys_tuned": len(seen), "tuning_seconds": t_tune,
                  "status": list(stt)}
         log(f"autotuned ({len(seen)} shapes in {t_tune:.1f} s): {dtt * 1e3:.1f} ms per batch "
@@ -274,6 +283,7 @@ def batched_bench(args) -> int:
         "config": {"workload": f"{len(wls)} mixtures: 3-12 s, N in {{2,3}}, M = N + 1, D in {{4,8}}, RT60 0.3-1.0 s, "
                                "STFT 1024/256, K = 10, 50 iterations", "mixtures": len(wls),
                    "sum_FT": sum(w.F * w.T for w in wls), "iterations": n_iter},
+        "eager_ms_per_step": dt_eager * 1e3, "graph_equals_eager": graph_equals_eager,
         "side_by_side": {
             "single_fp32_iss": {"value": u32 / dt32, "ms": dt32 * 1e3, "status": st32},
             "single_fp64_iss": {"value": u64 / dt64, "ms": dt64 * 1e3, "mixtures": len(C64), "status": st64},

@@ -302,6 +302,16 @@ int ctfiss_batch_set_state(ctfiss_batch* b, const void* const* W, const void* co
 /* n_iter iterations of every mixture (as ctfiss_iterate). */
 int ctfiss_batch_iterate(ctfiss_batch* b, int32_t n_iter);
 
+/* Graph mode for the batch (enable != 0; ISS rule): ctfiss_batch_iterate
+ * captures the launches of an n_iter-iteration call once into a HIP graph (one
+ * per n_iter and per whether the carried Y is valid at the start, up to 8
+ * kept) and replays it on later calls; a replay is the captured work, with the
+ * same results bit for bit.  The launches read every mixture's buffers through
+ * the batch's device work tables, so graphs stay valid across set_input and
+ * set_state.  Needs a batch created on a non-NULL stream
+ * (CTFISS_E_UNSUPPORTED).  Disabling synchronises the stream and frees them. */
+int ctfiss_batch_set_graph(ctfiss_batch* b, int enable);
+
 /* Source images of every mixture into C[i] (host array of device pointers). */
 int ctfiss_batch_source_images(ctfiss_batch* b, void* const* C);
 

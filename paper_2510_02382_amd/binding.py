@@ -35,7 +35,7 @@ EXPORTS = (
     "ctfiss_batch_workspace_size", "ctfiss_batch_create", "ctfiss_batch_set_input", "ctfiss_batch_set_state",
     "ctfiss_batch_iterate", "ctfiss_batch_source_images", "ctfiss_batch_sync_status", "ctfiss_batch_destroy",
     "ctfiss_adjoint_workspace_size", "ctfiss_backward", "ctfiss_set_graph", "ctfiss_get_plan", "ctfiss_autotune",
-    "ctfiss_autotune_scratch_size", "ctfiss_clear_tuned_plans", "ctfiss_separate_noalloc",
+    "ctfiss_autotune_scratch_size", "ctfiss_clear_tuned_plans", "ctfiss_separate_noalloc", "ctfiss_batch_set_graph",
 )
 
 
@@ -76,6 +76,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "ctfiss_batch_set_input": ([vp, ctypes.POINTER(vp)], i32),
         "ctfiss_batch_set_state": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)], i32),
         "ctfiss_batch_iterate": ([vp, i32], i32),
+        "ctfiss_batch_set_graph": ([vp, i32], i32),
         "ctfiss_batch_source_images": ([vp, ctypes.POINTER(vp)], i32),
         "ctfiss_batch_sync_status": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "ctfiss_batch_destroy": ([vp], i32),
@@ -282,6 +283,10 @@ def ctfiss_batch_set_state(b, W, B, V) -> None:
 
 def ctfiss_batch_iterate(b, n_iter: int) -> None:
     _check(_lib.ctfiss_batch_iterate(b, int(n_iter)), "ctfiss_batch_iterate")
+
+
+def ctfiss_batch_set_graph(b, enable: bool) -> None:
+    _check(_lib.ctfiss_batch_set_graph(b, 1 if enable else 0), "ctfiss_batch_set_graph")
 
 
 def ctfiss_batch_source_images(b, C) -> None:

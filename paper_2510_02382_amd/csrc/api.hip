@@ -1278,6 +1278,13 @@ struct ctfiss_batch {
   int nblocks[4], nmfb_threads;
   std::vector<unsigned char> host;
   bool have_input, have_state, y_valid;
+  bool graph;  // ctfiss_batch_iterate replays captured HIP graphs
+  struct GraphEntry {
+    int n;
+    bool y_valid;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
 };
 
 namespace {
@@ -1316,6 +1323,9 @@ int ctfiss_batch_workspace_size(const ctfiss_shape* shapes, int32_t n, int preci
 
 int ctfiss_batch_destroy(ctfiss_batch* b) {
   if (!b) return CTFISS_E_ARG;
+  if (!b->graphs.empty()) (void)hipStreamSynchronize(b->stream);
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
   for (ctfiss_ctx* c : b->ctx)
     if (c) ctfiss_destroy(c);
   delete b;
@@ -1338,6 +1348,7 @@ int ctfiss_batch_create(const ctfiss_shape* shapes, int32_t n, int precision, in
   b->stream = static_cast<hipStream_t>(stream);
   b->ws = static_cast<char*>(workspace);
   b->have_input = b->have_state = b->y_valid = false;
+  b->graph = false;
   size_t off = 0;
   for (int i = 0; i < n; ++i) {
     size_t wb = 0;
@@ -1475,16 +1486,12 @@ int ctfiss_batch_set_state(ctfiss_batch* b, const void* const* W, const void* co
   return CTFISS_OK;
 }
 
-int ctfiss_batch_iterate(ctfiss_batch* b, int32_t n_iter) {
-  if (!b || n_iter < 0) return CTFISS_E_ARG;
-  if (!b->have_input || !b->have_state) return CTFISS_E_ORDER;
-  if (b->rule != CTFISS_RULE_ISS) {
-    for (ctfiss_ctx* c : b->ctx) {
-      const int st = ctfiss_iterate(c, n_iter, nullptr);
-      if (st != CTFISS_OK) return st;
-    }
-    return CTFISS_OK;
-  }
+}  // extern "C"
+
+namespace {
+
+// The launches of n_iter batched ISS iterations on the batch's stream.
+int batch_enqueue(ctfiss_batch* b, int32_t n_iter) {
   const bool f32 = b->prec != CTFISS_FP64;
   char* w = b->ws;
   const int* nst = reinterpret_cast<const int*>(w + b->off_ns);
@@ -1520,6 +1527,71 @@ int ctfiss_batch_iterate(ctfiss_batch* b, int32_t n_iter) {
       if (e != hipSuccess) return CTFISS_E_HIP;
     }
   }
+  return CTFISS_OK;
+}
+
+void batch_drop_graphs(ctfiss_batch* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctfiss_batch_iterate(ctfiss_batch* b, int32_t n_iter) {
+  if (!b || n_iter < 0) return CTFISS_E_ARG;
+  if (!b->have_input || !b->have_state) return CTFISS_E_ORDER;
+  if (b->rule != CTFISS_RULE_ISS) {
+    for (ctfiss_ctx* c : b->ctx) {
+      const int st = ctfiss_iterate(c, n_iter, nullptr);
+      if (st != CTFISS_OK) return st;
+    }
+    return CTFISS_OK;
+  }
+  if (!b->graph || n_iter == 0) return batch_enqueue(b, n_iter);
+  // graph mode: one captured graph per (n_iter, carried Y valid at the start).  The
+  // launches read the mixtures' buffers through the device work tables, so a graph
+  // stays valid across set_input and set_state.
+  const bool yv = b->y_valid;
+  for (auto& g : b->graphs) {
+    if (g.n == n_iter && g.y_valid == yv) {
+      if (hipGraphLaunch(g.exec, b->stream) != hipSuccess) return CTFISS_E_HIP;
+      b->y_valid = true;
+      return CTFISS_OK;
+    }
+  }
+  if (b->graphs.size() >= 8) {
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return CTFISS_E_HIP;
+    batch_drop_graphs(b);
+  }
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return CTFISS_E_HIP;
+  const int st = batch_enqueue(b, n_iter);
+  const hipError_t ee = hipStreamEndCapture(b->stream, &graph);
+  if (st != CTFISS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    b->y_valid = yv;
+    return st;
+  }
+  if (ee != hipSuccess || !graph) return CTFISS_E_HIP;
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return CTFISS_E_HIP;
+  b->graphs.push_back({n_iter, yv, exec});
+  return hipGraphLaunch(exec, b->stream) == hipSuccess ? CTFISS_OK : CTFISS_E_HIP;
+}
+
+int ctfiss_batch_set_graph(ctfiss_batch* b, int enable) {
+  if (!b) return CTFISS_E_ARG;
+  if (enable) {
+    if (b->stream == nullptr) return CTFISS_E_UNSUPPORTED;  // capture needs a created stream
+  } else if (!b->graphs.empty()) {
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return CTFISS_E_HIP;
+    batch_drop_graphs(b);
+  }
+  b->graph = enable != 0;
   return CTFISS_OK;
 }
 

@@ -625,14 +625,23 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
   if (!a.yload) demix_lane<R, G, CPL, RPL>(a, s, L, g, q, y, nloc);
 
   Cx<WR> wreg[RPL][WPL];
-  R ph[RPL][CPL];  // weights of the lane's rows and frames, phi[n][t - l]
+  // Weights of the lane's rows and frames, phi[n][t - l]: held in registers, or, for
+  // long rows (>= 24 frames per lane, whose registers the demixed rows need), read
+  // from LDS in every step (rows past Mbar then read row 0's weights: their y stays
+  // zero and nothing of them is stored).
+  constexpr bool kPhiLds = CPL >= 24;
+  R ph[RPL][kPhiLds ? 1 : CPL];
+  const R* phl[RPL];
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int p = g * RPL + i;
     const bool ok = p < Mb;
-    const R* phr = s.phi + (ok ? a.rm.src[p] * LP + Lm1 - a.rm.tap[p] : 0) + q;
+    const R* phr = s.phi + (ok ? a.rm.src[p] * LP + Lm1 - a.rm.tap[p] : Lm1) + q;
+    phl[i] = phr;
+    if constexpr (!kPhiLds) {
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) ph[i][j] = ok ? phr[G * j] : R(0);
+      for (int j = 0; j < CPL; ++j) ph[i][j] = ok ? phr[G * j] : R(0);
+    }
 #pragma unroll
     for (int k = 0; k < WPL; ++k) {
       const int c = q + G * k;
@@ -677,7 +686,8 @@ __device__ void iss_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds&
     for (int j = 0; j < CPL; ++j) {
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        const R tx = ph[i][j] * yr[j].x, ty = ph[i][j] * yr[j].y;
+        const R phv = kPhiLds ? phl[i][G * j] : ph[i][kPhiLds ? 0 : j];
+        const R tx = phv * yr[j].x, ty = phv * yr[j].y;
         ar[i] += y[i][j].x * tx;
         ar[i] += y[i][j].y * ty;
         ai[i] += y[i][j].y * tx;

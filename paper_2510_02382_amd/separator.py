@@ -203,6 +203,10 @@ class BatchSeparator:
     def iterate(self, n_iter: int) -> None:
         b.ctfiss_batch_iterate(self.batch, n_iter)
 
+    def set_graph(self, enable: bool = True) -> None:
+        """Replay captured HIP graphs for iterate() (ctfiss_batch_set_graph); needs a non-NULL stream."""
+        b.ctfiss_batch_set_graph(self.batch, enable)
+
     def source_images(self):
         C = [torch.empty((N, M, F, T), dtype=self.cdtype, device=self.device)
              for (F, T, M, D, N, K, taps) in self.shapes]
