@@ -17,7 +17,14 @@ For each (M, RT60, seed) it separates the same mixture with the ISS rule
     maximises the mean, and the same figure for the unprocessed mixture;
   * the GPU wall time of the 100 iterations (after one warm-up iteration).
 
-Usage: python -m paper_2510_02382_amd.study [--seeds 3] [--out FILE]
+Control: the same runs on mixtures drawn directly from the paper's own
+convolutive model, Eq. (2) (datagen.ctf_mixture: complex Gaussian NMF sources,
+random band-wise filters h_{m,n,f,l} with L_n = M / 2 taps per source, square
+extended mixing, no noise), whose source images are known exactly and which
+the demixing model can separate: there ISS and IP are compared where
+separation succeeds, as the paper's Fig. 2 does on speech.
+
+Usage: python -m paper_2510_02382_amd.study [--seeds 3] [--out FILE] [--no-control]
 """
 from __future__ import annotations
 
@@ -50,6 +57,28 @@ def best_permutation_sdr(images: np.ndarray, est: np.ndarray) -> tuple[float, li
     return float(np.mean(best[1])), best[1]
 
 
+def ctf_images(Ht: np.ndarray, S: np.ndarray, taps) -> np.ndarray:
+    """Source images of a mixture drawn from Eq. (2): c_{n,m,f,t} = sum_l h_{m,(n,l),f} s_{n,f,t-l}
+    (zero before the first frame).  Ht [F, M, Mbar] (column (n, l)), S [N, F, T] -> [N, M, F, T]."""
+    F, M, _ = Ht.shape
+    N, _, T = S.shape
+    out = np.zeros((N, M, F, T), dtype=np.complex128)
+    col = 0
+    for n in range(N):
+        for l in range(taps[n]):
+            delayed = np.zeros((F, T), dtype=np.complex128)
+            delayed[:, l:] = S[n, :, :T - l]
+            out[n] += Ht[:, :, col].T[:, :, None] * delayed[None, :, :]
+            col += 1
+    return out
+
+
+@dataclasses.dataclass
+class _Mix:
+    X: np.ndarray
+    images: np.ndarray
+
+
 def run_one(torch, Separator, wl, mix, B0, V0, precision, rule, vrule):
     dev = torch.device("cuda:0")
     cd = torch.complex64 if precision == "fp32" else torch.complex128
@@ -80,11 +109,12 @@ def main(argv=None) -> int:
     ap.add_argument("--mics", default="4,6,8")
     ap.add_argument("--rt60", default="0.30,0.47,1.30")
     ap.add_argument("--out", default=None, help="write one JSON line per run here")
+    ap.add_argument("--no-control", action="store_true", help="skip the mixtures drawn from Eq. (2)")
     args = ap.parse_args(argv)
 
     import torch
 
-    from datagen import WORKLOADS, init_nmf, make_mixture
+    from datagen import WORKLOADS, ctf_mixture, init_nmf, make_mixture
     from paper_2510_02382_amd import Separator
 
     runs = [("iss_fp32", "fp32", "iss", "all_taps"), ("iss_fp32_tap0", "fp32", "iss", "paper_tap0"),
@@ -110,6 +140,25 @@ def main(argv=None) -> int:
                 print(line, flush=True)
                 if out:
                     out.write(line + "\n")
+    controls = []
+    if not args.no_control:
+        for M in [int(m) for m in args.mics.split(",")]:
+            wl = dataclasses.replace(WORKLOADS[f"P{M}"], name=f"P{M}_ctf")
+            for seed in range(args.seeds):
+                X, Ht, S = ctf_mixture(wl.F, wl.T, wl.N, wl.row_taps, wl.K, 7000 + 100 * M + seed)
+                mix = _Mix(X=X, images=ctf_images(Ht, S, wl.row_taps))
+                B0, V0 = init_nmf(wl.N, wl.F, wl.K, wl.T, 7000 + 100 * M + seed)
+                sdr_in, _ = best_permutation_sdr(mix.images, np.broadcast_to(mix.X, mix.images.shape))
+                rec = {"control": "eq2", "M": M, "seed": seed, "F": wl.F, "T": wl.T, "sdr_mixture": sdr_in}
+                for name, prec, rule, vrule in runs:
+                    C, dt, status = run_one(torch, Separator, wl, mix, B0, V0, prec, rule, vrule)
+                    sv, _ = best_permutation_sdr(mix.images, C) if status == 0 else (float("nan"), None)
+                    rec[name] = {"sdr": sv, "seconds": dt, "status": status}
+                controls.append(rec)
+                line = json.dumps(rec)
+                print(line, flush=True)
+                if out:
+                    out.write(line + "\n")
     if out:
         out.close()
     # summary per (M, RT60): mean over seeds
@@ -126,6 +175,18 @@ def main(argv=None) -> int:
         print(f"| {M} | {rt:.2f} | {sm:.2f} | {mean('iss_fp32'):.2f} | {mean('iss_fp32_tap0'):.2f} | "
               f"{mean('ip_fp64'):.2f} | {mean('ip_fp32'):.2f} | {t_iss * 1e3:.1f} | {t_iss64 * 1e3:.1f} | "
               f"{t_ip * 1e3:.1f} | {t_ip / t_iss64:.2f} |")
+    if controls:
+        print("\nControl, mixtures drawn from Eq. (2) (no noise, square extended mixing):")
+        print("\n| M | SDR mixture | ISS | ISS tap-0 | ISS FP64 | IP FP64 | IP FP32 |")
+        print("|---|---|---|---|---|---|---|")
+        for M, grp in itertools.groupby(controls, key=lambda r: r["M"]):
+            grp = list(grp)
+            def cmean(key):
+                v = [g[key]["sdr"] for g in grp if g[key]["status"] == 0]
+                return float(np.mean(v)) if v else float("nan")
+            print(f"| {M} | {float(np.mean([g['sdr_mixture'] for g in grp])):.2f} | {cmean('iss_fp32'):.2f} | "
+                  f"{cmean('iss_fp32_tap0'):.2f} | {cmean('iss_fp64'):.2f} | {cmean('ip_fp64'):.2f} | "
+                  f"{cmean('ip_fp32'):.2f} |")
     return 0
 
 

@@ -43,8 +43,10 @@ def main() -> int:
     def progress(it, W, B, V):
         print(f"iteration {it + 1}/{wl.n_iter}: {time.time() - t0:.0f} s", flush=True)
 
-    W, _, _ = oth.run(X, wl.D, wl.row_taps, B0, V0, wl.n_iter, workers=args.workers, chunk=args.chunk,
-                      callback=progress)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):  # one BLAS thread per pool worker
+        W, _, _ = oth.run(X, wl.D, wl.row_taps, B0, V0, wl.n_iter, workers=args.workers, chunk=args.chunk,
+                          callback=progress)
     bins = sample_bins(wl.F)
     C = o.source_images(W[bins], X[:, bins, :], wl.D, wl.row_taps)  # [N, M, bins, T]
     np.savez(OUT, bins=bins, images=C.astype(np.complex64), n_iter=wl.n_iter, seed=0,
