@@ -332,7 +332,7 @@ def precision_bench(args) -> int:
     flops_launch = wl.F * wl.T * iss_flops_per_unit(wl.mbar)
     achieved = flops_launch / (avg_iss_ms * 1e-3) / 1e12
     _, _, _, allstats = time_path(torch, Separator, wl, Xc, B0, V0, "mixed", "iss", 1, 0, profile=-1)
-    names = ["w_update_iss", "v_partial", "v_final_mu", "final_rescale", "images", "lambda", "basis_update"]
+    names = ["w_update_iss", "v_partial", "v_update_mu", "final_rescale", "images", "lambda", "basis_update"]
     kernel_ms = {names[i]: allstats[i][1] / max(allstats[i][0], 1) for i in range(7)}
     log(f"mixed ISS: {dt / args.steps * 1e3:.3f} ms/step, {value:.4e} F·T·it/s, W update avg "
         f"{avg_iss_ms * 1e3:.1f} us ({achieved:.1f} TFLOP/s), status {stm}")
@@ -647,7 +647,7 @@ def main() -> int:
     achieved = flops_launch / (avg_iss_ms * 1e-3) / 1e12
     log("per-kernel breakdown (separate profiled steps, every kernel timed)")
     _, _, _, allstats = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", 1, 0, profile=-1)
-    names = ["w_update_iss", "v_partial", "v_final_mu", "final_rescale", "images", "lambda", "basis_update"]
+    names = ["w_update_iss", "v_partial", "v_update_mu", "final_rescale", "images", "lambda", "basis_update"]
     kernel_ms = {names[i]: allstats[i][1] / max(allstats[i][0], 1) for i in range(7)}
     log(f"FP32 ISS: {dt / args.steps * 1e3:.3f} ms/step, {value:.4e} F·T·it/s, k_iss avg {avg_iss_ms * 1e3:.1f} us "
         f"({achieved:.1f} TFLOP/s), status {st32}")

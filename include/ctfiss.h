@@ -159,6 +159,14 @@ int ctfiss_set_graph(ctfiss_ctx* ctx, int enable);
  * lane (cpl), rows per group (rpl) and workgroups per bin (team, 1 = one). */
 int ctfiss_get_plan(ctfiss_ctx* ctx, int32_t* G, int32_t* cpl, int32_t* rpl, int32_t* team);
 
+/* How the context runs the source-model steps (Eqs. (17)-(19)) of an iteration.
+ * fused: 0 = 1/lambda and the basis update are launches of their own; 1 = each
+ * bin of the W update forms them, the activations held in LDS; 2 = likewise,
+ * the activations read from device memory.  v_one_launch: 1 = the activation
+ * update and the row scales are one launch, 0 = partial sums over bin chunks
+ * and a final launch.  Either pointer may be null. */
+int ctfiss_get_nmf_path(ctfiss_ctx* ctx, int32_t* fused, int32_t* v_one_launch);
+
 /* Measured choice of the W update's launch shape: every instantiated shape that
  * fits the context's shape (team shapes where the default plan is a team plan)
  * runs the W update `trials` times on the context's input and state (after
@@ -259,7 +267,8 @@ const char* ctfiss_status_string(int status);
  * every launch of each kernel class whose bit is set in mask (0 disables,
  * -1 times every class) on the context's stream, in ctfiss_iterate and
  * ctfiss_source_images.  Kernel classes: 0 = W update [ISS or IP sweep],
- * 1 = activation partial sums, 2 = activation update and scale, 3 = final
+ * 1 = activation partial sums (bfloat16 contexts and CTFISS_UNFUSED_NMF only;
+ * elsewhere class 2 is one launch), 2 = activation update and scale, 3 = final
  * rescale, 4 = source images, 5 = source-variance product lambda = b v,
  * 6 = basis update.  ctfiss_kernel_stats synchronises and returns, for class
  * `which`, the launches and summed milliseconds since the last

@@ -34,7 +34,7 @@ EXPORTS = (
     "ctfiss_status_string", "ctfiss_set_profiling", "ctfiss_kernel_stats",
     "ctfiss_batch_workspace_size", "ctfiss_batch_create", "ctfiss_batch_set_input", "ctfiss_batch_set_state",
     "ctfiss_batch_iterate", "ctfiss_batch_source_images", "ctfiss_batch_sync_status", "ctfiss_batch_destroy",
-    "ctfiss_adjoint_workspace_size", "ctfiss_backward", "ctfiss_set_graph", "ctfiss_get_plan", "ctfiss_autotune",
+    "ctfiss_adjoint_workspace_size", "ctfiss_backward", "ctfiss_set_graph", "ctfiss_get_plan", "ctfiss_get_nmf_path", "ctfiss_autotune",
     "ctfiss_autotune_scratch_size", "ctfiss_clear_tuned_plans", "ctfiss_separate_noalloc", "ctfiss_batch_set_graph",
 )
 
@@ -83,6 +83,7 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
         "ctfiss_adjoint_workspace_size": ([ctypes.POINTER(Shape), i32, i32, ctypes.POINTER(sz)], i32),
         "ctfiss_backward": ([vp, i32, vp, vp, vp, vp, vp, vp, vp, sz], i32),
         "ctfiss_set_graph": ([vp, i32], i32),
+        "ctfiss_get_nmf_path": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "ctfiss_get_plan": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)],
                             i32),
         "ctfiss_autotune_scratch_size": ([vp, ctypes.POINTER(sz)], i32),
@@ -202,6 +203,14 @@ def ctfiss_kernel_stats(ctx, which: int) -> tuple[int, float]:
 def ctfiss_get_plan(ctx) -> tuple[int, int, int, int]:
     v = [ctypes.c_int32(0) for _ in range(4)]
     _check(_lib.ctfiss_get_plan(ctx, *[ctypes.byref(x) for x in v]), "ctfiss_get_plan")
+    return tuple(int(x.value) for x in v)
+
+
+def ctfiss_get_nmf_path(ctx) -> tuple[int, int]:
+    """(fused: 0 separate launches, 1 in the W update with activations in LDS, 2 likewise from
+    device memory; 1 if the activation update is one launch)."""
+    v = [ctypes.c_int32(0) for _ in range(2)]
+    _check(_lib.ctfiss_get_nmf_path(ctx, *[ctypes.byref(x) for x in v]), "ctfiss_get_nmf_path")
     return tuple(int(x.value) for x in v)
 
 

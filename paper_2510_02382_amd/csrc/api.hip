@@ -255,7 +255,7 @@ size_t images_lds(const Dims& d) { return out_lds_bytes(d.Mb, d.M, d.N); }
 size_t wupdate_lds(int rule, const Plan& p, const Dims& d, int rsize) {
   const bool nmf = p.nmf && rule == 0 && p.team <= 1;
   return iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, rsize, rule != 0, p.team, p.slice,
-                         nmf ? d.K : 0)
+                         nmf ? d.K : 0, nmf && p.nmf == 2)
       .total;
 }
 size_t nll_lds(const Dims& d) { return nll_lds_bytes(d.Mb); }
@@ -371,6 +371,7 @@ struct ctfiss_ctx {
   double* trace;  // [kTraceCap] NLL after each iteration of a traced call
   Plan plan;
   VSplit vs;
+  bool vone;  // activation update and row scales in one launch (else partials + final sum)
   bool have_input, have_state;
   bool y_valid;    // the carried Y holds W xbar of the current W (ISS)
   unsigned epoch;  // tag base of the last team launch's exchange words
@@ -450,6 +451,19 @@ int check_create_args(const ctfiss_shape* shape, int precision, int rule, int vr
   return CTFISS_OK;
 }
 
+// The single-launch activation update keeps each (source, 16 frames) in one workgroup,
+// so the matrix-core work of each of its SIMDs grows with the band and with K: it
+// beats the partial sums over bin chunks plus their final sum where a wave takes few
+// 16-bin subtiles (measured on MI355X: F = 513, K = 3, one launch 7.7 us against
+// 5.2 + 4.4 us; F = 1025, K = 20, 19.6 us against 6.9 + 4.9 us).  Cost: subtiles per
+// wave times MFMA steps per subtile (K/4 for lambda, 8 per 16-wide K tile).
+bool vupdate_pays(const Dims& d, int precision) {
+  const int nkt = (d.K + 15) / 16, nks = (d.K + 3) / 4;
+  const int waves = precision != CTFISS_FP64 ? (nkt <= 2 ? 16 : 8) : (nkt <= 1 ? 16 : nkt == 2 ? 8 : 4);
+  const int sub = ((d.F + 15) / 16 + waves - 1) / waves;
+  return sub * (nks + 8 * nkt) <= 48;
+}
+
 // Fills a context over `workspace` (checked by the caller): launch plan, pointers into the
 // workspace, cleared status word and exchange words.
 int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int rule, int vrule, double floor,
@@ -477,20 +491,30 @@ int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int
   };
   plan.blocks = resident(plan);
   // Single-workgroup ISS bins form 1/lambda and update b themselves (no separate
-  // lambda and basis-update launches), with the activations in LDS, where that
-  // layout fits without fewer workgroups in flight (e.g. Mbar <= 8, K = 3, where
-  // an iteration is bound by launch latency; not Mbar = 24, K = 20, where the
-  // activations' 50 KB would halve the workgroups per CU).  CTFISS_UNFUSED_NMF in
-  // the environment keeps the separate launches.
+  // lambda and basis-update launches) where the layout fits without fewer
+  // workgroups in flight: with the activations in LDS (e.g. Mbar <= 8, K = 3, where
+  // an iteration is bound by launch latency), else, in FP32 and mixed precision,
+  // reading them from device memory (e.g. Mbar = 24, K = 20, where their 50 KB in LDS
+  // would halve the workgroups per CU; measured on MI355X, 13.3 against 13.6 ms per
+  // 100 FP32 iterations, while FP64, whose sweep is slower per bin, lost 31 against
+  // 27 ms).  CTFISS_UNFUSED_NMF in the environment keeps the separate launches;
+  // CTFISS_NMF_FROM_DEVICE reads the activations from device memory wherever the bins
+  // fuse (the same arithmetic in the same order as from LDS).
   const bool unfused = std::getenv("CTFISS_UNFUSED_NMF") != nullptr;
   if (rule == CTFISS_RULE_ISS && plan.team <= 1 && !unfused && precision != CTFISS_MIXED_BF16) {
-    Plan q = plan;
-    q.nmf = 1;
-    q.lds = wupdate_lds(rule, q, d, precision != CTFISS_FP64 ? 4 : 8);
-    if (q.lds <= (size_t)max_lds) {
+    const int need = plan.blocks < d.F ? plan.blocks : d.F;
+    const bool dev_v = std::getenv("CTFISS_NMF_FROM_DEVICE") != nullptr;
+    const int last = (dev_v || precision != CTFISS_FP64) ? 2 : 1;
+    for (int kind = dev_v ? 2 : 1; kind <= last; ++kind) {
+      Plan q = plan;
+      q.nmf = kind;
+      q.lds = wupdate_lds(rule, q, d, precision != CTFISS_FP64 ? 4 : 8);
+      if (q.lds > (size_t)max_lds) continue;
       q.blocks = resident(q);
-      const int need = plan.blocks < d.F ? plan.blocks : d.F;
-      if (q.blocks >= need) plan = q;
+      if (q.blocks >= need) {
+        plan = q;
+        break;
+      }
     }
   }
   // A team's waits end only once all its members run together: a team plan
@@ -514,6 +538,9 @@ int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int
   c->lay = lay;
   c->plan = plan;
   c->vs = choose_vsplit(d, precision);
+  // The bfloat16 activation partials keep their own launch; CTFISS_UNFUSED_NMF keeps the
+  // separate partial-sum and final launches that batches run.
+  c->vone = !unfused && precision != CTFISS_MIXED_BF16 && vupdate_pays(d, precision);
   c->ptr.X = nullptr;
   c->ptr.W = c->ws + lay.W;
   c->ptr.B = c->ws + lay.B;
@@ -649,12 +676,16 @@ int enqueue_iterations(ctfiss_ctx* c, int32_t n_iter) {
         return bf ? nmfb_bf16_t(d, p, c->floor, mu, s)
                : f32 ? nmfb_t<float>(d, p, c->floor, mu, s) : nmfb_t<double>(d, p, c->floor, mu, s);
       });
-    if (e == hipSuccess)
+    if (e == hipSuccess && c->vone)
+      e = timed(c, 2, [&] {
+        return f32 ? vupdate_t<float>(d, p, c->floor, tap0, s) : vupdate_t<double>(d, p, c->floor, tap0, s);
+      });
+    if (e == hipSuccess && !c->vone)
       e = timed(c, 1, [&] {
         return bf ? vpart_bf16_t(d, c->vs, p, tap0, s)
                : f32 ? vpart_t<float>(d, c->vs, p, tap0, s) : vpart_t<double>(d, c->vs, p, tap0, s);
       });
-    if (e == hipSuccess)
+    if (e == hipSuccess && !c->vone)
       e = timed(c, 2, [&] {
         return f32 ? vfinal_t<float>(d, c->vs, p, c->floor, tap0, s) : vfinal_t<double>(d, c->vs, p, c->floor, tap0, s);
       });
@@ -1046,14 +1077,16 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
       if (e == hipSuccess) e = lambda_t<float>(d, c->ptr, false, s);
       if (e == hipSuccess) e = wupdate_t<float>(c->rule, sep, d, c->ptr, false, false, c->epoch, c->floor, s);
       if (e == hipSuccess) e = nmfb_t<float>(d, c->ptr, c->floor, false, s);
-      if (e == hipSuccess) e = vpart_t<float>(d, c->vs, c->ptr, false, s);
-      if (e == hipSuccess) e = vfinal_t<float>(d, c->vs, c->ptr, c->floor, false, s);
+      if (e == hipSuccess && c->vone) e = vupdate_t<float>(d, c->ptr, c->floor, false, s);
+      if (e == hipSuccess && !c->vone) e = vpart_t<float>(d, c->vs, c->ptr, false, s);
+      if (e == hipSuccess && !c->vone) e = vfinal_t<float>(d, c->vs, c->ptr, c->floor, false, s);
     } else {
       if (e == hipSuccess) e = lambda_t<double>(d, c->ptr, false, s);
       if (e == hipSuccess) e = wupdate_t<double>(c->rule, sep, d, c->ptr, false, false, c->epoch, c->floor, s);
       if (e == hipSuccess) e = nmfb_t<double>(d, c->ptr, c->floor, false, s);
-      if (e == hipSuccess) e = vpart_t<double>(d, c->vs, c->ptr, false, s);
-      if (e == hipSuccess) e = vfinal_t<double>(d, c->vs, c->ptr, c->floor, false, s);
+      if (e == hipSuccess && c->vone) e = vupdate_t<double>(d, c->ptr, c->floor, false, s);
+      if (e == hipSuccess && !c->vone) e = vpart_t<double>(d, c->vs, c->ptr, false, s);
+      if (e == hipSuccess && !c->vone) e = vfinal_t<double>(d, c->vs, c->ptr, c->floor, false, s);
     }
     if (e != hipSuccess) break;
     p.Wk = ws + L.ckW + k * wb;
@@ -1083,6 +1116,13 @@ int ctfiss_get_plan(ctfiss_ctx* c, int32_t* G, int32_t* cpl, int32_t* rpl, int32
   if (cpl) *cpl = c->plan.CPL;
   if (rpl) *rpl = c->plan.RPL;
   if (team) *team = c->plan.team;
+  return CTFISS_OK;
+}
+
+int ctfiss_get_nmf_path(ctfiss_ctx* c, int32_t* fused, int32_t* v_one_launch) {
+  if (!c) return CTFISS_E_ARG;
+  if (fused) *fused = c->plan.nmf;
+  if (v_one_launch) *v_one_launch = c->vone ? 1 : 0;
   return CTFISS_OK;
 }
 
@@ -1166,9 +1206,13 @@ int ctfiss_autotune(ctfiss_ctx* c, int32_t trials, void* scratch, size_t scratch
   const bool f32 = c->prec != CTFISS_FP64;
   for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
     Plan p = cand[i];
-    if (c->plan.nmf && p.team <= 1) {
-      p.nmf = 1;
+    if (c->plan.nmf && p.team <= 1) {  // the fused form the context took, activations in LDS if they fit
+      p.nmf = c->plan.nmf;
       p.lds = wupdate_lds(c->rule, p, d, (int)rs);
+      if (p.lds > (size_t)max_lds && p.nmf == 1) {
+        p.nmf = 2;
+        p.lds = wupdate_lds(c->rule, p, d, (int)rs);
+      }
       if (p.lds > (size_t)max_lds) continue;
     }
     p.blocks = wx(c->prec) ? resident_wblocks<float, true>(c->rule, p, d)

@@ -191,6 +191,7 @@ struct IterLds {
   int slice;  // frames per team member (T for a single workgroup)
   int ta;     // row stride of a (TP, plus the Lmax - 1 frames of the next member in a team)
   int kb;     // K when the kernel also forms 1/lambda and updates b per bin (0: it does not)
+  int vg;     // kb > 0: the activations are read from device memory, not staged in vl
 };
 
 // Exchange words of one bin in a team launch (64-bit words, one 32-bit
@@ -218,10 +219,12 @@ __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a -
 // frames each (slice <= G * cpl); the layout is that of one member.
 // kb > 0 (single-workgroup ISS): the kernel also forms 1/lambda from b and v and
 // updates b per bin; then phi, the scaled bases bs [N][kb], the tap-aligned
-// powers pw [N][T] and the activations vl [N][kb][T] (loaded once per launch)
-// outlive the sweep (placed after the shared region).
+// powers pw [N][T] and the activations vl [N][kb][T] (loaded once per launch;
+// not with vg, where the kernel reads them from device memory) outlive the sweep
+// (placed after the shared region).
 __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, int N, int lmax, int G, int cpl,
-                                                   int rsize, bool ip, int team = 1, int slice = 0, int kb = 0) {
+                                                   int rsize, bool ip, int team = 1, int slice = 0, int kb = 0,
+                                                   bool vg = false) {
   IterLds L{};
   const size_t cs = 2 * (size_t)rsize;
   L.tp = G * cpl;
@@ -232,6 +235,7 @@ __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, 
   L.slice = team > 1 ? slice : T;
   L.ta = team > 1 ? L.tp + lmax - 1 : L.tp;
   L.kb = (!ip && L.team == 1) ? kb : 0;
+  L.vg = (L.kb && vg) ? 1 : 0;
   size_t off = 0;
   L.x = off; off += align_up((size_t)M * L.lx * cs, 16);
   L.w = off; off += align_up((size_t)Mb * Mb * cs, 16);
@@ -272,7 +276,10 @@ __host__ __device__ inline IterLds iter_lds_layout(int M, int T, int D, int Mb, 
     L.phi = off; off += align_up((size_t)N * L.lp * rsize, 16);
     L.bs = off; off += align_up((size_t)N * L.kb * rsize, 16);
     L.pw = off; off += align_up((size_t)N * T * rsize, 16);
-    L.vl = off; off += align_up((size_t)N * L.kb * T * rsize, 16);
+    if (!L.vg) {
+      L.vl = off;
+      off += align_up((size_t)N * L.kb * T * rsize, 16);
+    }
   }
   // team: 32-bit payloads of the exchange words a wave gathers (one step's
   // partial sums of every row; also the row powers of the epilogue)

@@ -197,23 +197,36 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
 }
 
 // Fused: phi[n][Lmax-1 + t] = 1 / lambda_{n,f,t}, lambda = sum_k b v (Sec. II), from the
-// staged b and the activations the workgroup holds in LDS (the same for every bin).
-// Ends with a barrier.
-template <typename R>
-__device__ void form_phi(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int tid) {
+// staged b and the activations (the same for every bin): held in LDS, or read from
+// device memory (VG; the launch's L2 keeps them).  Ends with a barrier.
+template <typename R, bool VG>
+__device__ __forceinline__ void form_phi_v(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int tid) {
   const int T = a.T, K = a.K, N = a.rm.N, nthr = blockDim.x, LP = L.lp, Lm1 = L.lmax - 1;
   bool bad = false;
   for (int i = tid; i < N * T; i += nthr) {
     const int n = i / T, t = i - n * T;
     const R* b = s.bs + n * K;
-    const R* v = s.vl + (size_t)n * K * T + t;
     R lam = R(0);
-    for (int k = 0; k < K; ++k) lam += b[k] * v[k * T];
+    if constexpr (VG) {
+      const R* v = a.V + (size_t)n * K * T + t;
+#pragma unroll 8
+      for (int k = 0; k < K; ++k) lam += b[k] * v[(size_t)k * T];
+    } else {
+      const R* v = s.vl + (size_t)n * K * T + t;
+      for (int k = 0; k < K; ++k) lam += b[k] * v[k * T];
+    }
     bad |= !finite_pos(lam);
     s.phi[n * LP + Lm1 + t] = R(1) / lam;
   }
   latch_wave(a.status, bad, kFaultMu);
   __syncthreads();
+}
+template <typename R>
+__device__ void form_phi(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int tid) {
+  if (L.vg)
+    form_phi_v<R, true>(a, s, L, tid);
+  else
+    form_phi_v<R, false>(a, s, L, tid);
 }
 
 // Fused: the basis update of Eq. (17) for bin f with t' = t - l,
@@ -223,7 +236,7 @@ __device__ void form_phi(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
 // or 16 lanes (the largest with every pair in one pass where possible); lane j adds
 // frames j, j + S, ..., and the group's sums are one DPP butterfly.  Starts with a
 // barrier (pw written).
-template <typename R, int S>
+template <typename R, int S, bool VG>
 __device__ __forceinline__ bool b_update_groups(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f,
                                                 int tid) {
   const int T = a.T, K = a.K, N = a.rm.N, F = a.F, nthr = blockDim.x, LP = L.lp, Lm1 = L.lmax - 1;
@@ -235,13 +248,20 @@ __device__ __forceinline__ bool b_update_groups(const IterArgs<R>& a, const BinL
     R num = R(0), den = R(0);
     if (act) {
       const int n = nk / K, Ln = a.rm.L[n];
-      const R* v = s.vl + (size_t)nk * T;
       const R* ph = s.phi + n * LP + Lm1;
       const R* pw = s.pw + n * T;
-      for (int t = j; t < T; t += S) {
-        const R il = ph[t], vv = v[t];
+      auto frame = [&](int t, R vv) {
+        const R il = ph[t];
         num += pw[t] * il * il * vv;
         den += (R)(Ln < T - t ? Ln : T - t) * il * vv;
+      };
+      if constexpr (VG) {  // device-memory loads: several in flight (the sums keep their order)
+        const R* v = a.V + (size_t)nk * T;
+#pragma unroll 8
+        for (int t = j; t < T; t += S) frame(t, v[t]);
+      } else {
+        const R* v = s.vl + (size_t)nk * T;
+        for (int t = j; t < T; t += S) frame(t, v[t]);
       }
     }
     num = group_sum<S>(num);
@@ -256,17 +276,18 @@ __device__ __forceinline__ bool b_update_groups(const IterArgs<R>& a, const BinL
   return bad;
 }
 
+template <typename R, bool VG>
+__device__ __forceinline__ bool b_update_v(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f,
+                                           int tid) {
+  const int NK = a.rm.N * a.K, nthr = blockDim.x;
+  if (NK * 64 <= nthr) return b_update_groups<R, 64, VG>(a, s, L, f, tid);
+  if (NK * 32 <= nthr) return b_update_groups<R, 32, VG>(a, s, L, f, tid);
+  return b_update_groups<R, 16, VG>(a, s, L, f, tid);
+}
 template <typename R>
 __device__ void b_update(const IterArgs<R>& a, const BinLds<R>& s, const IterLds& L, int f, int tid) {
-  const int NK = a.rm.N * a.K, nthr = blockDim.x;
   __syncthreads();
-  bool bad;
-  if (NK * 64 <= nthr)
-    bad = b_update_groups<R, 64>(a, s, L, f, tid);
-  else if (NK * 32 <= nthr)
-    bad = b_update_groups<R, 32>(a, s, L, f, tid);
-  else
-    bad = b_update_groups<R, 16>(a, s, L, f, tid);
+  const bool bad = L.vg ? b_update_v<R, true>(a, s, L, f, tid) : b_update_v<R, false>(a, s, L, f, tid);
   latch_wave(a.status, bad, kFaultMu);
 }
 
@@ -782,10 +803,12 @@ __global__ void __launch_bounds__(iter_max_threads(sizeof(R), CPL, RPL), iter_mi
   extern __shared__ __align__(16) unsigned char smem[];
   const BinLds<R> s = carve<R>(smem, L);
   // fused: the activations, the same for every bin, into LDS once (the first bin's
-  // staging barrier orders these stores before their first use)
+  // staging barrier orders these stores before their first use), unless read from
+  // device memory where they are used (L.vg)
   if constexpr (NMF)
     stage_lds<32 / sizeof(R), R>(
-        a.rm.N * a.K * a.T, threadIdx.x, blockDim.x, [&](int i) { return a.V[i]; }, [&](int i, R v) { s.vl[i] = v; });
+        L.vg ? 0 : a.rm.N * a.K * a.T, threadIdx.x, blockDim.x, [&](int i) { return a.V[i]; },
+        [&](int i, R v) { s.vl[i] = v; });
   // Bins dealt out round-robin over the resident workgroups: every bin costs
   // the same, so this balances as well as a shared counter would, without a
   // device-scope atomic round trip per bin.

@@ -21,7 +21,8 @@ struct Plan {
   int blocks;  // persistent workgroups launched (resident ones; at most F items)
   int team = 1;
   int slice = 0;
-  int nmf = 0;  // single-workgroup ISS: also forms 1/lambda and updates b per bin (lds sized for it)
+  int nmf = 0;  // single-workgroup ISS: also forms 1/lambda and updates b per bin (lds sized for it),
+                // with the activations in LDS (1) or read from device memory (2)
 };
 
 // Type-erased device pointers of one context.
@@ -72,6 +73,9 @@ template <typename R>
 hipError_t vpart_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, bool tap0, hipStream_t s);
 template <typename R>
 hipError_t vfinal_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, double floor, bool tap0, hipStream_t s);
+// Activation update and row scales in one launch (replaces vpart_t + vfinal_t).
+template <typename R>
+hipError_t vupdate_t(const Dims& d, const Ptrs& ptr, double floor, bool tap0, hipStream_t s);
 template <typename R>
 hipError_t apply_mu_t(const Dims& d, const Ptrs& ptr, bool scale_y, hipStream_t s);
 // bfloat16 matrix-core variants of the NMF contractions (FP32 data; nmf_bf16.hip).

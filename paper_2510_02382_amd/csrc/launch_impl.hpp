@@ -158,7 +158,7 @@ IterArgs<R> make_iargs(int rule, const Dims& d, const Ptrs& ptr, bool apply_mu, 
 inline IterLds wlayout(int rule, const Plan& p, const Dims& d, int rsize) {
   const bool nmf = p.nmf && rule == 0 && p.team <= 1;
   return iter_lds_layout(d.M, d.T, d.D, d.Mb, d.N, d.lmax, p.G, p.CPL, rsize, rule != 0, p.team, p.slice,
-                         nmf ? d.K : 0);
+                         nmf ? d.K : 0, nmf && p.nmf == 2);
 }
 
 template <typename R, bool WX>
@@ -238,6 +238,30 @@ hipError_t vfinal_t(const Dims& d, const VSplit& vs, const Ptrs& ptr, double flo
   const int nv = (d.N * d.K * d.T + 255) / 256;
   hipLaunchKernelGGL(k_vfinal<R>, dim3(nv + d.Mb), dim3(256), 0, s, a, nv);
   return hipGetLastError();
+}
+
+// One launch for the activation update and the row scales: (ceil(T/16), N + 1) workgroups,
+// as many waves as there are 16-bin subtiles up to the kernel's bound (at least four: the
+// scale slice reduces over 256 threads).
+template <typename R, int NKT>
+hipError_t vupdate_n(const Dims& d, const Ptrs& ptr, double floor, bool tap0, hipStream_t s) {
+  NmfArgs<R> a = make_nargs<R>(d, VSplit{1, d.F}, ptr, floor, tap0, false);
+  int waves = (d.F + 15) / 16;
+  const int wmax = vupdate_threads<R, NKT>() / 64;
+  waves = waves < 4 ? 4 : waves > wmax ? wmax : waves;
+  dim3 grid((d.T + 15) / 16, d.N + 1);
+  hipLaunchKernelGGL((k_vupdate<R, NKT>), grid, dim3(64 * waves), 0, s, a);
+  return hipGetLastError();
+}
+template <typename R>
+hipError_t vupdate_t(const Dims& d, const Ptrs& ptr, double floor, bool tap0, hipStream_t s) {
+  switch ((d.K + 15) / 16) {
+    case 1: return vupdate_n<R, 1>(d, ptr, floor, tap0, s);
+    case 2: return vupdate_n<R, 2>(d, ptr, floor, tap0, s);
+    case 3: return vupdate_n<R, 3>(d, ptr, floor, tap0, s);
+    case 4: return vupdate_n<R, 4>(d, ptr, floor, tap0, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename R>
@@ -475,6 +499,7 @@ hipError_t identity_t(const Dims& d, void* W, hipStream_t s) {
   template hipError_t nmfb_t<R>(const Dims&, const Ptrs&, double, bool, hipStream_t);                         \
   template hipError_t vpart_t<R>(const Dims&, const VSplit&, const Ptrs&, bool, hipStream_t);                 \
   template hipError_t vfinal_t<R>(const Dims&, const VSplit&, const Ptrs&, double, bool, hipStream_t);        \
+  template hipError_t vupdate_t<R>(const Dims&, const Ptrs&, double, bool, hipStream_t);                     \
   template hipError_t apply_mu_t<R>(const Dims&, const Ptrs&, bool, hipStream_t);                            \
   template hipError_t images_t<R>(const Dims&, const Ptrs&, void*, hipStream_t);                             \
   template hipError_t nll_t<R>(const Dims&, const Ptrs&, hipStream_t);                                       \

@@ -224,15 +224,18 @@ __device__ __forceinline__ void nmfb_block(const NmfArgs<R>& a, const int bx, co
 template <typename R>
 __global__ void __launch_bounds__(1024) k_nmf_b(NmfArgs<R> a) { nmfb_block<R>(a, blockIdx.x, blockIdx.y, blockDim.x >> 6); }
 
-// Scale of row r, Eq. (19): mu_r = sqrt(sum_f musq[r][f] / (F T)).  Thread i adds
-// f = i, i + 256, ...; then a tree over the 256 threads: every caller gets the same
-// value bit for bit.  All 256 threads of the workgroup call it; red: 256 values of LDS.
+// Scale of row r, Eq. (19): mu_r = sqrt(sum_f musq[r][f] / (F T)).  Thread i < 256 adds
+// f = i, i + 256, ...; then a tree over those 256 threads: every caller gets the same
+// value bit for bit.  Every thread of the workgroup (at least 256) calls it; red: 256
+// values of LDS.
 template <typename R>
 __device__ __forceinline__ R row_scale(const NmfArgs<R>& a, int r, R* red) {
   const int tid = threadIdx.x;
-  R acc = 0;
-  for (int f = tid; f < a.F; f += 256) acc += a.musq[(size_t)r * a.F + f];
-  red[tid] = acc;
+  if (tid < 256) {
+    R acc = 0;
+    for (int f = tid; f < a.F; f += 256) acc += a.musq[(size_t)r * a.F + f];
+    red[tid] = acc;
+  }
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (tid < w) red[tid] += red[tid + w];
@@ -362,6 +365,151 @@ __device__ __forceinline__ void vpart_block(const NmfArgs<R>& a, const int bx, c
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_vpart(NmfArgs<R> a) { vpart_block<R>(a, blockIdx.x, blockIdx.y, blockIdx.z); }
+
+// Activation update in one launch: one workgroup per (source n, 16 frames) whose waves
+// take the 16-bin subtiles of the band in turn (subtile s to wave s mod waves), each
+// accumulating
+//   num[k][t] = sum_f b_{f,k} P'_{f,t} / lambda_{f,t}^2,  den[k][t] = sum_f b_{f,k} / lambda_{f,t}
+// over its subtiles in its MFMA accumulators (lambda = b v recomputed on MFMA per subtile,
+// as in k_vpart), the loads of its next subtile in flight while it computes one.  The waves'
+// tiles are then added in wave order and the workgroup updates v at its frames,
+// v <- max(v sqrt(num / (C' den)), floor).  No partial sums leave the workgroup, so no
+// second launch adds them up.  The extra y slice (y = N) computes the row scales mu of
+// Eq. (19).  NKT: 16-wide tiles of the bases (K <= 16 NKT).
+template <typename R, int NKT>
+constexpr int vupdate_threads() {
+  return sizeof(R) == 4 ? (NKT <= 2 ? 1024 : 512) : (NKT <= 1 ? 1024 : NKT == 2 ? 512 : 256);
+}
+template <typename R, int NKT>
+struct VSub {
+  R av[4 * NKT];  // b_{f, 4s + lq} at f = fs + lr (lambda's A operand)
+  R pv[4];        // P'_{f, t} at the accumulator rows f
+  R bt[NKT][4];   // b_{f, 16 kt + lr} at the accumulator rows f
+};
+template <typename R, int NKT>
+__global__ void __launch_bounds__((vupdate_threads<R, NKT>())) k_vupdate(NmfArgs<R> a) {
+  constexpr int KS = 4 * NKT;
+  constexpr int NW = vupdate_threads<R, NKT>() / 64;
+  __shared__ R tiles[NW][2][NKT][4][64];
+  if ((int)blockIdx.y == a.rm.N) {  // the row scales (workgroup-uniform branch)
+    R* rs = &tiles[0][0][0][0][0];
+    for (int r = blockIdx.x; r < a.rm.Mb; r += gridDim.x) {
+      const R m = row_scale(a, r, rs);
+      if (threadIdx.x == 0) {
+        if (!finite_pos(m)) latch(a.status, kFaultScale);
+        a.mu[r] = m;
+      }
+    }
+    return;
+  }
+  const int T = a.T, K = a.K, F = a.F;
+  const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  const int n = blockIdx.y, tb = blockIdx.x * 16 + lr;
+  const int nkt = (K + 15) / 16, nks = (K + 3) / 4;
+  const R* Bn = a.B + (size_t)n * F * K;
+  const R* Vn = a.V + (size_t)n * K * T;
+  const R* Pn = (a.tap0 ? a.P0 : a.P) + (size_t)n * F * T;
+  R vop[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = 4 * s + lq;
+    vop[s] = (s < nks && k < K && tb < T) ? Vn[(size_t)k * T + tb] : R(0);
+  }
+  auto load = [&](int fs, VSub<R, NKT>& u) {
+    const int fa = fs + lr;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = 4 * s + lq;
+      u.av[s] = (s < nks && k < K && fa < F) ? Bn[(size_t)fa * K + k] : R(0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int f = fs + acc_row<R>(lq, v);
+      u.pv[v] = (f < F && tb < T) ? Pn[(size_t)f * T + tb] : R(0);
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt) {
+        const int k = 16 * kt + lr;
+        u.bt[kt][v] = (kt < nkt && f < F && k < K) ? Bn[(size_t)f * K + k] : R(0);
+      }
+    }
+  };
+  typename Acc4<R>::type num[NKT], den[NKT];
+#pragma unroll
+  for (int kt = 0; kt < NKT; ++kt) num[kt] = den[kt] = acc_zero<R>();
+  const int step = 16 * nwave;
+  VSub<R, NKT> cur;
+  load(16 * wave, cur);
+  for (int fs = 16 * wave; fs < F; fs += step) {
+    VSub<R, NKT> nxt;
+    load(fs + step, nxt);  // lanes past the band load nothing
+    typename Acc4<R>::type lam = acc_zero<R>();
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      if (s < nks) lam = mfma16(cur.av[s], vop[s], lam);
+    R e1[4], e2[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int f = fs + acc_row<R>(lq, v);
+      e1[v] = e2[v] = R(0);
+      if (f < F && tb < T) {
+        const R il = R(1) / lam[v];
+        e1[v] = cur.pv[v] * il * il;
+        e2[v] = il;
+      }
+    }
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) {
+      if (kt < nkt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          num[kt] = mfma16(cur.bt[kt][v], e1[v], num[kt]);
+          den[kt] = mfma16(cur.bt[kt][v], e2[v], den[kt]);
+        }
+      }
+    }
+    cur = nxt;
+  }
+  // every wave's tiles to LDS at once, then element e of the sums: waves added in order
+#pragma unroll
+  for (int kt = 0; kt < NKT; ++kt) {
+    if (kt < nkt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        tiles[wave][0][kt][v][l] = num[kt][v];
+        tiles[wave][1][kt][v][l] = den[kt][v];
+      }
+    }
+  }
+  __syncthreads();
+  const int nel = 2 * NKT * 256;
+  for (int e = threadIdx.x; e < nel; e += blockDim.x) {
+    R* col = &tiles[0][0][0][0][0] + e;
+    R acc = R(0);
+    for (int w = 0; w < nwave; ++w) acc += col[(size_t)w * nel];
+    col[0] = acc;  // wave 0's slot: read by this thread alone above
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  bool bad = false;
+  if (tb < T) {
+    const R c = a.tap0 ? R(1) : (R)min(a.rm.L[n], T - tb);
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) {
+      if (kt >= nkt) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = 16 * kt + acc_row<R>(lq, v);
+        if (k < K) {
+          const size_t o = ((size_t)n * K + k) * T + tb;
+          const R vv = a.V[o] * sqrt(tiles[0][0][kt][v][l] / (c * tiles[0][1][kt][v][l]));
+          bad |= !isfinite(vv);
+          a.V[o] = vv > a.floor ? vv : a.floor;
+        }
+      }
+    }
+  }
+  latch_wave(a.status, bad, kFaultMu);
+}
 
 // v <- max(v sqrt(num / (C' den)), floor) with the chunk partials summed in
 // chunk order; C' = #{l < L_n : t + l < T} (ALL_TAPS) or 1 (PAPER_TAP0).

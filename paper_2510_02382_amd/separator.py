@@ -71,6 +71,12 @@ class Separator:
         """(G, frames per lane, rows per group, workgroups per bin) of the W update."""
         return b.ctfiss_get_plan(self.ctx)
 
+    def nmf_path(self):
+        """(fused, v_one_launch) of ctfiss_get_nmf_path: where 1/lambda and the basis update run
+        (0 own launches, 1 in the W update with the activations in LDS, 2 read from device
+        memory) and whether the activation update is one launch."""
+        return b.ctfiss_get_nmf_path(self.ctx)
+
     def autotune(self, trials: int = 3):
         """Time every fitting launch shape of the W update on this context's data and keep the
         fastest (ctfiss_autotune; cached for later contexts of the shape).  Returns plan()."""

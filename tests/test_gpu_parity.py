@@ -102,7 +102,7 @@ def gpu_run(X, D, taps, B0, V0, W0, n_iter, precision, rule="iss", vrule="all_ta
     C = sep.source_images() if images else None
     status = sep.status()
     torch.cuda.synchronize()
-    out = dict(W=W.cpu().numpy(), B=B.cpu().numpy(), V=V.cpu().numpy(), status=status)
+    out = dict(W=W.cpu().numpy(), B=B.cpu().numpy(), V=V.cpu().numpy(), status=status, nmf_path=sep.nmf_path())
     if images:
         out["C"] = C.cpu().numpy()
     sep.close()
@@ -456,18 +456,29 @@ def test_autotune_keeps_a_fault_latched_before_it():
 @pytest.mark.parametrize("case,vrule", [("c1_like", "all_taps"), ("three_src", "paper_tap0"), ("ragged", "all_taps"),
                                         ("long_frames", "all_taps"), ("short_T", "all_taps"), ("max_rows", "all_taps")])
 def test_separate_nmf_launches_match_oracle_and_fused_path(case, vrule, precision, monkeypatch):
-    """By default a single-workgroup ISS bin forms its own 1/lambda and basis update, and one
-    launch finishes the activation update (its last workgroup per source and frame tile).
+    """By default a single-workgroup ISS bin forms its own 1/lambda and basis update, and at
+    these few bins one launch (a workgroup per source and 16 frames) updates the activations.
     CTFISS_UNFUSED_NMF keeps lambda, the basis update, the activation partials and the
     activation update as separate launches: both follow the oracle over four iterations split
-    over two calls, and agree with each other to the same bound."""
+    over two calls, and agree with each other to the same bound.  With CTFISS_NMF_FROM_DEVICE
+    the fused bins read the activations from device memory instead of LDS: the same sums in
+    the same order, so the same bits where the default fuses with them in LDS (FP64 at
+    Mbar = 24, K = 20 does not fuse by default: there the variant is held to the oracle)."""
     X, B0, V0, W0, D, taps = make_case(case, seed=44)
     fused = gpu_run(X, D, taps, B0, V0, W0, 4, precision, vrule=vrule, splits=[3, 1])
+    monkeypatch.setenv("CTFISS_NMF_FROM_DEVICE", "1")
+    fused_dev = gpu_run(X, D, taps, B0, V0, W0, 4, precision, vrule=vrule, splits=[3, 1])
+    monkeypatch.delenv("CTFISS_NMF_FROM_DEVICE")
     monkeypatch.setenv("CTFISS_UNFUSED_NMF", "1")
     plain = gpu_run(X, D, taps, B0, V0, W0, 4, precision, vrule=vrule, splits=[3, 1])
-    assert fused["status"] == 0 and plain["status"] == 0
+    assert fused["status"] == 0 and plain["status"] == 0 and fused_dev["status"] == 0
+    assert plain["nmf_path"] == (0, 0) and fused_dev["nmf_path"][0] == 2
+    if fused["nmf_path"][0] == 1:
+        for k in ("W", "B", "V", "C"):
+            assert np.array_equal(fused[k], fused_dev[k]), k
     r = oracle_run(X, D, taps, B0, V0, W0, 4, "fp32" if precision == "mixed" else precision, vrule=vrule)
     tol = "fp64" if precision == "fp64" else "fp32"
     check_outputs(None, plain, r, 10 * TOL1[tol], 10 * ELEM1[tol])
     check_outputs(None, fused, r, 10 * TOL1[tol], 10 * ELEM1[tol])
+    check_outputs(None, fused_dev, r, 10 * TOL1[tol], 10 * ELEM1[tol])
     check_outputs(None, fused, plain, 10 * TOL1[tol], 10 * ELEM1[tol])
