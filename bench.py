@@ -649,6 +649,9 @@ def main() -> int:
     _, _, _, allstats = time_path(torch, Separator, wl, Xc, B0, V0, "fp32", "iss", 1, 0, profile=-1)
     names = ["w_update_iss", "v_partial", "v_update_mu", "final_rescale", "images", "lambda", "basis_update"]
     kernel_ms = {names[i]: allstats[i][1] / max(allstats[i][0], 1) for i in range(7)}
+    probe = Separator(wl.F, wl.T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision="fp32", rule="iss")
+    nmf_path = probe.nmf_path()  # (1/lambda + basis update in the W update: 0/1/2, one-launch activation update)
+    probe.close()
     log(f"FP32 ISS: {dt / args.steps * 1e3:.3f} ms/step, {value:.4e} F·T·it/s, k_iss avg {avg_iss_ms * 1e3:.1f} us "
         f"({achieved:.1f} TFLOP/s), status {st32}")
 
@@ -740,7 +743,10 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
                      "kernel": "k_iss (W update: ISS sweep on the carried Y + tap-aligned powers, one launch per "
-                               "iteration)",
+                               "iteration; with nmf_path[0] > 0 each bin also forms its 1/lambda and basis update)",
+                     "nmf_path": list(nmf_path),
+                     "iteration_us": dt / args.steps / wl.n_iter * 1e6,
+                     "frac_iteration": flops_launch / (dt / args.steps / wl.n_iter) / 1e12 / PEAK_FP32_VALU_TFLOPS,
                      "avg_launch_us": avg_iss_ms * 1e3, "flops_per_launch": flops_launch,
                      "flops_per_unit": iss_flops_per_unit(wl.mbar), "units_per_launch": units_launch,
                      "executed_flops_per_launch": exec_flops_launch,

@@ -164,6 +164,32 @@ def test_paper_tap0_rule_matches_oracle(case, precision):
     check_outputs(f"paper_tap0[{case}-{precision}]", g, r, 10 * TOL1[precision], 10 * ELEM1[precision])
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "mixed"])
+@pytest.mark.parametrize("K", [33, 64])
+def test_wide_bases_match_oracle(K, precision):
+    """K > 32: three and four 16-wide basis tiles in the activation update (one launch at these
+    few bins) and in the fused basis update, up to the largest K the library takes; three
+    iterations against the oracle on both activation rules, with and without the NMF steps in
+    the W update."""
+    import os
+    X, B0, V0, W0, D, taps = make_case("three_src", seed=12)
+    B0, V0 = init_nmf(len(taps), X.shape[1], K, X.shape[2], 12)
+    tol = "fp64" if precision == "fp64" else "fp32"
+    for vrule in ("all_taps", "paper_tap0"):
+        r = oracle_run(X, D, taps, B0, V0, W0, 3, tol, vrule=vrule)
+        for unfused in (False, True):
+            if unfused:
+                os.environ["CTFISS_UNFUSED_NMF"] = "1"
+            try:
+                g = gpu_run(X, D, taps, B0, V0, W0, 3, precision, vrule=vrule)
+            finally:
+                os.environ.pop("CTFISS_UNFUSED_NMF", None)
+            assert g["status"] == 0
+            assert g["nmf_path"][1] == (0 if unfused else 1)
+            check_outputs(f"wide_bases[K{K}-{precision}-{vrule}-{'unfused' if unfused else 'default'}]", g, r,
+                          10 * TOL1[tol], 10 * ELEM1[tol])
+
+
 def test_identity_initialisation_and_zero_iterations():
     X, B0, V0, _, D, taps = make_case("c0_like", seed=2)
     g = gpu_run(X, D, taps, B0, V0, None, 0, "fp64")
