@@ -152,10 +152,10 @@ __device__ void load_bin(const IterArgs<R>& a, const BinLds<R>& s, const IterLds
       Mb * Mb, tid, nthr,
       [&](int i) {
         Cx<R> w = Wf[i];
-        if (a.mu) {
-          const R m = a.mu[i / Mb];
-          w.x = w.x / m;
-          w.y = w.y / m;
+        if (a.mu) {  // rows times 1/mu (as k_apply_mu scales them)
+          const R rm = R(1) / a.mu[i / Mb];
+          w.x = w.x * rm;
+          w.y = w.y * rm;
         }
         return w;
       },
@@ -332,8 +332,8 @@ __device__ __forceinline__ void demix_lane(const IterArgs<R>& a, const BinLds<R>
   }
 }
 
-// Stage 2 (carried): the lane's rows and frames of the stored Y, divided by the
-// pending row scale exactly as W is in load_bin; zero for t >= T.
+// Stage 2 (carried): the lane's rows and frames of the stored Y, times the reciprocal
+// of the pending row scale exactly as W is in load_bin; zero for t >= T.
 template <typename R, int G, int CPL, int RPL>
 __device__ __forceinline__ void load_rows(const IterArgs<R>& a, int f, int g, int q, Cx<R> (&y)[RPL][CPL],
                                           int t0, int nloc) {
@@ -342,14 +342,14 @@ __device__ __forceinline__ void load_rows(const IterArgs<R>& a, int f, int g, in
   for (int i = 0; i < RPL; ++i) {
     const int p = g * RPL + i;
     const bool ok = p < Mb;
-    const R m = (ok && a.mu) ? a.mu[p] : R(1);
+    const R rm = (ok && a.mu) ? R(1) / a.mu[p] : R(1);  // one reciprocal per row
     const Cx<R>* yr = a.Y + ((size_t)f * Mb + (ok ? p : 0)) * T + t0 + q;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
       Cx<R> v = (ok && q + G * j < nloc) ? yr[G * j] : Cx<R>{R(0), R(0)};
       if (a.mu) {
-        v.x = v.x / m;
-        v.y = v.y / m;
+        v.x = v.x * rm;
+        v.y = v.y * rm;
       }
       y[i][j] = v;
     }

@@ -597,9 +597,9 @@ __global__ void __launch_bounds__(256) k_apply_mu(Cx<R>* W, R* B, Cx<R>* Y, cons
   const size_t nw = (size_t)F * Mb * Mb, nb = (size_t)N * F * K, ny = Y ? (size_t)F * Mb * T : 0;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nw) {
-    const R m = mu[(i / Mb) % Mb];
+    const R rm = R(1) / mu[(i / Mb) % Mb];  // the rounding of the lazy form in the W update
     Cx<R> w = W[i];
-    W[i] = Cx<R>{w.x / m, w.y / m};
+    W[i] = Cx<R>{w.x * rm, w.y * rm};
   } else if (i < nw + nb) {
     const size_t j = i - nw;
     const int n = (int)(j / ((size_t)F * K));
@@ -607,9 +607,9 @@ __global__ void __launch_bounds__(256) k_apply_mu(Cx<R>* W, R* B, Cx<R>* Y, cons
     B[j] = B[j] * (R(1) / (m * m));  // the same rounding as pending_scale
   } else if (i < nw + nb + ny) {
     const size_t j = i - nw - nb;
-    const R m = mu[(j / T) % Mb];
+    const R rm = R(1) / mu[(j / T) % Mb];
     Cx<R> y = Y[j];
-    Y[j] = Cx<R>{y.x / m, y.y / m};
+    Y[j] = Cx<R>{y.x * rm, y.y * rm};
   }
 }
 
