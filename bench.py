@@ -300,6 +300,70 @@ def batched_bench(args) -> int:
     return 0
 
 
+def exchange_cost(args) -> int:
+    """Price of the team exchange at c3, on correct kernels only.  A team member of the c3 W update
+    (P workgroups per bin, each holding S = ceil(T/P) frames of every row) does what the
+    single-workgroup kernel of the same launch shape does on a bin of S frames, plus the exchange
+    of its partial sums with the other members (one round per ISS step) and the halo and row
+    powers after the sweep.  Timed: (a) the mixed-precision team launch on the c3 mixture, (b) the
+    single-workgroup kernel of the member's shape (CTFISS_PLAN=G,CPL,RPL) on that mixture cut to its
+    first S frames with its bins repeated P times, i.e. as many workgroup items of the same shape
+    as the team launch, none of which exchanges.  (a) - (b) per launch is the exchange."""
+    import numpy as np
+    import torch
+
+    from datagen import WORKLOADS, init_nmf, make_mixture
+    from paper_2510_02382_amd import Separator
+
+    wl = WORKLOADS["c3"]
+    n_iter = 20
+    mix = make_mixture(wl, 0)
+    B0n, V0n = init_nmf(wl.N, wl.F, wl.K, wl.T, 0)
+    dev = torch.device("cuda:0")
+
+    def launch_us(F, T, X, B0, V0, plan=None):
+        if plan:  # the member's shape, with the NMF steps as launches of their own as in a team
+            os.environ["CTFISS_PLAN"] = plan
+            os.environ["CTFISS_UNFUSED_NMF"] = "1"
+        try:
+            sep = Separator(F, T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision="mixed", rule="iss")
+        finally:
+            os.environ.pop("CTFISS_PLAN", None)
+            os.environ.pop("CTFISS_UNFUSED_NMF", None)
+        shape = sep.plan()
+        Xd = torch.from_numpy(X).to(dev, torch.complex64)
+        Bd = torch.from_numpy(B0).to(dev, torch.float32)
+        Vd = torch.from_numpy(V0).to(dev, torch.float32)
+        run_config(sep, Xd, Bd, Vd, 2)  # warm-up
+        torch.cuda.synchronize()
+        sep.set_profiling(1)
+        run_config(sep, Xd, Bd, Vd, n_iter)
+        n, ms = sep.kernel_stats(0)
+        st = sep.status()
+        sep.close()
+        return ms / max(n, 1) * 1e3, shape, st
+
+    log("team launch on the c3 mixture")
+    team_us, (G, cpl, rpl, P), st_team = launch_us(wl.F, wl.T, mix.X, B0n, V0n)
+    if P <= 1:
+        log("the default c3 plan is not a team plan: nothing to price")
+        return 1
+    S = -(-wl.T // P)
+    Xs = np.ascontiguousarray(np.tile(mix.X[:, :, :S], (1, P, 1)))
+    Bs = np.ascontiguousarray(np.tile(B0n, (1, P, 1)))
+    Vs = np.ascontiguousarray(V0n[:, :, :S])
+    log(f"single-workgroup launches of the member shape ({G}, {cpl}, {rpl}) on {P * wl.F} bins of {S} frames")
+    single_us, shape1, st_single = launch_us(P * wl.F, S, Xs, Bs, Vs, plan=f"{G},{cpl},{rpl}")
+    assert shape1[3] == 1 and shape1[:3] == (G, cpl, rpl), shape1
+    out = {"workload": "c3 team exchange", "team_plan": [G, cpl, rpl, P], "member_frames": S,
+           "items_per_launch": P * wl.F, "team_launch_us": team_us, "no_exchange_launch_us": single_us,
+           "exchange_us_per_launch": team_us - single_us,
+           "exchange_share": (team_us - single_us) / team_us,
+           "status": [st_team, st_single], "iterations_timed": n_iter}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def precision_bench(args) -> int:
     """Long-signal workload with Mbar = 64: 60 s at 16 kHz, N=3, M=4, RT60 0.8 s, STFT 4096/1024
     (F=2049, T=938), D=16 stacked frames (taps 22+21+21), K=30, 100 iterations.  A bin's 64 rows x
@@ -590,6 +654,9 @@ def main() -> int:
                     help="c3: the 60 s, Mbar = 64 mixture (team launches) instead of the 10 s, Mbar = 24 one; "
                          "c4: forward and reverse pass of 32 mixtures (gradients); P4/P6/P8: the paper's "
                          "shapes, eager and graph replay")
+    ap.add_argument("--exchange-cost", action="store_true",
+                    help="c3: time the team launch against single-workgroup launches of the member's shape "
+                         "on as many items without exchange")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -604,7 +671,7 @@ def main() -> int:
     if args.batched:
         return batched_bench(args)
     if args.workload == "c3":
-        return precision_bench(args)
+        return exchange_cost(args) if args.exchange_cost else precision_bench(args)
     if args.workload == "c4":
         return adjoint_bench(args)
     if args.workload in ("P4", "P6", "P8"):
