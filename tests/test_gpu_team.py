@@ -68,6 +68,21 @@ def test_forced_team_paper_tap0_rule(precision, monkeypatch):
     check_outputs(None, g, r, 10 * TOL1[precision], 10 * ELEM1[precision], keys=("W", "B", "V"))
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_too_few_workgroups_for_a_team_are_raised_to_its_size(precision, monkeypatch):
+    """CTFISS_WBLOCKS below the team size would leave a bin's members unable to run together;
+    the library raises the count to the team size (here 3 workgroups for 7 bins x 3 members),
+    and any count of at least one team gives the default launch's results bit for bit."""
+    monkeypatch.setenv("CTFISS_PLAN", _plan("ragged", precision))
+    X, B0, V0, W0, D, taps = make_case("ragged", seed=15)
+    ref = gpu_run(X, D, taps, B0, V0, W0, 2, precision)
+    monkeypatch.setenv("CTFISS_WBLOCKS", "1")
+    g = gpu_run(X, D, taps, B0, V0, W0, 2, precision)
+    assert g["status"] == 0 and ref["status"] == 0
+    for k in ("W", "B", "V", "C"):
+        assert np.array_equal(g[k], ref[k]), k
+
+
 def test_team_and_single_workgroup_agree(monkeypatch):
     """The same bins through one workgroup and through a team of four differ
     only in the order of the frame sums."""
