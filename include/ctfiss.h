@@ -285,8 +285,10 @@ int ctfiss_kernel_stats(ctfiss_ctx* ctx, int which, int64_t* launches, double* t
  * those in another order), but
  * an iteration is a handful of launches over all mixtures: the W update is
  * one persistent launch per launch shape over the (mixture, bin) items of
- * every mixture of that shape, and each NMF step is one launch over the
- * workgroups of all mixtures.  The IP rule is accepted and runs mixture by
+ * every mixture of that shape (the shapes' launches overlap on up to three
+ * side streams of the batch, forked from and joined to its stream within the
+ * iteration, also in a captured graph), and each NMF step is one launch over
+ * the workgroups of all mixtures.  The IP rule is accepted and runs mixture by
  * mixture.  Mixture i uses its own device buffers exactly as a context does
  * (X[i] [M_i][F_i][T_i], W[i], B[i], V[i], C[i]: same layouts and types). */
 typedef struct ctfiss_batch ctfiss_batch;

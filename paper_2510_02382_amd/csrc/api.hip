@@ -1,6 +1,7 @@
 // C ABI of the CTF-MNMF-ISS library: validation, workspace layout, launch order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1317,6 +1318,12 @@ struct ctfiss_batch {
     int blocks;
   };
   std::vector<Bucket> buckets;
+  // W updates of different launch shapes overlap: bucket k runs on lane[k] (0: the batch's
+  // stream, j > 0: side[j - 1]), forked from and joined to the batch's stream by events
+  std::vector<hipStream_t> side;
+  std::vector<int> lane;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
   // device tables (offsets into ws) and their host images
   size_t off_w, off_ws, off_cnt, off_n, off_ns, tab_bytes, wsz, nsz;
   int nblocks[4], nmfb_threads;
@@ -1367,9 +1374,15 @@ int ctfiss_batch_workspace_size(const ctfiss_shape* shapes, int32_t n, int preci
 
 int ctfiss_batch_destroy(ctfiss_batch* b) {
   if (!b) return CTFISS_E_ARG;
-  if (!b->graphs.empty()) (void)hipStreamSynchronize(b->stream);
+  if (!b->graphs.empty() || !b->side.empty()) (void)hipStreamSynchronize(b->stream);
   for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
   b->graphs.clear();
+  for (hipStream_t x : b->side) {
+    (void)hipStreamSynchronize(x);
+    (void)hipStreamDestroy(x);
+  }
+  for (hipEvent_t x : b->join) (void)hipEventDestroy(x);
+  if (b->fork) (void)hipEventDestroy(b->fork);
   for (ctfiss_ctx* c : b->ctx)
     if (c) ctfiss_destroy(c);
   delete b;
@@ -1455,6 +1468,46 @@ int ctfiss_batch_create(const ctfiss_shape* shapes, int32_t n, int precision, in
       return CTFISS_E_UNSUPPORTED;
     }
     bk.blocks = res < bins ? res : bins;
+  }
+  // Streams for the W updates of the launch shapes: the buckets, largest first (by
+  // sum of F T Mbar^2, the sweep's work), each to the least loaded of up to four
+  // streams (the batch's and three side streams of default priority; a process has
+  // four hardware queues), so that one launch's last round overlaps the next one's.
+  // The persistent workgroups of concurrent launches take their items from separate
+  // counters; a bin's arithmetic does not depend on which launch shares the device.
+  if (rule == CTFISS_RULE_ISS && b->buckets.size() > 1) {
+    const int nl = b->buckets.size() < 4 ? (int)b->buckets.size() : 4;
+    std::vector<double> work(b->buckets.size(), 0.0), load(nl, 0.0);
+    std::vector<int> order(b->buckets.size());
+    for (size_t k = 0; k < b->buckets.size(); ++k) {
+      order[k] = (int)k;
+      for (int i : b->buckets[k].mix) {
+        const Dims& d = b->ctx[i]->d;
+        work[k] += (double)d.F * d.T * d.Mb * d.Mb;
+      }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    b->lane.assign(b->buckets.size(), 0);
+    for (int k : order) {
+      int best = 0;
+      for (int j = 1; j < nl; ++j)
+        if (load[j] < load[best]) best = j;
+      b->lane[k] = best;
+      load[best] += work[k];
+    }
+    hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int j = 1; j < nl && e == hipSuccess; ++j) {
+      hipStream_t x = nullptr;
+      hipEvent_t ev = nullptr;
+      e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+      if (e == hipSuccess) b->side.push_back(x);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) b->join.push_back(ev);
+    }
+    if (e != hipSuccess) {
+      ctfiss_batch_destroy(b);
+      return CTFISS_E_HIP;
+    }
   }
   b->host.assign(b->tab_bytes, 0);
   *out = b;
@@ -1552,12 +1605,22 @@ int batch_enqueue(ctfiss_batch* b, int32_t n_iter) {
     const bool mu = it > 0;
     hipError_t e = nmf(0, mu ? 1 : 0, 256);  // lambda; also zeroes the bucket counters
     const int v = mu ? 1 : (b->y_valid ? 2 : 0);
+    const int ns = (int)b->side.size();
+    if (e == hipSuccess && ns > 0) {  // fork: the side streams start after lambda
+      e = hipEventRecord(b->fork, s);
+      for (int j = 0; j < ns && e == hipSuccess; ++j) e = hipStreamWaitEvent(b->side[j], b->fork, 0);
+    }
     for (int k = 0; e == hipSuccess && k < nb; ++k) {
       const auto& bk = b->buckets[k];
       const void* desc = w + b->off_w + ((size_t)v * b->n + bk.wbase) * b->wsz;
       const int* start = reinterpret_cast<const int*>(w + b->off_ws) + bk.sbase;
-      e = f32 ? wupdate_batch_t<float>(bk.plan, desc, start, (int)bk.mix.size(), cnt + k, bk.lds, bk.blocks, s)
-              : wupdate_batch_t<double>(bk.plan, desc, start, (int)bk.mix.size(), cnt + k, bk.lds, bk.blocks, s);
+      hipStream_t sk = (ns > 0 && b->lane[k] > 0) ? b->side[b->lane[k] - 1] : s;
+      e = f32 ? wupdate_batch_t<float>(bk.plan, desc, start, (int)bk.mix.size(), cnt + k, bk.lds, bk.blocks, sk)
+              : wupdate_batch_t<double>(bk.plan, desc, start, (int)bk.mix.size(), cnt + k, bk.lds, bk.blocks, sk);
+    }
+    for (int j = 0; e == hipSuccess && j < ns; ++j) {  // join before the basis update
+      e = hipEventRecord(b->join[j], b->side[j]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, b->join[j], 0);
     }
     if (e == hipSuccess) b->y_valid = true;
     if (e == hipSuccess) e = nmf(1, mu ? 3 : 2, b->nmfb_threads);
