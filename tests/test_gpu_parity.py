@@ -478,6 +478,28 @@ def test_autotune_keeps_a_fault_latched_before_it():
 
 
 # ------------------------------------------------------------------ fused and separate NMF launches
+@pytest.mark.parametrize("name,precision,path", [
+    ("c1", "fp32", (2, 0)),        # activations read from device memory (50 KB would halve occupancy)
+    ("c1", "mixed", (2, 0)),
+    ("c1", "fp64", (0, 0)),        # FP64 keeps lambda and the basis update as launches of their own
+    ("c1", "mixed_bf16", (0, 0)),  # the bfloat16 contractions are launches of their own
+    ("P4", "fp32", (1, 1)),        # activations in LDS, one-launch activation update
+    ("c3", "mixed", (0, 0)),       # team launches
+])
+def test_nmf_path_at_the_benchmark_shapes(name, precision, path, monkeypatch):
+    """The form of the NMF steps a context takes at the benchmark shapes (ctfiss_get_nmf_path),
+    and the separate launches everywhere with CTFISS_UNFUSED_NMF."""
+    from paper_2510_02382_amd import Separator
+    wl = WORKLOADS[name]
+    sep = Separator(wl.F, wl.T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision=precision)
+    assert sep.nmf_path() == path
+    sep.close()
+    monkeypatch.setenv("CTFISS_UNFUSED_NMF", "1")
+    sep = Separator(wl.F, wl.T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision=precision)
+    assert sep.nmf_path() == (0, 0)
+    sep.close()
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64", "mixed"])
 @pytest.mark.parametrize("case,vrule", [("c1_like", "all_taps"), ("three_src", "paper_tap0"), ("ragged", "all_taps"),
                                         ("long_frames", "all_taps"), ("short_T", "all_taps"), ("max_rows", "all_taps")])
