@@ -251,12 +251,26 @@ __device__ __forceinline__ R row_scale(const NmfArgs<R>& a, int r, R* red) {
 template <typename R>
 __device__ __forceinline__ R vfinal_value(const NmfArgs<R>& a, int n, int k, int t, bool& bad) {
   const int T = a.T, K = a.K;
+  // up to 24 chunks' partials in flight at once (one round trip for F <= 1536 at 64 bins per
+  // chunk), then added in chunk order
+  constexpr int CB = 24;
+  const size_t step = (size_t)K * T, o0 = ((size_t)n * a.nch * K + k) * T + t;
   R num = 0, den = 0;
-#pragma unroll 8
-  for (int ch = 0; ch < a.nch; ++ch) {
-    const size_t o = (((size_t)n * a.nch + ch) * K + k) * T + t;
-    num += a.vnum[o];
-    den += a.vden[o];
+  for (int c0 = 0; c0 < a.nch; c0 += CB) {
+    R xn[CB], xd[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      const bool ok = c0 + u < a.nch;
+      xn[u] = ok ? a.vnum[o0 + (size_t)(c0 + u) * step] : R(0);
+      xd[u] = ok ? a.vden[o0 + (size_t)(c0 + u) * step] : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      if (c0 + u < a.nch) {
+        num += xn[u];
+        den += xd[u];
+      }
+    }
   }
   const R c = a.tap0 ? R(1) : (R)min(a.rm.L[n], T - t);
   const R v = a.V[((size_t)n * K + k) * T + t] * sqrt(num / (c * den));
