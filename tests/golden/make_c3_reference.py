@@ -6,8 +6,9 @@ mixture and initial factors of datagen (seed 0), as the benchmark's precision le
 
 Only datagen and oracle/ are called.  Run from the repository root:
     python tests/golden/make_c3_reference.py [--workers N]
-(about 20 minutes on 16 host threads; the images are stored in complex64, i.e. to ~6e-8
-relative, well below the errors they are used to measure).
+(hours: ~3.7 h with 7 pool workers on an 8-core host, 80-210 s per iteration, since every
+iteration's activation update needs all 2049 bins; the images are stored in complex64, i.e.
+to ~6e-8 relative, well below the errors they are used to measure).
 """
 import argparse
 import os
