@@ -158,3 +158,35 @@ def test_mbar64_slice_100_iterations_against_oracle(c3_slice, precision, monkeyp
         e = rel(g["C"][n], r["C"][n])
         record(source=n, rel=e, elem=elem_err(g["C"][n:n + 1], r["C"][n:n + 1], "C"))
         assert e < tol, (n, e)
+
+
+# ------------------------------------------------------------------ the whole precision workload
+@pytest.mark.parametrize("precision,tol", [("mixed", 1e-4), ("mixed_bf16", 1e-2)])
+def test_c3_whole_run_matches_oracle_images(precision, tol):
+    """The precision workload at full size, as the benchmark runs it (60 s mixture, F = 2049,
+    T = 938, Mbar = 64 in team launches, K = 30, 100 iterations from W = I): the source images
+    of 16 bins spread over the band against the FP64 oracle's whole run of the same seeded
+    mixture (tests/golden/c3_oracle_images.npz, written by make_c3_reference.py from the
+    oracle only), per source within the targets (mixed 1e-4, bfloat16 NMF contractions 1e-2)."""
+    import os
+    from datagen import WORKLOADS, init_nmf, make_mixture
+    from paper_2510_02382_amd import Separator
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_oracle_images.npz")
+    ref = np.load(path)
+    bins, Cref = ref["bins"], ref["images"].astype(np.complex128)
+    wl = WORKLOADS["c3"]
+    assert int(ref["n_iter"]) == wl.n_iter
+    X = make_mixture(wl, 0).X
+    B0, V0 = init_nmf(wl.N, wl.F, wl.K, wl.T, 0)
+    sep = Separator(wl.F, wl.T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision=precision)
+    assert sep.plan()[3] > 1  # team launches
+    sep.set_input(torch.from_numpy(X).to("cuda", torch.complex64))
+    sep.set_state(B=torch.from_numpy(B0).to("cuda", torch.float32), V=torch.from_numpy(V0).to("cuda", torch.float32))
+    sep.iterate(wl.n_iter)
+    C = sep.source_images()[:, :, torch.as_tensor(bins, device="cuda"), :].cpu().numpy().astype(np.complex128)
+    assert sep.status() == 0
+    sep.close()
+    for n in range(wl.N):
+        e = rel(C[n], Cref[n])
+        record(f"c3_whole_run[{precision}]", source=n, rel=e, elem=elem_err(C[n:n + 1], Cref[n:n + 1], "C"))
+        assert e < tol, (n, e)
