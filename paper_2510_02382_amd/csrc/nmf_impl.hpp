@@ -1,8 +1,9 @@
 // Source-model kernels of one iteration: lambda = b v, basis update (Eq. (17)),
 // activation update (Eq. (18) / ALL_TAPS) and the scale of Eq. (19).
 //
-// The scale of iteration i is applied lazily: b_n /= mu_{(n,0)}^2 where b is
-// next read (k_lambda and k_nmf_b of iteration i+1), W rows /= mu in the next
+// The scale of iteration i is applied lazily: b_n times 1/mu_{(n,0)}^2 where b is
+// next read (k_lambda and k_nmf_b of iteration i+1, or the W update's own staging
+// of b where it forms 1/lambda), W rows and carried Y rows times 1/mu in the next
 // W update, and by k_apply_mu after the last iteration of a call.
 #pragma once
 
@@ -20,7 +21,7 @@ struct NmfArgs {
   R* vnum;           // [N][nch][K][T] partial numerators
   R* vden;           // [N][nch][K][T] partial denominators
   const R* musq;     // [Mb][F] row power sums
-  R* mu;             // [Mb] scale of this iteration (out of k_vfinal)
+  R* mu;             // [Mb] scale of this iteration (out of k_vfinal or k_vupdate)
   const R* mu_prev;  // [Mb] pending scale of the previous iteration, or null
   int* status;
   int* work;         // bin counter of the W-update kernel, zeroed here by k_lambda
