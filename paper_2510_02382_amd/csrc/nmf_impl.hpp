@@ -430,6 +430,11 @@ __global__ void __launch_bounds__((vupdate_threads<R, NKT>())) k_vupdate(NmfArgs
     const int k = 4 * s + lq;
     vop[s] = (s < nks && k < K && tb < T) ? Vn[(size_t)k * T + tb] : R(0);
   }
+  __shared__ R vt[16 * NKT][16];  // v of the workgroup's frames, for the final update
+  if (wave == 0) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) vt[4 * s + lq][lr] = vop[s];
+  }
   auto load = [&](int fs, VSub<R, NKT>& u) {
     const int fa = fs + lr;
 #pragma unroll
@@ -516,7 +521,7 @@ __global__ void __launch_bounds__((vupdate_threads<R, NKT>())) k_vupdate(NmfArgs
         const int k = 16 * kt + acc_row<R>(lq, v);
         if (k < K) {
           const size_t o = ((size_t)n * K + k) * T + tb;
-          const R vv = a.V[o] * sqrt(tiles[0][0][kt][v][l] / (c * tiles[0][1][kt][v][l]));
+          const R vv = vt[k][lr] * sqrt(tiles[0][0][kt][v][l] / (c * tiles[0][1][kt][v][l]));
           bad |= !isfinite(vv);
           a.V[o] = vv > a.floor ? vv : a.floor;
         }
