@@ -106,6 +106,87 @@ __device__ __forceinline__ R wave_sum(R v) {
   return v;
 }
 
+// Wave sums of N values at once, transposed.  Level k pairs lanes that differ in lane
+// bit 5 - k (across halves and rows of 16 with the gfx950 lane swaps, within a row with
+// DPP mirrors and quad permutations, each an involution that flips that bit); the
+// lane whose bit is 0 keeps the lower half of its values plus its partner's lower
+// half, the other the upper halves, so the values per lane halve at every level (an
+// odd count takes a zero into the upper half).  After six levels lane l holds the wave
+// sum of value tsum_index<N>(l) (a padding zero where that index is N or more):
+// ~3 operations per value pair and level instead of a six-level butterfly per value.
+// The lane swaps of a (lower, upper) pair leave, in either half or row, that part's
+// own value in one result and its partner's matching value in the other.
+template <int W>
+__device__ __forceinline__ float pair_swap_sum(float lo, float hi) {
+  const auto r = W == 32 ? __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false)
+                         : __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+template <int W>
+__device__ __forceinline__ double pair_swap_sum(double lo, double hi) {
+  const unsigned l0 = (unsigned)__double2loint(lo), l1 = (unsigned)__double2hiint(lo);
+  const unsigned h0 = (unsigned)__double2loint(hi), h1 = (unsigned)__double2hiint(hi);
+  const auto a = W == 32 ? __builtin_amdgcn_permlane32_swap(l0, h0, false, false)
+                         : __builtin_amdgcn_permlane16_swap(l0, h0, false, false);
+  const auto b = W == 32 ? __builtin_amdgcn_permlane32_swap(l1, h1, false, false)
+                         : __builtin_amdgcn_permlane16_swap(l1, h1, false, false);
+  return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+template <int D>
+constexpr int tsum_dpp() {  // within a row of 16: the involution that flips lane bit log2(D)
+  return D == 8 ? 0x140 : D == 4 ? 0x141 : D == 2 ? 0x4E : 0xB1;  // row_mirror, row_half_mirror, xor 2, xor 1
+}
+template <typename R, int N, int LEVEL>
+struct TSum {
+  static __device__ __forceinline__ R run(const R (&v)[N], int lane) {
+    constexpr int D = 32 >> LEVEL, H = (N + 1) / 2;
+    const bool up = (lane & D) != 0;
+    R w[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const R lo = v[i], hi = H + i < N ? v[H + i] : R(0);
+      if constexpr (D >= 16) {
+        w[i] = pair_swap_sum<D == 32 ? 32 : 16>(lo, hi);
+      } else {
+        const R send = up ? lo : hi, keep = up ? hi : lo;
+        w[i] = keep + dpp<tsum_dpp<D>()>(send);
+      }
+    }
+    return TSum<R, H, LEVEL + 1>::run(w, lane);
+  }
+};
+template <typename R, int N>
+struct TSum<R, N, 6> {
+  static __device__ __forceinline__ R run(const R (&v)[N], int) { return v[0]; }
+};
+// The value index lane `lane` ends with, or N where it holds only padding: the lane's
+// window of real values shrinks to its lower or upper half at every level.
+template <int N>
+__device__ __forceinline__ int tsum_index(int lane) {
+  int j = 0, n = N, real = N;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int h = (n + 1) / 2;
+    if (lane & (32 >> k)) {
+      j += h;
+      real = real > h ? real - h : 0;
+    } else {
+      real = real < h ? real : h;
+    }
+    n = h;
+  }
+  return real > 0 ? j : N;
+}
+// dst[j] = the wave sum of v[j] for every j < N (written by the lane that holds it).
+template <typename R, int N>
+__device__ __forceinline__ void wave_sums(const R (&v)[N], R* dst) {
+  static_assert(N >= 1 && N <= 64, "values per transposed wave sum");
+  const int lane = threadIdx.x & 63;
+  const R s = TSum<R, N, 0>::run(v, lane);
+  const int j = tsum_index<N>(lane);
+  if (j < N) dst[j] = s;
+}
+
 // ------------------------------------------------------------------ images
 // gC [N][M][F][T]: H = W^{-1} (Gauss-Jordan, partial pivoting), then
 // g_H = g_C Y^H, g_Y = H^H g_C (rows of each source), g_W = -H^H g_H H^H + g_Y xbar^H,
@@ -638,11 +719,7 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs<R> a) {
     ph[p] = w;
     gph[p] = R(0.0);
   }
-  // frame sum v of this wave into its slot; then block_finish adds the waves' slots
-  auto wave_put = [&](int v, R x) {
-    const R s = group_sum<64>(x);  // DPP within rows of 16 lanes, two cross-row steps
-    if (lane == 0) red[wave * 3 * MB + v] = s;
-  };
+  // the waves' frame sums go to their slots (wave_sums); block_finish adds the slots
   auto block_finish = [&](int nv) {
     __syncthreads();
     if (tid < nv) {
@@ -657,15 +734,22 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs<R> a) {
     constexpr int r = decltype(rc)::value;
     if (r < Mb) {
     const Cx<R> yr = y[r];
+    // the frame sums of rows p0 .. p0 + 3 (3 values each), transposed wave sums
+    auto fwd_sums = [&](auto cc) {
+      constexpr int p0 = 4 * decltype(cc)::value, NR = MB - p0 < 4 ? MB - p0 : 4;
+      R v[3 * NR];
 #pragma unroll
-    for (int p = 0; p < MB; ++p) {
-      if (p < Mb) {
+      for (int i = 0; i < NR; ++i) {
+        const int p = p0 + i;
         const Cx<R> q = cmulc(y[p], yr);
-        wave_put(3 * p, ph[p] * cabs2(yr));
-        wave_put(3 * p + 1, ph[p] * q.x);
-        wave_put(3 * p + 2, ph[p] * q.y);
+        const bool ok = p < Mb;
+        v[3 * i] = ok ? ph[p] * cabs2(yr) : R(0.0);
+        v[3 * i + 1] = ok ? ph[p] * q.x : R(0.0);
+        v[3 * i + 2] = ok ? ph[p] * q.y : R(0.0);
       }
-    }
+      wave_sums<R, 3 * NR>(v, red + wave * 3 * MB + 3 * p0);
+    };
+    static_for(fwd_sums, std::make_integer_sequence<int, (MB + 3) / 4>{});
     if (tid < Mb) wr[tid] = W[r * MB + tid];
     block_finish(3 * Mb);
     if (tid < Mb) {
@@ -710,14 +794,21 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs<R> a) {
     y[r] = cscale(y[r], R(1.0) / sc);  // row r before the step
     const Cx<R> yr = y[r];
     if (tid < Mb) wr[tid] = cscale(W[r * MB + tid], R(1.0) / sc);
+    // the frame sums of rows p0 .. p0 + 5 (2 values each), transposed wave sums
+    auto rev_sums = [&](auto cc) {
+      constexpr int p0 = 6 * decltype(cc)::value, NR = MB - p0 < 6 ? MB - p0 : 6;
+      R v[2 * NR];
 #pragma unroll
-    for (int p = 0; p < MB; ++p) {
-      if (p < Mb) {
+      for (int i = 0; i < NR; ++i) {
+        const int p = p0 + i;
         const Cx<R> q = cmulc(gy[p], yr);
-        wave_put(2 * p, q.x);
-        wave_put(2 * p + 1, q.y);
+        const bool ok = p < Mb;
+        v[2 * i] = ok ? q.x : R(0.0);
+        v[2 * i + 1] = ok ? q.y : R(0.0);
       }
-    }
+      wave_sums<R, 2 * NR>(v, red + wave * 3 * MB + 2 * p0);
+    };
+    static_for(rev_sums, std::make_integer_sequence<int, (MB + 5) / 6>{});
     block_finish(2 * Mb);  // also completes wr
     if (tid < Mb) {
       const int p = tid;
