@@ -955,23 +955,43 @@ __global__ void __launch_bounds__(256) k_adj_l1(AdjArgs<R> a) {
   if (lane == 0) a.gB[i] += s;
 }
 
-// One wave per (n, k, s), lanes over f:
-// gV += sum_f (B^ glamh + H1 P / lam^2 + H2 c / lam + Bk glam).
+// gV[n][k][s] += sum_f (B^ glamh + H1 P / lam^2 + H2 c / lam + Bk glam).  One workgroup
+// of 16 waves per (source n, 64 frames, 8 bases): lane l takes frame 64 x + l (the
+// (n, f, s) arrays are read along s, contiguously, once for all 8 bases), wave w the bins
+// f = w, w + 16, ... (the (n, f, k) factors are the same for the whole wave); the waves'
+// partial sums are added in wave order through LDS.
+constexpr int kL2Waves = 16, kL2Bases = 8;
 template <typename R>
-__global__ void __launch_bounds__(256) k_adj_l2(AdjArgs<R> a) {
-  const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (i >= (size_t)a.N * a.K * a.T) return;
-  const int s = (int)(i % a.T), k = (int)((i / a.T) % a.K), n = (int)(i / ((size_t)a.K * a.T));
-  const R c = tapc<R>(a.rm, n, s, a.T);
-  R acc = R(0.0);
-  for (int f = lane; f < a.F; f += 64) {
-    const size_t fk = ((size_t)n * a.F + f) * a.K + k, fs = ((size_t)n * a.F + f) * a.T + s;
-    const R il = a.ilam[fs];
-    acc += a.Bh[fk] * a.glamh[fs] + a.H1[fk] * a.P[fs] * il * il + a.H2[fk] * c * il + a.Bk[fk] * a.glam[fs];
+__global__ void __launch_bounds__(64 * kL2Waves) k_adj_l2(AdjArgs<R> a) {
+  __shared__ R part[kL2Waves][kL2Bases][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ntile = (a.T + 63) / 64, nkc = (a.K + kL2Bases - 1) / kL2Bases;
+  const int tile = blockIdx.x % ntile, kc = (blockIdx.x / ntile) % nkc, n = blockIdx.x / (ntile * nkc);
+  const int s = tile * 64 + lane, k0 = kc * kL2Bases;
+  const bool ok = s < a.T;
+  const R c = ok ? tapc<R>(a.rm, n, s, a.T) : R(0.0);
+  R acc[kL2Bases];
+#pragma unroll
+  for (int kk = 0; kk < kL2Bases; ++kk) acc[kk] = R(0.0);
+  if (ok) {
+    for (int f = wave; f < a.F; f += kL2Waves) {
+      const size_t fs = ((size_t)n * a.F + f) * a.T + s, fk = ((size_t)n * a.F + f) * a.K + k0;
+      const R il = a.ilam[fs], e1 = a.glamh[fs], e2 = a.P[fs] * il * il, e3 = c * il, e4 = a.glam[fs];
+#pragma unroll
+      for (int kk = 0; kk < kL2Bases; ++kk) {
+        if (k0 + kk < a.K)
+          acc[kk] += a.Bh[fk + kk] * e1 + a.H1[fk + kk] * e2 + a.H2[fk + kk] * e3 + a.Bk[fk + kk] * e4;
+      }
+    }
   }
-  acc = wave_sum(acc);
-  if (lane == 0) a.gV[i] += acc;
+#pragma unroll
+  for (int kk = 0; kk < kL2Bases; ++kk) part[wave][kk][lane] = acc[kk];
+  __syncthreads();
+  if (wave < kL2Bases && ok && k0 + wave < a.K) {  // wave kk adds basis kk's partials
+    R sum = R(0.0);
+    for (int w = 0; w < kL2Waves; ++w) sum += part[w][wave][lane];
+    a.gV[((size_t)n * a.K + k0 + wave) * a.T + s] += sum;
+  }
 }
 
 }  // namespace
@@ -1089,7 +1109,8 @@ hipError_t adj_iteration_t(const AdjPtrs& p, const Dims& d, double floor, hipStr
     hipLaunchKernelGGL(k_adj_iss<R>, dim3(d.F), dim3(256), lds, s, a);
   }
   hipLaunchKernelGGL(k_adj_l1<R>, blocks(nfk * 64), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_l2<R>, blocks(nkt * 64), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_adj_l2<R>, dim3((unsigned)(d.N * ((d.K + kL2Bases - 1) / kL2Bases) * ((d.T + 63) / 64))),
+                     dim3(64 * kL2Waves), 0, s, a);
   return hipGetLastError();
 }
 }  // namespace
