@@ -228,6 +228,33 @@ hipError_t launch_zero_status(int* status, hipStream_t s) {
 __global__ void __launch_bounds__(256) k_zero_words(unsigned long long* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
+// Three device-to-device copies of 32-bit words in one launch (the per-iteration
+// saves and restores of W, B and V in the reverse pass are launch-bound copies).
+struct Copy3 {
+  unsigned* dst[3];
+  const unsigned* src[3];
+  size_t words[3];
+};
+__global__ void __launch_bounds__(256) k_copy3(Copy3 c) {
+  const size_t n0 = c.words[0], n1 = n0 + c.words[1], n = n1 + c.words[2];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int r = i < n0 ? 0 : (i < n1 ? 1 : 2);
+    const size_t j = i - (r == 0 ? 0 : (r == 1 ? n0 : n1));
+    c.dst[r][j] = c.src[r][j];
+  }
+}
+// bytes: multiples of 4 (every state array here is).
+hipError_t launch_copy3(void* d0, const void* s0, size_t b0, void* d1, const void* s1, size_t b1, void* d2,
+                        const void* s2, size_t b2, hipStream_t s) {
+  Copy3 c{{static_cast<unsigned*>(d0), static_cast<unsigned*>(d1), static_cast<unsigned*>(d2)},
+          {static_cast<const unsigned*>(s0), static_cast<const unsigned*>(s1), static_cast<const unsigned*>(s2)},
+          {b0 / 4, b1 / 4, b2 / 4}};
+  const size_t n = c.words[0] + c.words[1] + c.words[2];
+  if (n == 0) return hipSuccess;
+  const size_t blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+  hipLaunchKernelGGL(k_copy3, dim3((unsigned)blocks), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
 hipError_t launch_zero_words(unsigned long long* p, size_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const size_t blocks = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
@@ -1024,9 +1051,8 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
   c->have_state = true;
   c->y_valid = false;
   for (int k = 0; k <= n_iter; ++k) {
-    e = cp(ws + L.ckW + k * wb, c->ptr.W, wb);
-    if (e == hipSuccess) e = cp(ws + L.ckB + k * bb, c->ptr.B, bb);
-    if (e == hipSuccess) e = cp(ws + L.ckV + k * vb, c->ptr.V, vb);
+    e = launch_copy3(ws + L.ckW + k * wb, c->ptr.W, wb, ws + L.ckB + k * bb, c->ptr.B, bb, ws + L.ckV + k * vb,
+                     c->ptr.V, vb, s);
     if (e != hipSuccess) return CTFISS_E_HIP;
     if (k < n_iter) {
       const int st = ctfiss_iterate(c, 1, nullptr);
@@ -1073,9 +1099,8 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
   for (int k = n_iter - 1; k >= 0 && e == hipSuccess; --k) {
     // iteration k again from its saved state, stopping before the rescale is
     // applied: W = W^s, B = B^, V = V^, mu, P and 1/lambda of iteration k
-    e = cp(c->ptr.W, ws + L.ckW + k * wb, wb);
-    if (e == hipSuccess) e = cp(c->ptr.B, ws + L.ckB + k * bb, bb);
-    if (e == hipSuccess) e = cp(c->ptr.V, ws + L.ckV + k * vb, vb);
+    e = launch_copy3(c->ptr.W, ws + L.ckW + k * wb, wb, c->ptr.B, ws + L.ckB + k * bb, bb, c->ptr.V,
+                     ws + L.ckV + k * vb, vb, s);
     c->epoch = c->epoch % 0x1FFFFFFu + 1u;
     if (f32) {
       if (e == hipSuccess) e = lambda_t<float>(d, c->ptr, false, s);
@@ -1107,9 +1132,9 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
   if (e == hipSuccess && gB0) e = cp(gB0, p.gB, bb);
   if (e == hipSuccess && gV0) e = cp(gV0, p.gV, vb);
   // the context ends in the forward's final state
-  if (e == hipSuccess) e = cp(c->ptr.W, ws + L.ckW + n_iter * wb, wb);
-  if (e == hipSuccess) e = cp(c->ptr.B, ws + L.ckB + n_iter * bb, bb);
-  if (e == hipSuccess) e = cp(c->ptr.V, ws + L.ckV + n_iter * vb, vb);
+  if (e == hipSuccess)
+    e = launch_copy3(c->ptr.W, ws + L.ckW + n_iter * wb, wb, c->ptr.B, ws + L.ckB + n_iter * bb, bb, c->ptr.V,
+                     ws + L.ckV + n_iter * vb, vb, s);
   c->y_valid = false;
   return e == hipSuccess ? CTFISS_OK : CTFISS_E_HIP;
 }
