@@ -214,7 +214,7 @@ int ctfiss_nll(ctfiss_ctx* ctx, double* out);
  * reversed from its saved state (hand-written adjoint kernels of the rescale,
  * activation and basis updates, the ISS sweep row by row and the demix).
  * ISS contexts in FP32 (complex64, the kernels' arithmetic in FP32) or FP64,
- * with the all-taps activation rule and Mbar <= 32 only (else
+ * under either activation rule (the context's), with Mbar <= 32 only (else
  * CTFISS_E_UNSUPPORTED).  aws: device workspace of
  * ctfiss_adjoint_workspace_size() bytes (256-byte aligned), scratch for the
  * call.  The context ends in the forward's final state, as after

@@ -10,7 +10,8 @@ The computation is the one the NumPy oracle documents, with the same
 readings: ISS sweep with rows r ascending (Eqs. (11), (16); numerator
 w_p^H Q_p w_r, z_r = 1 - d_r^{-1/2}), delayed variances dropped before frame 0,
 basis update Eq. (17), activation update over all taps of a source (the
-majorise-minimise step of Eq. (5)), factor floor after each multiplicative
+majorise-minimise step of Eq. (5); vrule "all_taps") or over tap 0 only
+(Eq. (18) as printed; vrule "paper_tap0"), factor floor after each multiplicative
 update, rescale Eqs. (19)-(21), and source images by projection back
 (Eq. (24) with H = W^{-1}).  The loss is the mean over all elements of
 |c - c_target|^2.
@@ -20,6 +21,8 @@ from __future__ import annotations
 import torch
 
 FLOOR = 1e-8
+ALL_TAPS = "all_taps"
+PAPER_TAP0 = "paper_tap0"
 
 
 def stacked(X, D):
@@ -80,7 +83,13 @@ def iss_sweep(W, Y, phi):
     return W, Y
 
 
-def iteration(W, B, V, Xb, taps, floor=FLOOR):
+def tap0_power(Y, taps):
+    """P0[n, f, s] = |y_(n,0)[s]|^2, the power of the first tap row of each source."""
+    first = [sum(taps[:n]) for n in range(len(taps))]
+    return torch.stack([Y[:, r, :].abs() ** 2 for r in first])
+
+
+def iteration(W, B, V, Xb, taps, floor=FLOOR, vrule=ALL_TAPS):
     N, F, K = B.shape
     T = Xb.shape[-1]
     lam = B @ V
@@ -91,7 +100,10 @@ def iteration(W, B, V, Xb, taps, floor=FLOOR):
     num = (P / lam ** 2) @ V.transpose(1, 2)
     den = (c[:, None, :] / lam) @ V.transpose(1, 2)
     B = torch.clamp(B * torch.sqrt(num / den), min=floor)
-    # activations with the new bases: sums over f of b P / lambda^2 and b c / lambda
+    # activations with the new bases: sums over f of b P / lambda^2 and b c / lambda, with
+    # P the tap-0 power and c = 1 under Eq. (18) as printed
+    if vrule == PAPER_TAP0:
+        P, c = tap0_power(Y, taps), torch.ones_like(c)
     lam = B @ V
     num = B.transpose(1, 2) @ (P / lam ** 2)
     den = B.transpose(1, 2) @ (c[:, None, :] / lam)
@@ -116,7 +128,7 @@ def images(W, Xb, taps, M):
     return torch.stack(out)
 
 
-def forward(X, B0, V0, D, taps, n_iter, floor=FLOOR):
+def forward(X, B0, V0, D, taps, n_iter, floor=FLOOR, vrule=ALL_TAPS):
     """Images after n_iter iterations from W = I (Sec. V-A), B0, V0."""
     M, F, T = X.shape
     Xb = stacked(X, D)
@@ -124,7 +136,7 @@ def forward(X, B0, V0, D, taps, n_iter, floor=FLOOR):
     W = torch.eye(Mb, dtype=torch.complex128).expand(F, Mb, Mb)
     B, V = B0, V0
     for _ in range(n_iter):
-        W, B, V = iteration(W, B, V, Xb, taps, floor)
+        W, B, V = iteration(W, B, V, Xb, taps, floor, vrule)
     return images(W, Xb, taps, M), W, B, V
 
 

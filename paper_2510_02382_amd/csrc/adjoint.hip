@@ -8,7 +8,9 @@
 //   Y = W xbar (Eqs. (11), (16));  P[n, s] = sum_l |y_(n,l)[s + l]|^2;
 //   B^ = max(B sqrt(sum_s P v / lambda^2 / sum_s c v / lambda), floor)  (Eq. (17));
 //   V^ = max(V sqrt(sum_f B^ P / lambda^2 / sum_f B^ c / lambda), floor) with
-//   lambda = B^ V (all taps of a source, c[n, s] = #{l : s + l < T});
+//   lambda = B^ V (all taps of a source, c[n, s] = #{l : s + l < T}; under
+//   Eq. (18) as printed, the tap-0 rule, P0[n, s] = |y_(n,0)[s]|^2 and 1 in
+//   place of P and c);
 //   mu_r = sqrt(sum_{f,t} |y_r|^2 / (F T)), W' = W^s / mu, B' = B^ / mu_first^2,
 //   V' = V^  (Eqs. (19)-(21)),
 // and the images are c_n = H[:M, rows(n)] y_rows(n) with H = W^{-1} (Eq. (24)).
@@ -47,6 +49,7 @@ struct AdjArgs {
   const R* Vh;  // [N][K][T] after the activation update
   const R* ilam;  // [N][F][T] 1 / (Bk Vk)
   const R* P;     // [N][F][T] tap-aligned powers of the swept rows
+  const R* P0;    // [N][F][T] tap-0 powers (tap-0 activation rule) or null
   const R* mu;    // [Mb]
   // adjoints
   Cx<R>* gW;       // [F][Mb][Mb] in: of W', out: of Wk
@@ -55,11 +58,12 @@ struct AdjArgs {
   R* gBh;  // [N][F][K]
   R* gVh;  // [N][K][T]
   R* gP;   // [N][F][T]
+  R* gP0;  // [N][F][T] of P0 (tap-0 activation rule) or null
   R* glam;   // [N][F][T] of lambda = Bk Vk
   R* glamh;  // [N][F][T] of lambda = B^ Vk
   R* lamh;   // [N][F][T] B^ Vk
-  R* q1;     // [N][F][T] P / lamh^2
-  R* q2;     // [N][F][T] c / lamh
+  R* q1;     // [N][F][T] P / lamh^2 (P0 / lamh^2 under the tap-0 rule)
+  R* q2;     // [N][F][T] c / lamh (1 / lamh under the tap-0 rule)
   R* G1;     // [N][K][T] adjoint of the activation update's numerator sum
   R* G2;     // [N][K][T] ... denominator sum
   R* H1;     // [N][F][K] adjoint of the basis update's numerator sum
@@ -362,7 +366,7 @@ __global__ void __launch_bounds__(256) k_adj_rescale_apply(AdjArgs<R> a) {
 }
 
 // ------------------------------------------------------------------ activation update
-// Per (n, f, s): lamh = B^ Vk, q1 = P / lamh^2, q2 = c / lamh.
+// Per (n, f, s): lamh = B^ Vk, q1 = P / lamh^2, q2 = c / lamh (P0 and 1 under the tap-0 rule).
 template <typename R>
 __global__ void __launch_bounds__(256) k_adj_v0(AdjArgs<R> a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -372,8 +376,8 @@ __global__ void __launch_bounds__(256) k_adj_v0(AdjArgs<R> a) {
   R lam = R(0.0);
   for (int k = 0; k < a.K; ++k) lam += b[k] * a.Vk[((size_t)n * a.K + k) * a.T + s];
   a.lamh[i] = lam;
-  a.q1[i] = a.P[i] / (lam * lam);
-  a.q2[i] = tapc<R>(a.rm, n, s, a.T) / lam;
+  a.q1[i] = (a.P0 ? a.P0[i] : a.P[i]) / (lam * lam);
+  a.q2[i] = (a.P0 ? R(1.0) : tapc<R>(a.rm, n, s, a.T)) / lam;
 }
 
 // One wave per (n, k, s): num = sum_f B^ q1, den = sum_f B^ q2 (lanes over f);
@@ -410,7 +414,8 @@ __global__ void __launch_bounds__(256) k_adj_v1(AdjArgs<R> a) {
 }
 
 // Per (n, f, s): lamh = B^ Vk; gP = sum_k G1 B^ / lamh^2 (first contribution);
-// glamh = sum_k (-2 G1 B^ P / lamh^3 - G2 B^ c / lamh^2).
+// glamh = sum_k (-2 G1 B^ P / lamh^3 - G2 B^ c / lamh^2).  Under the tap-0 rule
+// P0 and 1 stand for P and c, that sum is gP0, and gP starts at zero.
 template <typename R>
 __global__ void __launch_bounds__(256) k_adj_v2(AdjArgs<R> a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -418,14 +423,19 @@ __global__ void __launch_bounds__(256) k_adj_v2(AdjArgs<R> a) {
   const int s = (int)(i % a.T), f = (int)((i / a.T) % a.F), n = (int)(i / ((size_t)a.F * a.T));
   const R* b = a.Bh + ((size_t)n * a.F + f) * a.K;
   const R lam = a.lamh[i];
-  const R p = a.P[i], c = tapc<R>(a.rm, n, s, a.T);
+  const R p = a.P0 ? a.P0[i] : a.P[i], c = a.P0 ? R(1.0) : tapc<R>(a.rm, n, s, a.T);
   R gp = R(0.0), gl = R(0.0);
   for (int k = 0; k < a.K; ++k) {
     const size_t o = ((size_t)n * a.K + k) * a.T + s;
     gp += a.G1[o] * b[k] / (lam * lam);
     gl += -R(2.0) * a.G1[o] * b[k] * p / (lam * lam * lam) - a.G2[o] * b[k] * c / (lam * lam);
   }
-  a.gP[i] = gp;
+  if (a.P0) {
+    a.gP0[i] = gp;
+    a.gP[i] = R(0.0);
+  } else {
+    a.gP[i] = gp;
+  }
   a.glamh[i] = gl;
 }
 
@@ -487,8 +497,9 @@ __global__ void __launch_bounds__(256) k_adj_b2(AdjArgs<R> a) {
 
 // ------------------------------------------------------------------ ISS sweep
 // One workgroup per bin.  Forward: Y = Wk xbar, the sweep with z and d_p
-// recorded.  Backward from gW^s and gY^s = 2 y (tap-aligned gP) + 2 gS_r y_r,
-// rows r = Mb-1 .. 0.  Then the demix (gW += gY xbar^H, gxbar = Wk^H gY) and
+// recorded.  Backward from gW^s and gY^s = 2 y (tap-aligned gP) + 2 gS_r y_r
+// (+ 2 y gP0 on the tap-0 rows under the tap-0 rule), rows r = Mb-1 .. 0.
+// Then the demix (gW += gY xbar^H, gxbar = Wk^H gY) and
 // glam += -sum_l gphi_(n,l)[s + l] / lam^2.
 template <typename R>
 __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs<R> a) {
@@ -569,6 +580,7 @@ __global__ void __launch_bounds__(256) k_adj_iss(AdjArgs<R> a) {
     const int n = a.rm.src[r], l = a.rm.tap[r];
     R g = R(2.0) * a.gS[r];
     if (t >= l) g += R(2.0) * a.gP[((size_t)n * F + f) * T + t - l];
+    if (a.gP0 && l == 0) g += R(2.0) * a.gP0[((size_t)n * F + f) * T + t];
     gY[e] = cscale(Y[e], g);
     gphi[e] = R(0.0);
   }
@@ -783,6 +795,7 @@ __global__ void __launch_bounds__(512) k_adj_iss_reg(AdjArgs<R> a) {
       const int n = a.rm.src[p], l = a.rm.tap[p];
       g = R(2.0) * a.gS[p];
       if (t >= l) g += R(2.0) * a.gP[((size_t)n * F + f) * T + t - l];
+      if (a.gP0 && l == 0) g += R(2.0) * a.gP0[((size_t)n * F + f) * T + t];
     }
     gy[p] = cscale(y[p], g);
   }
@@ -1024,6 +1037,7 @@ AdjArgs<R> make_adj(const AdjPtrs& p, const Dims& d, double floor) {
   a.Vh = static_cast<const R*>(p.Vh);
   a.ilam = static_cast<const R*>(p.ilam);
   a.P = static_cast<const R*>(p.P);
+  a.P0 = static_cast<const R*>(p.P0);
   a.mu = static_cast<const R*>(p.mu);
   a.gW = static_cast<Cx<R>*>(p.gW);
   a.gB = static_cast<R*>(p.gB);
@@ -1031,6 +1045,7 @@ AdjArgs<R> make_adj(const AdjPtrs& p, const Dims& d, double floor) {
   a.gBh = static_cast<R*>(p.gBh);
   a.gVh = static_cast<R*>(p.gVh);
   a.gP = static_cast<R*>(p.gP);
+  a.gP0 = static_cast<R*>(p.gP0);
   a.glam = static_cast<R*>(p.glam);
   a.glamh = static_cast<R*>(p.glamh);
   a.lamh = static_cast<R*>(p.lamh);

@@ -959,7 +959,7 @@ const char* ctfiss_status_string(int status) {
 namespace {
 
 struct AdjLayout {
-  size_t ckW, ckB, ckV, gW, gB, gBh, gV, gVh, gP, glam, glamh, lamh, q1, q2, G1, G2, H1, H2, part, gS, Y, gY, gphi,
+  size_t ckW, ckB, ckV, gW, gB, gBh, gV, gVh, gP, gP0, glam, glamh, lamh, q1, q2, G1, G2, H1, H2, part, gS, Y, gY, gphi,
       zt, dt, total;
 };
 
@@ -983,6 +983,7 @@ AdjLayout adj_layout(const Dims& d, int n_iter, size_t rs) {
   L.gV = take(v);
   L.gVh = take(v);
   L.gP = take(ft);
+  L.gP0 = take(ft);
   L.glam = take(ft);
   L.glamh = take(ft);
   L.lamh = take(ft);
@@ -1003,8 +1004,8 @@ AdjLayout adj_layout(const Dims& d, int n_iter, size_t rs) {
   return L;
 }
 
-// Reverse mode is built for FP32 and FP64 ISS contexts with the all-taps
-// activation rule, Mbar <= 32 and LDS for the per-bin adjoint kernels.
+// Reverse mode is built for FP32 and FP64 ISS contexts (either activation
+// rule), Mbar <= 32 and LDS for the per-bin adjoint kernels.
 bool adj_supported(const Dims& d, int rs) {
   return d.Mb <= 32 && adj_iss_lds(d.Mb, d.T, rs) <= kMaxLdsBytes && adj_images_lds(d.Mb, d.M, rs) <= kMaxLdsBytes;
 }
@@ -1028,10 +1029,10 @@ int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int precision, int3
 int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V0, const void* gC, void* gX,
                     void* gB0, void* gV0, void* aws, size_t aws_bytes) {
   if (!c || !B0 || !V0 || !gC || !gX || !aws || n_iter < 1) return CTFISS_E_ARG;
-  if (wx(c->prec) || c->rule != CTFISS_RULE_ISS || c->vrule != CTFISS_VRULE_ALL_TAPS)
-    return CTFISS_E_UNSUPPORTED;
+  if (wx(c->prec) || c->rule != CTFISS_RULE_ISS) return CTFISS_E_UNSUPPORTED;
   const Dims& d = c->d;
   const bool f32 = c->prec == CTFISS_FP32;
+  const bool tap0 = c->vrule == CTFISS_VRULE_PAPER_TAP0;
   const int rs = f32 ? 4 : 8;
   if (!adj_supported(d, rs)) return CTFISS_E_UNSUPPORTED;
   if (!c->have_input) return CTFISS_E_ORDER;
@@ -1067,6 +1068,7 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
   p.gBh = ws + L.gBh;
   p.gVh = ws + L.gVh;
   p.gP = ws + L.gP;
+  p.gP0 = tap0 ? ws + L.gP0 : nullptr;
   p.glam = ws + L.glam;
   p.glamh = ws + L.glamh;
   p.lamh = ws + L.lamh;
@@ -1106,16 +1108,16 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
       if (e == hipSuccess) e = lambda_t<float>(d, c->ptr, false, s);
       if (e == hipSuccess) e = wupdate_t<float>(c->rule, sep, d, c->ptr, false, false, c->epoch, c->floor, s);
       if (e == hipSuccess) e = nmfb_t<float>(d, c->ptr, c->floor, false, s);
-      if (e == hipSuccess && c->vone) e = vupdate_t<float>(d, c->ptr, c->floor, false, s);
-      if (e == hipSuccess && !c->vone) e = vpart_t<float>(d, c->vs, c->ptr, false, s);
-      if (e == hipSuccess && !c->vone) e = vfinal_t<float>(d, c->vs, c->ptr, c->floor, false, s);
+      if (e == hipSuccess && c->vone) e = vupdate_t<float>(d, c->ptr, c->floor, tap0, s);
+      if (e == hipSuccess && !c->vone) e = vpart_t<float>(d, c->vs, c->ptr, tap0, s);
+      if (e == hipSuccess && !c->vone) e = vfinal_t<float>(d, c->vs, c->ptr, c->floor, tap0, s);
     } else {
       if (e == hipSuccess) e = lambda_t<double>(d, c->ptr, false, s);
       if (e == hipSuccess) e = wupdate_t<double>(c->rule, sep, d, c->ptr, false, false, c->epoch, c->floor, s);
       if (e == hipSuccess) e = nmfb_t<double>(d, c->ptr, c->floor, false, s);
-      if (e == hipSuccess && c->vone) e = vupdate_t<double>(d, c->ptr, c->floor, false, s);
-      if (e == hipSuccess && !c->vone) e = vpart_t<double>(d, c->vs, c->ptr, false, s);
-      if (e == hipSuccess && !c->vone) e = vfinal_t<double>(d, c->vs, c->ptr, c->floor, false, s);
+      if (e == hipSuccess && c->vone) e = vupdate_t<double>(d, c->ptr, c->floor, tap0, s);
+      if (e == hipSuccess && !c->vone) e = vpart_t<double>(d, c->vs, c->ptr, tap0, s);
+      if (e == hipSuccess && !c->vone) e = vfinal_t<double>(d, c->vs, c->ptr, c->floor, tap0, s);
     }
     if (e != hipSuccess) break;
     p.Wk = ws + L.ckW + k * wb;
@@ -1126,6 +1128,7 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
     p.Vh = c->ptr.V;
     p.ilam = c->ptr.ilam;
     p.P = c->ptr.P;
+    p.P0 = c->ptr.P0;
     p.mu = c->ptr.mu;
     e = adj_iteration(p, d, c->floor, rs, s);
   }

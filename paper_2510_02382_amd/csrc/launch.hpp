@@ -127,10 +127,12 @@ struct AdjPtrs {
   const void* Vh;                    // V after the activation update
   const void* ilam;                  // 1 / (Bk Vk)
   const void* P;                     // tap-aligned powers of the swept rows
+  const void* P0;                    // tap-0 powers (tap-0 activation rule) or null
   const void* mu;                    // row scales of the iteration
   void* gW;                          // adjoints of the state: in, of the next state; out, of this one
   void* gB;
   void* gV;
+  void* gP0;                         // adjoint of P0 (tap-0 activation rule) or null
   void *gBh, *gVh, *gP, *glam, *glamh, *lamh, *q1, *q2, *G1, *G2, *H1, *H2, *part, *gS;  // scratch
   void* gX;                          // [M][F][T] accumulated
   int* status;

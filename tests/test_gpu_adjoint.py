@@ -15,6 +15,9 @@ reference gradients at 3e-4: measured 3e-7 to 7e-5, where one FP32 rounding
 is 6e-8 and the reverse pass adds a few hundred of them per gradient
 component (the finite differences of an FP32 forward are themselves noisier
 than that, ~3e-3 at h = 1e-3, so they do not check it).
+
+The activation update as Eq. (18) prints it (tap 0 only) is reversed as well:
+the same checks run under that rule against the reference's tap-0 forward.
 """
 import numpy as np
 import pytest
@@ -51,24 +54,24 @@ def problem(name, seed=0):
     return X, B0, V0, target, D, taps, n
 
 
-def reference(X, B0, V0, target, D, taps, n):
+def reference(X, B0, V0, target, D, taps, n, vrule="all_taps"):
     from oracle import ctf_iss_torch as ot
     Xt = torch.from_numpy(X).requires_grad_(True)
     Bt = torch.from_numpy(B0).requires_grad_(True)
     Vt = torch.from_numpy(V0).requires_grad_(True)
-    C = ot.forward(Xt, Bt, Vt, D, taps, n)[0]
+    C = ot.forward(Xt, Bt, Vt, D, taps, n, vrule=vrule)[0]
     ot.mse(C, torch.from_numpy(target)).backward()
     return C.detach().numpy(), Xt.grad.numpy(), Bt.grad.numpy(), Vt.grad.numpy()
 
 
-def gpu(X, B0, V0, target, D, taps, n, precision="fp64"):
+def gpu(X, B0, V0, target, D, taps, n, precision="fp64", vrule="all_taps"):
     from paper_2510_02382_amd.autograd import separate
     cd = torch.complex64 if precision == "fp32" else torch.complex128
     rd = torch.float32 if precision == "fp32" else torch.float64
     Xg = torch.from_numpy(X).to("cuda", cd).requires_grad_(True)
     Bg = torch.from_numpy(B0).to("cuda", rd).requires_grad_(True)
     Vg = torch.from_numpy(V0).to("cuda", rd).requires_grad_(True)
-    C = separate(Xg, Bg, Vg, D, taps, n)
+    C = separate(Xg, Bg, Vg, D, taps, n, vrule=vrule)
     loss = ((C - torch.from_numpy(target).to("cuda", cd)).abs() ** 2).mean()
     loss.backward()
     torch.cuda.synchronize()
@@ -96,8 +99,37 @@ def test_fp32_gradients_match_fp64_reference(case):
         assert rel(g, r) < 3e-4, (name, rel(g, r))
 
 
-@pytest.mark.parametrize("case", ["small", "c4_slice"])
-def test_gradients_match_central_differences(case):
+@pytest.mark.parametrize("case", list(CASES))
+def test_tap0_rule_gradients_match_autograd_reference(case):
+    args = problem(case, seed=5)
+    C, gX, gB, gV = gpu(*args, vrule="paper_tap0")
+    Cr, gXr, gBr, gVr = reference(*args, vrule="paper_tap0")
+    tol = TOL[case]
+    for name, g, r in (("C", C, Cr), ("gX", gX, gXr), ("gB0", gB, gBr), ("gV0", gV, gVr)):
+        assert rel(g, r) < tol, (name, rel(g, r))
+
+
+@pytest.mark.parametrize("case", ["uneven_taps", "c4_slice"])
+def test_tap0_rule_fp32_gradients_match_fp64_reference(case):
+    args = problem(case, seed=5)
+    C, gX, gB, gV = gpu(*args, precision="fp32", vrule="paper_tap0")
+    Cr, gXr, gBr, gVr = reference(*args, vrule="paper_tap0")
+    for name, g, r in (("C", C, Cr), ("gX", gX, gXr), ("gB0", gB, gBr), ("gV0", gV, gVr)):
+        assert rel(g, r) < 3e-4, (name, rel(g, r))
+
+
+def test_tap0_rule_changes_the_gradients():
+    """The two rules' gradients differ where a source has several taps, so the tap-0 checks
+    above are not passed by the all-taps reverse pass."""
+    args = problem("uneven_taps", seed=5)
+    _, gXa, gBa, gVa = gpu(*args)
+    _, gXp, gBp, gVp = gpu(*args, vrule="paper_tap0")
+    assert rel(gVa, gVp) > 1e-3 and rel(gXa, gXp) > 1e-3
+
+
+@pytest.mark.parametrize("case,vrule", [("small", "all_taps"), ("c4_slice", "all_taps"),
+                                        ("uneven_taps", "paper_tap0")])
+def test_gradients_match_central_differences(case, vrule):
     from paper_2510_02382_amd import Separator
     X, B0, V0, target, D, taps, n = problem(case, seed=3)
     M, F, T = X.shape
@@ -105,7 +137,7 @@ def test_gradients_match_central_differences(case):
     tgt = torch.from_numpy(target).cuda()
 
     def loss(Xn, Bn):
-        sep = Separator(F, T, M, D, N, K, taps, precision="fp64")
+        sep = Separator(F, T, M, D, N, K, taps, precision="fp64", vrule=vrule)
         sep.set_input(torch.from_numpy(np.ascontiguousarray(Xn)).cuda())
         sep.set_state(B=torch.from_numpy(np.ascontiguousarray(Bn)).cuda(), V=torch.from_numpy(V0).cuda())
         sep.iterate(n)
@@ -114,7 +146,7 @@ def test_gradients_match_central_differences(case):
         sep.close()
         return out
 
-    _, gX, gB, _ = gpu(X, B0, V0, target, D, taps, n)
+    _, gX, gB, _ = gpu(X, B0, V0, target, D, taps, n, vrule=vrule)
     rng = rng_for(11)
     h = 1e-3
     for _ in range(2):
@@ -129,7 +161,7 @@ def test_gradients_match_central_differences(case):
         assert abs(an - fd) <= 1e-3 * abs(fd), (an, fd)
 
 
-def test_backward_rejects_mixed_precision_and_tap0_rule():
+def test_backward_rejects_mixed_precision():
     from paper_2510_02382_amd import Separator
     from paper_2510_02382_amd import binding as b
     X, B0, V0, target, D, taps, n = problem("small")
@@ -140,12 +172,6 @@ def test_backward_rejects_mixed_precision_and_tap0_rule():
     sep.set_input(torch.from_numpy(X).cuda().to(torch.complex64))
     with pytest.raises(b.CtfissError) as e:
         sep.backward(n, torch.from_numpy(B0).cuda().float(), torch.from_numpy(V0).cuda().float(), gC)
-    assert e.value.status == b.CTFISS_E_UNSUPPORTED
-    sep.close()
-    sep = Separator(F, T, M, D, N, K, taps, precision="fp64", vrule="paper_tap0")
-    sep.set_input(torch.from_numpy(X).cuda())
-    with pytest.raises(b.CtfissError) as e:
-        sep.backward(n, torch.from_numpy(B0).cuda(), torch.from_numpy(V0).cuda(), gC.to(torch.complex128))
     assert e.value.status == b.CTFISS_E_UNSUPPORTED
     sep.close()
 

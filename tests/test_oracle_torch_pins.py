@@ -1,10 +1,12 @@
 """Pins of the FP64 PyTorch forward used for reference gradients (CPU).
 
 * Its forward equals the NumPy oracle's (W, B, V and the images) on a case
-  with stacked frames and uneven taps: the two are written separately, so a
-  dropped term or a wrong shift in either would show here.
+  with stacked frames and uneven taps, under both activation rules: the two
+  are written separately, so a dropped term or a wrong shift in either would
+  show here.
 * Its autograd gradients of the image MSE with respect to the mixture and the
-  initial bases match central finite differences of the same forward.
+  initial bases match central finite differences of the same forward, under
+  both activation rules.
 """
 import numpy as np
 import pytest
@@ -20,12 +22,14 @@ def _case(F, T, M, D, taps, K, seed):
     return X, B0, V0
 
 
-def test_torch_forward_matches_numpy_oracle():
+@pytest.mark.parametrize("vrule", [o.ALL_TAPS, o.PAPER_TAP0])
+def test_torch_forward_matches_numpy_oracle(vrule):
     F, T, M, D, taps, K = 3, 23, 2, 3, (4, 2), 3
     X, B0, V0 = _case(F, T, M, D, taps, K, 5)
-    W, B, V = o.run(X, D, taps, B0, V0, 4)
+    W, B, V = o.run(X, D, taps, B0, V0, 4, vrule=vrule)
     C = o.source_images(W, X, D, taps)
-    Ct, Wt, Bt, Vt = ot.forward(torch.from_numpy(X), torch.from_numpy(B0), torch.from_numpy(V0), D, taps, 4)
+    Ct, Wt, Bt, Vt = ot.forward(torch.from_numpy(X), torch.from_numpy(B0), torch.from_numpy(V0), D, taps, 4,
+                                vrule=vrule)
     for a, b in ((Wt, W), (Bt, B), (Vt, V), (Ct, C)):
         a = a.detach().numpy()
         assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-12
@@ -46,8 +50,18 @@ def test_torch_tap_power_matches_index_loops():
     assert list(c[0]) == [3, 3, 3, 3, 3, 2, 1] and list(c[1]) == [2, 2, 2, 2, 2, 2, 1]
 
 
+def test_torch_rules_differ():
+    """The two activation rules give different activations once a source has more than one tap."""
+    F, T, M, D, taps, K = 3, 23, 2, 3, (4, 2), 3
+    X, B0, V0 = (torch.from_numpy(a) for a in _case(F, T, M, D, taps, K, 5))
+    Va = ot.forward(X, B0, V0, D, taps, 1, vrule=ot.ALL_TAPS)[3]
+    Vp = ot.forward(X, B0, V0, D, taps, 1, vrule=ot.PAPER_TAP0)[3]
+    assert float((Va - Vp).abs().max()) > 1e-3 * float(Va.abs().max())
+
+
+@pytest.mark.parametrize("vrule", [ot.ALL_TAPS, ot.PAPER_TAP0])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_torch_gradients_match_central_differences(seed):
+def test_torch_gradients_match_central_differences(seed, vrule):
     F, T, M, D, taps, K, n_iter = 2, 12, 2, 2, (3, 1), 2, 3
     X, B0, V0 = _case(F, T, M, D, taps, K, 30 + seed)
     rng = rng_for(40 + seed)
@@ -55,12 +69,13 @@ def test_torch_gradients_match_central_differences(seed):
     tg = torch.from_numpy(target)
 
     def loss(Xn, Bn):
-        C = ot.forward(torch.from_numpy(Xn), torch.from_numpy(Bn), torch.from_numpy(V0), D, taps, n_iter)[0]
+        C = ot.forward(torch.from_numpy(Xn), torch.from_numpy(Bn), torch.from_numpy(V0), D, taps, n_iter,
+                       vrule=vrule)[0]
         return float(ot.mse(C, tg))
 
     Xt = torch.from_numpy(X).requires_grad_(True)
     Bt = torch.from_numpy(B0).requires_grad_(True)
-    C = ot.forward(Xt, Bt, torch.from_numpy(V0), D, taps, n_iter)[0]
+    C = ot.forward(Xt, Bt, torch.from_numpy(V0), D, taps, n_iter, vrule=vrule)[0]
     ot.mse(C, tg).backward()
     gX, gB = Xt.grad.numpy(), Bt.grad.numpy()
     dX = rng.standard_normal(X.shape) + 1j * rng.standard_normal(X.shape)
