@@ -213,9 +213,10 @@ int ctfiss_nll(ctfiss_ctx* ctx, double* out);
  * with the state saved before every iteration; each iteration is then
  * reversed from its saved state (hand-written adjoint kernels of the rescale,
  * activation and basis updates, the ISS sweep row by row and the demix).
- * ISS contexts in FP32 (complex64, the kernels' arithmetic in FP32) or FP64,
- * under either activation rule (the context's), with Mbar <= 32 only (else
- * CTFISS_E_UNSUPPORTED).  aws: device workspace of
+ * ISS contexts in FP32 (complex64, the kernels' arithmetic in FP32), FP64 or
+ * mixed precision (the forward as ctfiss_iterate runs it, the adjoint kernels
+ * in FP32; not the bfloat16 NMF path), under either activation rule (the
+ * context's), with Mbar <= 32 only (else CTFISS_E_UNSUPPORTED).  aws: device workspace of
  * ctfiss_adjoint_workspace_size() bytes (256-byte aligned), scratch for the
  * call.  The context ends in the forward's final state, as after
  * ctfiss_iterate.  Enqueued on the context's stream without waiting (so that

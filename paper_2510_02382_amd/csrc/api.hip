@@ -1004,8 +1004,8 @@ AdjLayout adj_layout(const Dims& d, int n_iter, size_t rs) {
   return L;
 }
 
-// Reverse mode is built for FP32 and FP64 ISS contexts (either activation
-// rule), Mbar <= 32 and LDS for the per-bin adjoint kernels.
+// Reverse mode is built for FP32, FP64 and mixed ISS contexts (either
+// activation rule), Mbar <= 32 and LDS for the per-bin adjoint kernels.
 bool adj_supported(const Dims& d, int rs) {
   return d.Mb <= 32 && adj_iss_lds(d.Mb, d.T, rs) <= kMaxLdsBytes && adj_images_lds(d.Mb, d.M, rs) <= kMaxLdsBytes;
 }
@@ -1016,11 +1016,11 @@ extern "C" {
 
 int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int precision, int32_t n_iter, size_t* bytes) {
   if (!bytes || n_iter < 1) return CTFISS_E_ARG;
-  if (precision != CTFISS_FP32 && precision != CTFISS_FP64) return CTFISS_E_UNSUPPORTED;
+  if (precision != CTFISS_FP32 && precision != CTFISS_FP64 && precision != CTFISS_MIXED) return CTFISS_E_UNSUPPORTED;
   Dims d;
   const int st = validate_shape(shape, precision, &d);
   if (st != CTFISS_OK) return st;
-  const int rs = precision == CTFISS_FP32 ? 4 : 8;
+  const int rs = precision == CTFISS_FP64 ? 8 : 4;
   if (!adj_supported(d, rs)) return CTFISS_E_UNSUPPORTED;
   *bytes = adj_layout(d, n_iter, rs).total;
   return CTFISS_OK;
@@ -1029,9 +1029,9 @@ int ctfiss_adjoint_workspace_size(const ctfiss_shape* shape, int precision, int3
 int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V0, const void* gC, void* gX,
                     void* gB0, void* gV0, void* aws, size_t aws_bytes) {
   if (!c || !B0 || !V0 || !gC || !gX || !aws || n_iter < 1) return CTFISS_E_ARG;
-  if (wx(c->prec) || c->rule != CTFISS_RULE_ISS) return CTFISS_E_UNSUPPORTED;
+  if (c->prec == CTFISS_MIXED_BF16 || c->rule != CTFISS_RULE_ISS) return CTFISS_E_UNSUPPORTED;
   const Dims& d = c->d;
-  const bool f32 = c->prec == CTFISS_FP32;
+  const bool f32 = c->prec != CTFISS_FP64;  // FP32, or mixed: FP32 data and adjoint kernels
   const bool tap0 = c->vrule == CTFISS_VRULE_PAPER_TAP0;
   const int rs = f32 ? 4 : 8;
   if (!adj_supported(d, rs)) return CTFISS_E_UNSUPPORTED;
@@ -1106,7 +1106,9 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
     c->epoch = c->epoch % 0x1FFFFFFu + 1u;
     if (f32) {
       if (e == hipSuccess) e = lambda_t<float>(d, c->ptr, false, s);
-      if (e == hipSuccess) e = wupdate_t<float>(c->rule, sep, d, c->ptr, false, false, c->epoch, c->floor, s);
+      if (e == hipSuccess)
+        e = wx(c->prec) ? wupdate_t<float, true>(c->rule, sep, d, c->ptr, false, false, c->epoch, c->floor, s)
+                        : wupdate_t<float>(c->rule, sep, d, c->ptr, false, false, c->epoch, c->floor, s);
       if (e == hipSuccess) e = nmfb_t<float>(d, c->ptr, c->floor, false, s);
       if (e == hipSuccess && c->vone) e = vupdate_t<float>(d, c->ptr, c->floor, tap0, s);
       if (e == hipSuccess && !c->vone) e = vpart_t<float>(d, c->vs, c->ptr, tap0, s);

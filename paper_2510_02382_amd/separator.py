@@ -128,9 +128,9 @@ class Separator:
 
     def backward(self, n_iter: int, B0: torch.Tensor, V0: torch.Tensor, gC: torch.Tensor):
         """Gradients (gX, gB0, gV0) of a real loss through W = I, (B0, V0), n_iter
-        iterations and the source images, given gC = dL/dC (ctfiss_backward; FP32 or
-        FP64, ISS, all-taps rule).  The input bound by set_input is X.  Enqueued without
-        waiting: a numeric fault stays latched for status() / check()."""
+        iterations and the source images, given gC = dL/dC (ctfiss_backward; FP32, FP64 or
+        mixed, ISS, either activation rule).  The input bound by set_input is X.  Enqueued
+        without waiting: a numeric fault stays latched for status() / check()."""
         self._check(B0, (self.N, self.F, self.K), self.rdtype, "B0")
         self._check(V0, (self.N, self.K, self.T), self.rdtype, "V0")
         self._check(gC, (self.N, self.M, self.F, self.T), self.cdtype, "gC")
