@@ -216,7 +216,9 @@ int ctfiss_nll(ctfiss_ctx* ctx, double* out);
  * ISS contexts in FP32 (complex64, the kernels' arithmetic in FP32), FP64 or
  * mixed precision (the forward as ctfiss_iterate runs it, the adjoint kernels
  * in FP32; not the bfloat16 NMF path), under either activation rule (the
- * context's), with Mbar <= 32 only (else CTFISS_E_UNSUPPORTED).  aws: device workspace of
+ * context's) and any plan, team launches included; every Mbar in FP32 and
+ * mixed precision, Mbar <= 56 in FP64 (the per-bin images adjoint must fit
+ * LDS), else CTFISS_E_UNSUPPORTED.  aws: device workspace of
  * ctfiss_adjoint_workspace_size() bytes (256-byte aligned), scratch for the
  * call.  The context ends in the forward's final state, as after
  * ctfiss_iterate.  Enqueued on the context's stream without waiting (so that

@@ -1005,9 +1005,12 @@ AdjLayout adj_layout(const Dims& d, int n_iter, size_t rs) {
 }
 
 // Reverse mode is built for FP32, FP64 and mixed ISS contexts (either
-// activation rule), Mbar <= 32 and LDS for the per-bin adjoint kernels.
+// activation rule) whose per-bin adjoint kernels fit LDS: every Mbar in FP32
+// and mixed precision, Mbar <= 56 in FP64 (the images adjoint holds W, its
+// augmented inverse and the image gradients of a bin, 3 Mbar^2 + 2 M Mbar + Mbar
+// complex values).
 bool adj_supported(const Dims& d, int rs) {
-  return d.Mb <= 32 && adj_iss_lds(d.Mb, d.T, rs) <= kMaxLdsBytes && adj_images_lds(d.Mb, d.M, rs) <= kMaxLdsBytes;
+  return adj_iss_lds(d.Mb, d.T, rs) <= kMaxLdsBytes && adj_images_lds(d.Mb, d.M, rs) <= kMaxLdsBytes;
 }
 
 }  // namespace

@@ -135,6 +135,62 @@ def test_mixed_gradients_match_fp64_reference(case, vrule):
         assert rel(g, r) < max(3e-4, 2 * rel(g32, r)), (name, rel(g, r), rel(g32, r))
 
 
+# Wide demixing matrices: Mbar = 48 (FP64's limit is 56: its images adjoint holds W, the augmented
+# inverse and the image gradients of a bin in LDS) and Mbar = 64 (FP32 and mixed), through the
+# context's own plan and through a forced team plan (the forward replayed by frame-split launches).
+WIDE = {
+    "rows48": (2, 100, 3, 16, (16, 16, 16), 3, 2),
+    "rows64": (2, 100, 4, 16, (22, 21, 21), 3, 2),
+}
+
+
+def wide_problem(name, seed=0):
+    F, T, M, D, taps, K, n = WIDE[name]
+    X, B0, V0 = random_problem(F, T, M, len(taps), K, seed, scale_spread=0.5)
+    rng = rng_for(seed + 7)
+    target = 0.3 * (rng.standard_normal((len(taps), M, F, T)) + 1j * rng.standard_normal((len(taps), M, F, T)))
+    return X, B0, V0, target, D, taps, n
+
+
+@pytest.mark.parametrize("plan", [None, "16,4,1,3"])
+def test_wide_rows_fp64_gradients_match_autograd_reference(plan, monkeypatch):
+    if plan:
+        monkeypatch.setenv("CTFISS_PLAN", plan)
+    else:
+        monkeypatch.delenv("CTFISS_PLAN", raising=False)
+    args = wide_problem("rows48")
+    g, ref = gpu(*args), reference(*args)
+    for name, a, r in zip(("C", "gX", "gB0", "gV0"), g, ref):
+        assert rel(a, r) < 1e-8, (name, rel(a, r))
+
+
+@pytest.mark.parametrize("precision,plan", [("fp32", None), ("mixed", None), ("fp32", "16,8,1,4")])
+def test_wide_rows_fp32_gradients_match_fp64_reference(precision, plan, monkeypatch):
+    if plan:
+        monkeypatch.setenv("CTFISS_PLAN", plan)
+    else:
+        monkeypatch.delenv("CTFISS_PLAN", raising=False)
+    args = wide_problem("rows64")
+    g, ref = gpu(*args, precision=precision), reference(*args)
+    for name, a, r in zip(("C", "gX", "gB0", "gV0"), g, ref):
+        assert rel(a, r) < 3e-4, (name, rel(a, r))
+
+
+def test_fp64_reverse_beyond_its_lds_is_rejected():
+    from paper_2510_02382_amd import Separator
+    from paper_2510_02382_amd import binding as b
+    X, B0, V0, target, D, taps, n = wide_problem("rows64")
+    M, F, T = X.shape
+    N, _, K = B0.shape
+    sep = Separator(F, T, M, D, N, K, taps, precision="fp64")
+    sep.set_input(torch.from_numpy(X).cuda())
+    gC = torch.zeros((N, M, F, T), dtype=torch.complex128, device="cuda")
+    with pytest.raises(b.CtfissError) as e:
+        sep.backward(n, torch.from_numpy(B0).cuda(), torch.from_numpy(V0).cuda(), gC)
+    assert e.value.status == b.CTFISS_E_UNSUPPORTED
+    sep.close()
+
+
 def test_tap0_rule_changes_the_gradients():
     """The two rules' gradients differ where a source has several taps, so the tap-0 checks
     above are not passed by the all-taps reverse pass."""
