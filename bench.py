@@ -284,6 +284,7 @@ def batched_bench(args) -> int:
                                "STFT 1024/256, K = 10, 50 iterations", "mixtures": len(wls),
                    "sum_FT": sum(w.F * w.T for w in wls), "iterations": n_iter},
         "eager_ms_per_step": dt_eager * 1e3, "graph_equals_eager": graph_equals_eager,
+        "hw_queues": args.hw_queues,
         "side_by_side": {
             "single_fp32_iss": {"value": u32 / dt32, "ms": dt32 * 1e3, "status": st32},
             "single_fp64_iss": {"value": u64 / dt64, "ms": dt64 * 1e3, "mixtures": len(C64), "status": st64},
@@ -571,7 +572,7 @@ def adjoint_bench(args) -> int:
                                f"w.r.t. the mixture STFT and the initial bases",
                    "F": wl.F, "T": wl.T, "Mbar": wl.mbar, "K": wl.K, "iterations": wl.n_iter, "mixtures": nmix},
         "fp64_ms_per_step": dt64 * 1e3, "fp64_forward_ms_per_step": dt_fwd * 1e3, "streams": len(streams),
-        "gradient_check": check, "cpu_baseline": cpu,
+        "hw_queues": args.hw_queues, "gradient_check": check, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -650,6 +651,9 @@ def main() -> int:
     ap.add_argument("--autotune", action="store_true",
                     help="--batched: also time the batch after tuning the launch shape of every distinct shape")
     ap.add_argument("--streams", type=int, default=8, help="c4: streams the mixtures are spread over")
+    ap.add_argument("--hw-queues", type=int, default=None,
+                    help="hardware queues the HIP runtime opens for this process (GPU_MAX_HW_QUEUES, at most "
+                         "32); default 16 for c4 (mixtures spread over several streams), else the runtime's own")
     ap.add_argument("--workload", choices=["c1", "c3", "c4", "P4", "P6", "P8"], default="c1",
                     help="c3: the 60 s, Mbar = 64 mixture (team launches) instead of the 10 s, Mbar = 24 one; "
                          "c4: forward and reverse pass of 32 mixtures (gradients); P4/P6/P8: the paper's "
@@ -665,6 +669,15 @@ def main() -> int:
         print("bench.py: this build runs one mixture on one GPU; --gpus must be 1 "
               "(the bin-sharded multi-GPU path is a design, not built)", file=sys.stderr)
         return 2
+
+    # streams beyond the runtime's hardware queues (4 by default) share queues and so run
+    # their kernels one after another; set before the runtime starts.  The differentiation
+    # workload's 8 streams gain from 16 queues (277 -> 255 ms per step); the batch's graph
+    # replay does not (934 -> 960 ms), so it keeps the runtime's own count
+    q = args.hw_queues if args.hw_queues is not None else (16 if args.workload == "c4" and not args.batched else 0)
+    if q > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(q, 32))
+    args.hw_queues = os.environ.get("GPU_MAX_HW_QUEUES")
 
     import torch
 
