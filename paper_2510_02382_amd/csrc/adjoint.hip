@@ -249,26 +249,34 @@ __global__ void __launch_bounds__(256) k_adj_images(AdjArgs<R> a, const Cx<R>* _
   }
   // H[i][j] = aug[i][Mb + j]
   auto H = [&](int i, int j) { return aug[i * 2 * Mb + Mb + j]; };
-  auto yv = [&](int r, int t) {
-    Cx<R> s{R(0.0), R(0.0)};
-    for (int c = 0; c < Mb; ++c) s = cfma(Wl[r * Mb + c], xbar(a, f, c, t), s);
-    return s;
-  };
   auto gc = [&](int r, int m, int t) { return gC[(((size_t)a.rm.src[r] * M + m) * F + f) * T + t]; };
-  // gH[m][r] = sum_t gC[n(r)][m][t] conj(y_r[t])
-  for (int e = tid; e < M * Mb; e += nt) {
-    const int m = e / Mb, r = e - m * Mb;
-    Cx<R> s{R(0.0), R(0.0)};
-    for (int t = 0; t < T; ++t) s = cfma(gc(r, m, t), cconj(yv(r, t)), s);
-    gH[e] = s;
-  }
-  // gY[r][t] = sum_m conj(H[m][r]) gC[n(r)][m][t]  (into the sweep scratch)
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  // y_r[t] = sum_c W[r][c] xbar_c[t], once per bin, into the sweep scratch (unused at this stage),
+  // and gY[r][t] = sum_m conj(H[m][r]) gC[n(r)][m][t]
+  Cx<R>* Yb = a.Y + (size_t)f * Mb * T;
   Cx<R>* gY = a.gY + (size_t)f * Mb * T;
   for (int e = tid; e < Mb * T; e += nt) {
     const int r = e / T, t = e - r * T;
     Cx<R> s{R(0.0), R(0.0)};
-    for (int m = 0; m < M; ++m) s = cfma(cconj(H(m, r)), gc(r, m, t), s);
-    gY[e] = s;
+    for (int c = 0; c < Mb; ++c) s = cfma(Wl[r * Mb + c], xbar(a, f, c, t), s);
+    Yb[e] = s;
+    Cx<R> g{R(0.0), R(0.0)};
+    for (int m = 0; m < M; ++m) g = cfma(cconj(H(m, r)), gc(r, m, t), g);
+    gY[e] = g;
+  }
+  __syncthreads();
+  // gH[m][r] = sum_t gC[n(r)][m][t] conj(y_r[t]): one wave per entry, lanes over the frames
+  for (int e = wave; e < M * Mb; e += nw) {
+    const int m = e / Mb, r = e - m * Mb;
+    R sx = R(0.0), sy = R(0.0);
+    for (int t = lane; t < T; t += 64) {
+      const Cx<R> q = cmulc(gc(r, m, t), Yb[r * T + t]);
+      sx += q.x;
+      sy += q.y;
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if (lane == 0) gH[e] = Cx<R>{sx, sy};
   }
   __syncthreads();
   // A = gH H^H: A[m][c] = sum_r gH[m][r] conj(H[c][r])
@@ -279,13 +287,22 @@ __global__ void __launch_bounds__(256) k_adj_images(AdjArgs<R> a, const Cx<R>* _
     A[e] = s;
   }
   __syncthreads();
-  // gW[r][c] = -sum_m conj(H[m][r]) A[m][c] + sum_t gY[r][t] conj(xbar_c[t])
-  for (int e = tid; e < Mb * Mb; e += nt) {
+  // gW[r][c] = sum_t gY[r][t] conj(xbar_c[t]) - sum_m conj(H[m][r]) A[m][c]: one wave per entry
+  for (int e = wave; e < Mb * Mb; e += nw) {
     const int r = e / Mb, c = e - r * Mb;
-    Cx<R> s{R(0.0), R(0.0)};
-    for (int m = 0; m < M; ++m) s = cfms(cconj(H(m, r)), A[m * Mb + c], s);
-    for (int t = 0; t < T; ++t) s = cfma(gY[r * T + t], cconj(xbar(a, f, c, t)), s);
-    a.gW[(size_t)f * Mb * Mb + e] = s;
+    R sx = R(0.0), sy = R(0.0);
+    for (int t = lane; t < T; t += 64) {
+      const Cx<R> q = cmulc(gY[r * T + t], xbar(a, f, c, t));
+      sx += q.x;
+      sy += q.y;
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if (lane == 0) {
+      Cx<R> s{sx, sy};
+      for (int m = 0; m < M; ++m) s = cfms(cconj(H(m, r)), A[m * Mb + c], s);
+      a.gW[(size_t)f * Mb * Mb + e] = s;
+    }
   }
   // gX[m][f][t] = sum_d sum_r conj(W[r][d M + m]) gY[r][t + d]
   for (int e = tid; e < M * T; e += nt) {
