@@ -948,6 +948,55 @@ __global__ void __launch_bounds__(256) k_adj_demix_x(AdjArgs<R> a) {
   a.gX[i] = cadd(a.gX[i], s);
 }
 
+// Both demix adjoints of one bin per workgroup, from LDS: the bin's gY rows, its observation
+// rows (xs[m][D - 1 + t] = x[m][f][t], zero before frame 0, so xbar_c[t] = xs[m][D - 1 + t - d]
+// for c = d M + m) and Wk are loaded once; gW[r][c] += sum_t gY[r][t] conj(xbar_c[t]) with a
+// wave per entry (lanes over frames, as k_adj_demix_w) and gX[m][f][t] += sum_d sum_r
+// conj(Wk[r][d M + m]) gY[r][t + d] with a thread per output (as k_adj_demix_x): the same sums in
+// the same order as those two kernels, which read every gY value 12 times (M D) from memory and
+// take the shapes whose rows do not fit LDS.
+template <typename R>
+__global__ void __launch_bounds__(1024) k_adj_demix(AdjArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int f = blockIdx.x, tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  const int Mb = a.Mb, T = a.T, F = a.F, M = a.M, D = a.D, LX = T + D - 1;
+  Cx<R>* gy = reinterpret_cast<Cx<R>*>(smem);  // [Mb][T]
+  Cx<R>* xs = gy + (size_t)Mb * T;              // [M][LX]
+  Cx<R>* w = xs + (size_t)M * LX;               // [Mb][Mb]
+  const Cx<R>* g = a.gY + (size_t)f * Mb * T;
+  for (int e = tid; e < Mb * T; e += nt) gy[e] = g[e];
+  for (int e = tid; e < M * LX; e += nt) {
+    const int m = e / LX, t = e - m * LX - (D - 1);
+    xs[e] = t >= 0 ? a.X[((size_t)m * F + f) * T + t] : Cx<R>{R(0.0), R(0.0)};
+  }
+  for (int e = tid; e < Mb * Mb; e += nt) w[e] = a.Wk[(size_t)f * Mb * Mb + e];
+  __syncthreads();
+  for (int e = wave; e < Mb * Mb; e += nw) {
+    const int r = e / Mb, c = e - r * Mb, d = c / M, m = c - d * M;
+    const Cx<R>* xr = xs + m * LX + (D - 1 - d);
+    R sx = R(0.0), sy = R(0.0);
+    for (int t = lane; t < T; t += 64) {
+      const Cx<R> q = cmulc(gy[r * T + t], xr[t]);
+      sx += q.x;
+      sy += q.y;
+    }
+    sx = group_sum<64>(sx);
+    sy = group_sum<64>(sy);
+    if (lane == 0) {
+      const size_t o = (size_t)f * Mb * Mb + e;
+      a.gW[o] = cadd(a.gW[o], Cx<R>{sx, sy});
+    }
+  }
+  for (int e = tid; e < M * T; e += nt) {
+    const int m = e / T, t = e - m * T;
+    Cx<R> acc{R(0.0), R(0.0)};
+    for (int d = 0; d < D && t + d < T; ++d)
+      for (int r = 0; r < Mb; ++r) acc = cfma(cconj(w[r * Mb + d * M + m]), gy[r * T + t + d], acc);
+    const size_t o = ((size_t)m * F + f) * T + t;
+    a.gX[o] = cadd(a.gX[o], acc);
+  }
+}
+
 // Per (n, f, s): glam[n][f][s] -= sum_l gphi_(n,l)[s + l] / lam^2 (phi = 1 / lambda).
 template <typename R>
 __global__ void __launch_bounds__(256) k_adj_phi(AdjArgs<R> a) {
@@ -1129,8 +1178,20 @@ hipError_t adj_iteration_t(const AdjPtrs& p, const Dims& d, double floor, hipStr
     if (MB == 4) hipLaunchKernelGGL((k_adj_iss_reg<R, 4>), dim3(d.F), dim3(nthr), lds, s, a);
     if (MB == 8) hipLaunchKernelGGL((k_adj_iss_reg<R, 8>), dim3(d.F), dim3(nthr), lds, s, a);
     if (MB == 12) hipLaunchKernelGGL((k_adj_iss_reg<R, 12>), dim3(d.F), dim3(nthr), lds, s, a);
-    hipLaunchKernelGGL(k_adj_demix_w<R>, blocks((size_t)d.F * d.Mb * d.Mb * 64), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_adj_demix_x<R>, blocks((size_t)d.M * d.F * d.T), dim3(256), 0, s, a);
+    const size_t dlds = ((size_t)d.Mb * d.T + (size_t)d.M * (d.T + d.D - 1) + (size_t)d.Mb * d.Mb) * 2 * rs;
+    if (dlds <= kMaxLdsBytes) {
+      if (dlds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_adj_demix<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)dlds);
+        if (e != hipSuccess) return e;
+      }
+      // 8 waves per bin (three such workgroups share a CU at the differentiation workload's
+      // FP32 size), 16 in FP64 (one workgroup per CU there)
+      hipLaunchKernelGGL(k_adj_demix<R>, dim3(d.F), dim3(rs == 8 ? 1024 : 512), dlds, s, a);
+    } else {
+      hipLaunchKernelGGL(k_adj_demix_w<R>, blocks((size_t)d.F * d.Mb * d.Mb * 64), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_adj_demix_x<R>, blocks((size_t)d.M * d.F * d.T), dim3(256), 0, s, a);
+    }
     hipLaunchKernelGGL(k_adj_phi<R>, blocks(nft), dim3(256), 0, s, a);
   } else {
     const size_t lds = adj_iss_lds(d.Mb, d.T, rs);
