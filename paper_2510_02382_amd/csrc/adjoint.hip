@@ -1035,17 +1035,21 @@ __global__ void __launch_bounds__(256) k_adj_l1(AdjArgs<R> a) {
 }
 
 // gV[n][k][s] += sum_f (B^ glamh + H1 P / lam^2 + H2 c / lam + Bk glam).  One workgroup
-// of 16 waves per (source n, 64 frames, 8 bases): lane l takes frame 64 x + l (the
-// (n, f, s) arrays are read along s, contiguously, once for all 8 bases), wave w the bins
-// f = w, w + 16, ... (the (n, f, k) factors are the same for the whole wave); the waves'
-// partial sums are added in wave order through LDS.
+// of 16 waves per (source n, 64 frames, 8 bases, chunk of bins): lane l takes frame 64 x + l
+// (the (n, f, s) arrays are read along s, contiguously, once for all 8 bases), wave w the
+// chunk's bins f = f0 + w, f0 + w + 16, ... (the (n, f, k) factors are the same for the whole
+// wave); the waves' partial sums are added in wave order through LDS.  With one chunk the sum
+// goes to gV; with several, each chunk's sum goes to chunk_sums[chunk][n][k][s] and
+// k_adj_l2_sum adds them to gV in chunk order (the chunks spread the bins of a few (source,
+// frames, bases) tiles over many workgroups).
 constexpr int kL2Waves = 16, kL2Bases = 8;
 template <typename R>
-__global__ void __launch_bounds__(64 * kL2Waves) k_adj_l2(AdjArgs<R> a) {
+__global__ void __launch_bounds__(64 * kL2Waves) k_adj_l2(AdjArgs<R> a, R* chunk_sums, int fchunk) {
   __shared__ R part[kL2Waves][kL2Bases][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ntile = (a.T + 63) / 64, nkc = (a.K + kL2Bases - 1) / kL2Bases;
   const int tile = blockIdx.x % ntile, kc = (blockIdx.x / ntile) % nkc, n = blockIdx.x / (ntile * nkc);
+  const int ch = blockIdx.y, f0 = ch * fchunk, f1 = min(a.F, f0 + fchunk);
   const int s = tile * 64 + lane, k0 = kc * kL2Bases;
   const bool ok = s < a.T;
   const R c = ok ? tapc<R>(a.rm, n, s, a.T) : R(0.0);
@@ -1053,7 +1057,7 @@ __global__ void __launch_bounds__(64 * kL2Waves) k_adj_l2(AdjArgs<R> a) {
 #pragma unroll
   for (int kk = 0; kk < kL2Bases; ++kk) acc[kk] = R(0.0);
   if (ok) {
-    for (int f = wave; f < a.F; f += kL2Waves) {
+    for (int f = f0 + wave; f < f1; f += kL2Waves) {
       const size_t fs = ((size_t)n * a.F + f) * a.T + s, fk = ((size_t)n * a.F + f) * a.K + k0;
       const R il = a.ilam[fs], e1 = a.glamh[fs], e2 = a.P[fs] * il * il, e3 = c * il, e4 = a.glam[fs];
 #pragma unroll
@@ -1069,11 +1073,31 @@ __global__ void __launch_bounds__(64 * kL2Waves) k_adj_l2(AdjArgs<R> a) {
   if (wave < kL2Bases && ok && k0 + wave < a.K) {  // wave kk adds basis kk's partials
     R sum = R(0.0);
     for (int w = 0; w < kL2Waves; ++w) sum += part[w][wave][lane];
-    a.gV[((size_t)n * a.K + k0 + wave) * a.T + s] += sum;
+    const size_t o = ((size_t)n * a.K + k0 + wave) * a.T + s;
+    if (chunk_sums)
+      chunk_sums[(size_t)ch * a.N * a.K * a.T + o] = sum;
+    else
+      a.gV[o] += sum;
   }
 }
 
+// gV[n][k][s] += the chunk sums of k_adj_l2 in chunk order.
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_l2_sum(AdjArgs<R> a, const R* chunk_sums, int nch) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x, n = (size_t)a.N * a.K * a.T;
+  if (i >= n) return;
+  R sum = R(0.0);
+  for (int c = 0; c < nch; ++c) sum += chunk_sums[(size_t)c * n + i];
+  a.gV[i] += sum;
+}
+
 }  // namespace
+
+// Chunks of bins of the activation adjoint's sums: 64 bins or more each, at most kAdjL2Chunks.
+int adj_l2_chunks(int F) {
+  const int c = (F + 63) / 64;
+  return c < 1 ? 1 : (c > kAdjL2Chunks ? kAdjL2Chunks : c);
+}
 
 // LDS of the per-bin adjoint kernels for real size rs (complex 2 rs).
 size_t adj_images_lds(int Mb, int M, int rs) { return (size_t)(3 * Mb * Mb + 2 * M * Mb + Mb) * 2 * rs + 64; }
@@ -1202,8 +1226,11 @@ hipError_t adj_iteration_t(const AdjPtrs& p, const Dims& d, double floor, hipStr
     hipLaunchKernelGGL(k_adj_iss<R>, dim3(d.F), dim3(256), lds, s, a);
   }
   hipLaunchKernelGGL(k_adj_l1<R>, blocks(nfk * 64), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_adj_l2<R>, dim3((unsigned)(d.N * ((d.K + kL2Bases - 1) / kL2Bases) * ((d.T + 63) / 64))),
-                     dim3(64 * kL2Waves), 0, s, a);
+  const int l2ch = adj_l2_chunks(d.F), l2fc = (d.F + l2ch - 1) / l2ch;
+  R* l2sums = l2ch > 1 ? static_cast<R*>(p.l2sums) : nullptr;
+  hipLaunchKernelGGL(k_adj_l2<R>, dim3((unsigned)(d.N * ((d.K + kL2Bases - 1) / kL2Bases) * ((d.T + 63) / 64)), l2ch),
+                     dim3(64 * kL2Waves), 0, s, a, l2sums, l2fc);
+  if (l2ch > 1) hipLaunchKernelGGL(k_adj_l2_sum<R>, blocks(nkt), dim3(256), 0, s, a, l2sums, l2ch);
   return hipGetLastError();
 }
 }  // namespace

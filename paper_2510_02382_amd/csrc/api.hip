@@ -960,7 +960,7 @@ namespace {
 
 struct AdjLayout {
   size_t ckW, ckB, ckV, gW, gB, gBh, gV, gVh, gP, gP0, glam, glamh, lamh, q1, q2, G1, G2, H1, H2, part, gS, Y, gY, gphi,
-      zt, dt, total;
+      zt, dt, l2sums, total;
 };
 
 AdjLayout adj_layout(const Dims& d, int n_iter, size_t rs) {
@@ -1000,6 +1000,7 @@ AdjLayout adj_layout(const Dims& d, int n_iter, size_t rs) {
   L.gphi = take(yt * rs);
   L.zt = take(w);
   L.dt = take((size_t)d.F * d.Mb * d.Mb * rs);
+  L.l2sums = take((size_t)adj_l2_chunks(d.F) * d.N * d.K * d.T * rs);
   L.total = off;
   return L;
 }
@@ -1090,6 +1091,7 @@ int ctfiss_backward(ctfiss_ctx* c, int32_t n_iter, const void* B0, const void* V
   p.gphi = ws + L.gphi;
   p.ztape = ws + L.zt;
   p.dtape = ws + L.dt;
+  p.l2sums = ws + L.l2sums;
   // the iterations re-run below stop before the rescale and need lambda, the basis
   // update and the activation update from their own launches
   Plan sep = c->plan;

@@ -141,7 +141,10 @@ struct AdjPtrs {
   void* gphi;
   void* ztape;                       // [F][Mb][Mb]
   void* dtape;
+  void* l2sums;                      // [adj_l2_chunks(F)][N][K][T] chunk sums of the activation adjoint
 };
+constexpr int kAdjL2Chunks = 8;
+int adj_l2_chunks(int F);
 size_t adj_images_lds(int Mb, int M, int rs);
 size_t adj_iss_lds(int Mb, int T, int rs);
 hipError_t adj_images(const AdjPtrs& p, const Dims& d, const void* W, const void* gC, int rs, hipStream_t s);

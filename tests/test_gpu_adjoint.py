@@ -43,9 +43,11 @@ CASES = {
     # beyond the register-column sweep adjoint (Mbar <= 12, T <= 512): the per-bin scratch forms
     "rows16_lds": (2, 40, 4, 4, (8, 8), 2, 2),         # Mbar = 16, adjoints in LDS
     "long_T_global": (2, 600, 2, 2, (2, 2), 2, 2),     # T = 600, adjoints in global scratch
+    # 130 bins: the activation adjoint's sums over the bins split into 3 chunks
+    "many_bins": (130, 40, 2, 2, (2, 2), 3, 2),
 }
 TOL = {"small": 1e-8, "uneven_taps": 1e-8, "three_sources": 1e-8, "c4_slice": 1e-6, "rows16_lds": 1e-8,
-       "long_T_global": 1e-8}
+       "long_T_global": 1e-8, "many_bins": 1e-8}
 
 
 def rel(a, b):
