@@ -179,6 +179,19 @@ bool choose_plan(int prec, int rule, const Dims& d, size_t max_lds, Plan* out) {
       return true;
     }
   }
+  // Mbar <= 8 in FP64 (ISS and IP) and FP32 IP: the bin's latency is again the frame
+  // loop of each step, so the wider groups that fit win (measured at Mbar = 4, 6, 8,
+  // T = 501, W update per launch: FP64 ISS 64-lane 20.7 / 26.8 / 54.4 us against
+  // 73.3 / 102.5 / 175.7 us for 32-lane groups; FP64 IP 64-lane 76 / 154 / 181 us against
+  // 85 / 169 / 198; FP32 IP 32-lane 91 / 104 / 127 us against 124 / 134 / 174 us for
+  // 16-lane groups and 85 / 172 / 198 us for 64-lane ones).
+  if (d.Mb <= 8 && !(rule == 0 && f32)) {
+    Plan p;
+    if (plan_for(prec, rule, d, max_lds, f32 ? 32 : 64, 1, 0, &p)) {
+      *out = p;
+      return true;
+    }
+  }
   for (int i = 0; i < n; ++i)
     if (plan_for(prec, rule, d, max_lds, list[i].G, list[i].RPL, 0, out)) return true;
   // ISS bins too long for one workgroup: teams of workgroups
