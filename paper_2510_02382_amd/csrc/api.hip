@@ -548,7 +548,10 @@ int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int
   if (rule == CTFISS_RULE_ISS && plan.team <= 1 && !unfused && precision != CTFISS_MIXED_BF16) {
     const int need = plan.blocks < d.F ? plan.blocks : d.F;
     const bool dev_v = std::getenv("CTFISS_NMF_FROM_DEVICE") != nullptr;
-    const int last = (dev_v || precision != CTFISS_FP64) ? 2 : 1;
+    // FP64 reads the activations from device memory only at Mbar <= 8, where each bin is its
+    // workgroup's only one (P4: 33.5 us per iteration against 41.2 us for the W update, lambda
+    // and basis-update launches; at c1 the separate launches win, 27.5 against 30.9 ms)
+    const int last = (dev_v || precision != CTFISS_FP64 || d.Mb <= 8) ? 2 : 1;
     for (int kind = dev_v ? 2 : 1; kind <= last; ++kind) {
       Plan q = plan;
       q.nmf = kind;
