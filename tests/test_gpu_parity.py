@@ -530,3 +530,27 @@ def test_separate_nmf_launches_match_oracle_and_fused_path(case, vrule, precisio
     check_outputs(None, fused, r, 10 * TOL1[tol], 10 * ELEM1[tol])
     check_outputs(None, fused_dev, r, 10 * TOL1[tol], 10 * ELEM1[tol])
     check_outputs(None, fused, plain, 10 * TOL1[tol], 10 * ELEM1[tol])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "mixed"])
+@pytest.mark.parametrize("rule", ["iss", "ip"])
+@pytest.mark.parametrize("D,taps", [(1, (1,) * 8), (2, (3, 2, 2, 2, 2, 2, 2, 1))])
+def test_most_sources_match_oracle(D, taps, rule, precision):
+    """N = 8 sources, the most the boundary takes (CTFISS_MAX_SOURCES), with one tap each
+    (the determined M = N = 8 case, Mbar = 8) and with uneven taps over two stacked frames
+    (Mbar = 16): three iterations over two calls against the oracle, per output and per
+    element.  The mixed path is an ISS path only."""
+    if precision == "mixed" and rule == "ip":
+        return
+    F, T, M, K = 5, 120, 8, 3
+    X, B0, V0 = random_problem(F, T, M, len(taps), K, 71, scale_spread=0.5)
+    rng = rng_for(72)
+    Mb = M * D
+    W0 = np.eye(Mb) + 0.2 * (rng.standard_normal((F, Mb, Mb)) + 1j * rng.standard_normal((F, Mb, Mb)))
+    g = gpu_run(X, D, taps, B0, V0, W0, 3, precision, rule, splits=[2, 1])
+    tol = "fp64" if precision == "fp64" else "fp32"
+    r = oracle_run(X, D, taps, B0, V0, W0, 3, tol, rule)
+    assert g["status"] == 0
+    tn, te = (10 * TOL1_IP32[0], 10 * TOL1_IP32[1]) if (rule, tol) == ("ip", "fp32") else \
+        (10 * TOL1[tol], 10 * ELEM1[tol])
+    check_outputs(f"most_sources[D{D}-{rule}-{precision}]", g, r, tn, te)
