@@ -581,6 +581,103 @@ def adjoint_bench(args) -> int:
     return 0
 
 
+def c0_bench(args) -> int:
+    """The small FP64 workload: 4 s, N = 2, M = 3, STFT 1024/256 (F = 513, T = 251), K = 10, 30
+    iterations, with D = 4 stacked frames (Mbar = 12, taps 6 + 6) and, alongside, D = 1 (Mbar = 3,
+    taps 2 + 1).  FP64 ISS with graph replay is `value` (an iteration is tens of microseconds, so
+    launches matter); FP64 ISS eager, FP64 IP and FP32 ISS are timed alike beside it, every path's
+    images are compared with the FP64 oracle of its rule, and the oracle is timed on all host threads
+    (bin chunks) and on one thread."""
+    import torch
+    from threadpoolctl import threadpool_limits
+
+    from datagen import WORKLOADS, init_nmf, make_mixture
+    from oracle import ctf_iss as o
+    from paper_2510_02382_amd import Separator
+
+    dev = torch.device("cuda:0")
+    lines = {}
+    for name in ("c0", "c0_d1"):
+        wl = WORKLOADS[name]
+        log(f"workload {wl.name}: F={wl.F} T={wl.T} M={wl.M} Mbar={wl.mbar} taps={wl.row_taps} K={wl.K} "
+            f"iters={wl.n_iter}")
+        mix = make_mixture(wl, 0)
+        B0n, V0n = init_nmf(wl.N, wl.F, wl.K, wl.T, 0)
+        Xc = torch.from_numpy(mix.X).to(dev)
+        B0d, V0d = torch.from_numpy(B0n).to(dev), torch.from_numpy(V0n).to(dev)
+        units = wl.F * wl.T * wl.n_iter
+        stream = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(stream):
+            sep = Separator(wl.F, wl.T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision="fp64", stream=stream)
+            sep.set_graph(True)
+            sep.set_input(Xc)
+            for _ in range(args.warmup + 1):
+                sep.set_state(B=B0d, V=V0d)
+                sep.iterate(wl.n_iter)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                sep.set_state(B=B0d, V=V0d)
+                sep.iterate(wl.n_iter)
+                Cg = sep.source_images()
+            stream.synchronize()
+            dtg = (time.perf_counter() - t0) / args.steps
+            stg = sep.status()
+            sep.close()
+        log(f"FP64 ISS, graph replay: {dtg * 1e3:.3f} ms per separation, status {stg}")
+        side, images = {}, {"iss_fp64_graph": Cg}
+        for prec, rule in (("fp64", "iss"), ("fp64", "ip"), ("fp32", "iss")):
+            dt, Cp, st, _ = time_path(torch, Separator, wl, Xc, B0d, V0d, prec, rule, args.side_steps, 1)
+            key = f"{rule}_{prec}"
+            side[key] = {"value": units * args.side_steps / dt, "ms_per_step": dt / args.side_steps * 1e3,
+                         "status": st}
+            images[key] = Cp
+            log(f"{key}: {dt / args.side_steps * 1e3:.3f} ms per separation, status {st}")
+        side["speedup_iss_fp64_vs_ip_fp64"] = side["ip_fp64"]["ms_per_step"] / side["iss_fp64"]["ms_per_step"]
+        accuracy, cpu = None, None
+        if not args.no_cpu_baseline:
+            accuracy = {"reference": f"FP64 oracle, {wl.n_iter} iterations of the same rule on the original FP64 "
+                                     f"data", "target_fp64": 1e-9, "target_fp32": 1e-4, "per_source_rel_err": {}}
+            for rule in ("iss", "ip"):
+                Cref, dto, workers = oracle_reference(wl, mix.X, B0n, V0n, rule)
+                log(f"  oracle {rule.upper()}: {dto:.1f} s on {workers} threads")
+                for key, Cp in images.items():
+                    if key.startswith(rule):
+                        accuracy["per_source_rel_err"][key] = per_source_err(Cp.cpu().numpy(), Cref)
+                if rule == "iss":
+                    with threadpool_limits(limits=1):
+                        t0 = time.perf_counter()
+                        o.run(mix.X, wl.D, wl.row_taps, B0n, V0n, wl.n_iter, rule=o.ISS)
+                        dt1 = time.perf_counter() - t0
+                    log(f"  oracle ISS, one thread: {dt1:.1f} s")
+                    cpu = {"value": units / dto, "unit": "F·T·iters/s", "cores": workers, "kind": "oracle",
+                           "sample": f"all {wl.n_iter} ISS iterations of the mixture (F={wl.F}, T={wl.T}, "
+                                     f"Mbar={wl.mbar}) in FP64 NumPy, the W update of bin chunks on {workers} "
+                                     f"threads, BLAS on 1 thread each; {dto:.1f} s",
+                           "one_thread_value": units / dt1, "one_thread_s": dt1,
+                           "cpu_model": cpu_info(), "os_cpu_count": os.cpu_count()}
+                else:
+                    cpu["ip_oracle_value"] = units / dto
+        lines[name] = {
+            "value": units / dtg, "ms_per_step": dtg * 1e3, "status": stg,
+            "config": {"workload": f"{name}: 4 s, N=2, M=3, RT60 0.6 s, STFT 1024/256, D={wl.D} stacked frames "
+                                   f"(Mbar={wl.mbar}, taps {'+'.join(map(str, wl.row_taps))}), K={wl.K}, "
+                                   f"{wl.n_iter} iterations, FP64, graph replay",
+                       "F": wl.F, "T": wl.T, "Mbar": wl.mbar, "K": wl.K, "iterations": wl.n_iter},
+            "side_by_side": side, "accuracy": accuracy, "cpu_baseline": cpu}
+    main_line = lines["c0"]
+    out = {
+        "metric": "F·T·iters/s ISS vs IP vs FP64-ISS at rel err ≤1e-4; HBM GB/s fraction",
+        "value": main_line["value"], "unit": "F·T·iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": main_line["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": main_line["config"], "status": main_line["status"], "side_by_side": main_line["side_by_side"],
+        "accuracy": main_line["accuracy"], "cpu_baseline": main_line["cpu_baseline"], "d1_variant": lines["c0_d1"],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def small_bench(args) -> int:
     """The paper's experimental shape (Sec. V-A, Table I): 8 s at 16 kHz, N=2, M = 4/6/8 microphones,
     no frame stacking (Mbar = M, L_n = M / 2), STFT 1024/256 (F=513, T=501), K=3, 100 iterations.  At
@@ -709,7 +806,7 @@ def main() -> int:
     ap.add_argument("--hw-queues", type=int, default=None,
                     help="hardware queues the HIP runtime opens for this process (GPU_MAX_HW_QUEUES, at most "
                          "32); default 16 for c4 (mixtures spread over several streams), else the runtime's own")
-    ap.add_argument("--workload", choices=["c1", "c3", "c4", "P4", "P6", "P8"], default="c1",
+    ap.add_argument("--workload", choices=["c0", "c1", "c3", "c4", "P4", "P6", "P8"], default="c1",
                     help="c3: the 60 s, Mbar = 64 mixture (team launches) instead of the 10 s, Mbar = 24 one; "
                          "c4: forward and reverse pass of 32 mixtures (gradients); P4/P6/P8: the paper's "
                          "shapes, eager and graph replay")
@@ -744,6 +841,8 @@ def main() -> int:
         return adjoint_bench(args)
     if args.workload in ("P4", "P6", "P8"):
         return small_bench(args)
+    if args.workload == "c0":
+        return c0_bench(args)
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
