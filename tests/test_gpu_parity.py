@@ -554,3 +554,18 @@ def test_most_sources_match_oracle(D, taps, rule, precision):
     tn, te = (10 * TOL1_IP32[0], 10 * TOL1_IP32[1]) if (rule, tol) == ("ip", "fp32") else \
         (10 * TOL1[tol], 10 * ELEM1[tol])
     check_outputs(f"most_sources[D{D}-{rule}-{precision}]", g, r, tn, te)
+
+
+@pytest.mark.parametrize("name", ["P4", "P6", "P8"])
+def test_launch_shapes_at_the_paper_shapes(name):
+    """The measured plan rule at Mbar <= 8 (no frame stacking, T = 501): 64-lane row groups of 8
+    frames per lane for ISS in both precisions and for FP64 IP, 32-lane groups of 16 frames for
+    FP32 IP (ctfiss_get_plan: G, frames per lane, rows per group, team)."""
+    from paper_2510_02382_amd import Separator
+    wl = WORKLOADS[name]
+    want = {("fp32", "iss"): (64, 8, 1, 1), ("fp64", "iss"): (64, 8, 1, 1),
+            ("fp64", "ip"): (64, 8, 1, 1), ("fp32", "ip"): (32, 16, 1, 1)}
+    for (precision, rule), plan in want.items():
+        sep = Separator(wl.F, wl.T, wl.M, wl.D, wl.N, wl.K, wl.row_taps, precision=precision, rule=rule)
+        assert sep.plan() == plan, (precision, rule, sep.plan())
+        sep.close()
