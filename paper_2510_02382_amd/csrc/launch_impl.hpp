@@ -106,9 +106,27 @@ bool have_tkernel(int G, int cpl, int rpl) {
   return pickt<R, WX>(G, cpl, rpl) != nullptr;
 }
 
+// FP64 ISS W update in 32-lane groups of 10 frames for at most 24 rows (768 threads): the
+// k_iss bin loop under a 768-thread launch bound, which lets the compiler keep the rows in up
+// to 168 VGPRs where the 1024-thread bound of k_iss (32 rows) caps them at 128 and spills
+// inside the ISS step loop.  Same arithmetic in the same order as k_iss.
+template <typename R, int G, int CPL>
+__global__ void __launch_bounds__(768) k_iss768(IterArgs<R> a, IterLds L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BinLds<R> s = carve<R>(smem, L);
+  for (int f = blockIdx.x; f < a.F; f += gridDim.x) {
+    if (f != (int)blockIdx.x) __syncthreads();  // the previous bin's LDS traffic is over
+    iss_bin<R, G, CPL, 1>(a, s, L, f);
+  }
+}
+
 template <typename R, bool WX>
 WFn<R> pick_plan(int rule, const Plan& p) {
   if (p.team > 1) return (rule == 0 && !p.nmf) ? pickt<R, WX>(p.G, p.CPL, p.RPL) : nullptr;
+  if constexpr (sizeof(R) == 8 && !WX) {
+    if (rule == 0 && !p.nmf && p.G == 32 && p.CPL == 10 && p.RPL == 1 && p.threads <= 768)
+      return &k_iss768<R, 32, 10>;
+  }
   return pick<R, WX>(rule, p.G, p.CPL, p.RPL, p.nmf != 0);
 }
 
