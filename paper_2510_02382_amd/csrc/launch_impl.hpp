@@ -106,10 +106,11 @@ bool have_tkernel(int G, int cpl, int rpl) {
   return pickt<R, WX>(G, cpl, rpl) != nullptr;
 }
 
-// FP64 ISS W update in 32-lane groups of 10 frames for at most 24 rows (768 threads): the
-// k_iss bin loop under a 768-thread launch bound, which lets the compiler keep the rows in up
-// to 168 VGPRs where the 1024-thread bound of k_iss (32 rows) caps them at 128 and spills
-// inside the ISS step loop.  Same arithmetic in the same order as k_iss.
+// FP64 ISS W update of 10-16 frames per lane in workgroups of at most 768 threads (e.g. 24
+// rows of 32 lanes): the k_iss bin loop under a 768-thread launch bound, which lets the
+// compiler keep the rows in up to 168 VGPRs where the 1024-thread bound of k_iss caps them
+// at 128 and spills inside the ISS step loop; three waves per SIMD still fit, as under the
+// 1024-thread bound.  Same arithmetic in the same order as k_iss.
 template <typename R, int G, int CPL>
 __global__ void __launch_bounds__(768) k_iss768(IterArgs<R> a, IterLds L) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -124,8 +125,12 @@ template <typename R, bool WX>
 WFn<R> pick_plan(int rule, const Plan& p) {
   if (p.team > 1) return (rule == 0 && !p.nmf) ? pickt<R, WX>(p.G, p.CPL, p.RPL) : nullptr;
   if constexpr (sizeof(R) == 8 && !WX) {
-    if (rule == 0 && !p.nmf && p.G == 32 && p.CPL == 10 && p.RPL == 1 && p.threads <= 768)
-      return &k_iss768<R, 32, 10>;
+    if (rule == 0 && !p.nmf && p.RPL == 1 && p.threads <= 768 && (p.G == 32 || p.G == 64)) {
+      const bool g32 = p.G == 32;
+      if (p.CPL == 10) return g32 ? &k_iss768<R, 32, 10> : &k_iss768<R, 64, 10>;
+      if (p.CPL == 12) return g32 ? &k_iss768<R, 32, 12> : &k_iss768<R, 64, 12>;
+      if (p.CPL == 16) return g32 ? &k_iss768<R, 32, 16> : &k_iss768<R, 64, 16>;
+    }
   }
   return pick<R, WX>(rule, p.G, p.CPL, p.RPL, p.nmf != 0);
 }
