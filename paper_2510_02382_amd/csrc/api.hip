@@ -549,8 +549,9 @@ int init_ctx(ctfiss_ctx* c, const Dims& d, const Layout& lay, int precision, int
     const int need = plan.blocks < d.F ? plan.blocks : d.F;
     const bool dev_v = std::getenv("CTFISS_NMF_FROM_DEVICE") != nullptr;
     // FP64 reads the activations from device memory only at Mbar <= 8, where each bin is its
-    // workgroup's only one (P4: 33.5 us per iteration against 41.2 us for the W update, lambda
-    // and basis-update launches; at c1 the separate launches win, 27.5 against 30.9 ms)
+    // workgroup's only one (Mbar = 4, T = 501, K = 3: 33.5 us per iteration against 41.2 us for
+    // the W update, lambda and basis-update launches; at Mbar = 24, T = 313, K = 20 the separate
+    // launches win, 27.5 against 30.9 ms per 100 iterations)
     const int last = (dev_v || precision != CTFISS_FP64 || d.Mb <= 8) ? 2 : 1;
     for (int kind = dev_v ? 2 : 1; kind <= last; ++kind) {
       Plan q = plan;
